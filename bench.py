@@ -1,0 +1,144 @@
+"""Benchmark of the exact two-layer GRNG -> RNG build on one MI355X.
+
+Workload: 100,000 points in 16-D, a Gaussian mixture of 32 isotropic clusters
+(centres uniform in [0,10]^16, sigma 0.5) on the 2^-19 grid, with 1,000 random
+pivots whose radius is the distance to their 100th nearest other point.  One
+step = build the GRNG of the pivot layer, then the exact RNG of all points
+(every kept/eliminated decision exact).  Inputs (points, pivot ids, radii) are
+resident in device memory before timing starts.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_HBM_GBS = 8000.0
+MI355X_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
+    return ap.parse_args()
+
+
+def cpu_baseline(W, rows_hint: int):
+    """The oracle (C, OpenMP) on a bounded sample: RNG rows of sampled points, scaled to all N rows."""
+    import numpy as np
+
+    from oracle import native
+    native.build(force=False)
+    threads = native.default_threads()
+    g = np.random.default_rng(7)
+    rows = rows_hint or 64
+    xs = g.choice(W.n, rows, replace=False)
+    t0 = time.perf_counter()
+    native.rng_rows(W.X, W.q, xs, threads=threads)
+    dt = time.perf_counter() - t0
+    if not rows_hint and dt < 5.0:   # grow to roughly 10-30 s of CPU work
+        rows = int(min(W.n, max(rows, rows * 12.0 / max(dt, 1e-3))))
+        xs = g.choice(W.n, rows, replace=False)
+        t0 = time.perf_counter()
+        native.rng_rows(W.X, W.q, xs, threads=threads)
+        dt = time.perf_counter() - t0
+    est = dt * W.n / rows
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "RNG rows of %d random points (each row scans all %d points), %.2f s measured, "
+                      "scaled by N/rows to the full build" % (rows, W.n, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2208_10022_amd as P
+
+    dev = torch.device("cuda:0")
+    W = synth.clustered(n=args.n)
+    L = W.layers[0]
+    X = torch.from_numpy(W.X).to(dev)
+    pid = torch.from_numpy(L.pivot_ids).to(dev)
+    rad = torch.from_numpy(L.radii).to(dev)
+    torch.cuda.synchronize()
+
+    def step(idx):
+        idx.build_grng_layer(0, pid, rad)
+        idx.build_rng()
+
+    idx = P.Index(X, grid_exp=W.q)
+    for _ in range(args.warmup):
+        step(idx)
+    torch.cuda.synchronize()
+    times, stats = [], []
+    stream = torch.cuda.current_stream()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step(idx)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+        stats.append(idx.stats())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms = float(np.median(times))
+    st = stats[-1]
+    edges = idx.num_edges()
+    idx.close()
+
+    line = {
+        "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
+        "value": ms / 1000.0,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), "
+                               "1,000 random pivots with 100-NN radii" % W.n,
+                   "n": W.n, "d": W.d, "pivots": int(len(L.pivot_ids)), "grid_exp": W.q},
+        "edges": edges,
+        "witness_tests": st["witness_tests"],
+        "witness_tests_per_s": st["witness_tests"] / (ms / 1000.0),
+        "distance_computations": st["distance_computations"],
+        "candidate_pairs": st["candidate_pairs"],
+        "stage4_survivors": st["stage4_survivors"],
+        "orphans": st["orphans"],
+        "ms_layer": st["ms_layers"],
+        "ms_rng": st["ms_rng"],
+        "ms_lune": st["ms_lune"],
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(W, args.cpu_rows)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * grng.h -- C ABI of the MI355X (gfx950) exact RNG / GRNG library.
+ *
+ * Method: Foster, Sevilmis & Kimia, "Generalized Relative Neighborhood Graph
+ * (GRNG) for Similarity Search" (arXiv 2208.10022).  The library builds
+ *   - the GRNG of one or more nested pivot layers (Section 2, Definition 1;
+ *     Section 3 for a layer guided by a coarser one, Theorem 2), and
+ *   - the exact RNG of the points (Section 1, the RNG definition equation),
+ *     guided by the finest pivot layer (Section 2, Theorem 1, Propositions 1-4,
+ *     Algorithm 1),
+ * and answers the paper's two uses of the index: incremental insertion
+ * (Section 2, Stages I-VII) and RNG-neighbour queries (Algorithm 1 output).
+ *
+ * Exactness contract.  Results are the exact real-number answers for the
+ * float32 inputs as given.  This needs every coordinate and radius to lie on a
+ * dyadic grid: x = k * 2^-q with integer |k| < 2^24 (q = options.grid_exp),
+ * and d * kmax^2 < 2^51 where kmax is the largest |k| over all coordinates and
+ * d the dimension.  Under it every squared distance is exact in float64, so
+ * the library decides each lune test exactly; tests that involve a distance
+ * minus a radius are decided with an exact 128-bit integer predicate.  Inputs
+ * that break the contract are rejected with GRNG_ENOTGRID.
+ *
+ * Conventions.
+ *   - Pointers named *_dev are device pointers (HIP device memory of the
+ *     current device); other pointers are host pointers.
+ *   - The caller owns every buffer it passes.  The library copies what it
+ *     keeps into its own device memory, so inputs may be freed after the call
+ *     returns.  The library owns all device memory it allocates, released by
+ *     grng_destroy.
+ *   - All device work is enqueued on the stream given to grng_create.  Calls
+ *     that return host-visible counts synchronize that stream before returning.
+ *   - Errors: every call returns a grng_status; on failure grng_last_error()
+ *     describes it (thread-local) and the index is left as it was before the
+ *     call, except after GRNG_EDEVICE, after which only grng_destroy is valid.
+ *   - An index is used by one host thread at a time.
+ *   - Point ids are 0-based positions in the order points were given:
+ *     grng_create's points first, then each insert_batch appended in order.
+ *   - Edge output is canonical: pairs (u, v) with u < v, sorted by u then v,
+ *     so two edge sets are equal iff their arrays are byte-equal.
+ */
+#ifndef GRNG_H
+#define GRNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRNG_ABI_VERSION 1
+
+typedef struct grng_index grng_index;
+
+typedef enum grng_status {
+    GRNG_OK = 0,
+    GRNG_EINVAL = -1,    /* invalid argument (null pointer, size out of range, bad id, unsorted...) */
+    GRNG_ENOMEM = -2,    /* a device or host allocation failed */
+    GRNG_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+    GRNG_ENOTGRID = -4,  /* an input is not finite, not on the 2^-q grid, or too large (see above) */
+    GRNG_ECAPACITY = -5, /* caller buffer too small; *needed / *num_edges holds the required size */
+    GRNG_ESTATE = -6     /* call out of order (e.g. layer 1 before layer 0) */
+} grng_status;
+
+/* Distance-tile precision used by the screening passes.  Every kept/eliminated
+ * decision is exact in all modes; the modes differ in how much work reaches
+ * the exact float64 re-decision. */
+enum {
+    GRNG_PREC_FP64 = 0, /* exact float64 distance tiles (MFMA f64), no re-decision needed */
+    GRNG_PREC_FP32 = 1, /* float32 tiles + per-tile error bound, float64 re-decision of near ties */
+    GRNG_PREC_BF16 = 2  /* bf16 MFMA tiles (fp32 accumulate) + bound, float64 re-decision */
+};
+
+enum {
+    GRNG_ORDER_DISTANCE = 0, /* witnesses visited nearest-first (Section 2, Stages III and V) */
+    GRNG_ORDER_LEARNED = 1   /* witness domains ranked by the learned scorer (grng_set_scorer) */
+};
+
+typedef struct grng_options {
+    int32_t grid_exp;      /* q: every coordinate and radius is an integer multiple of 2^-q; 0..60 */
+    int32_t precision;     /* GRNG_PREC_* */
+    int32_t witness_order; /* GRNG_ORDER_* */
+    int32_t use_graph;     /* 1: insert_batch replays captured HIP graphs per size bucket */
+    int32_t autotune;      /* 1: pick tile shapes by timing candidates on first use */
+    int32_t stage4_pivots; /* pivot witnesses tested per pair before the exhaustive scan: 0 = default (16), 1..16 */
+    int32_t reserved_i[2]; /* must be 0 */
+    uint64_t reserved[4];  /* must be 0 */
+} grng_options;
+
+typedef struct grng_stats {
+    int64_t n_points;             /* points currently indexed */
+    int64_t n_edges;              /* exemplar RNG edges (after build_rng / insert_batch) */
+    int64_t n_layers;             /* pivot layers built */
+    int64_t orphans;              /* points in no pivot domain of the finest layer */
+    double distance_computations; /* squared distances produced (the paper's cost unit, Section 1) */
+    double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
+    double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
+    double stage4_survivors;      /* pairs left after pivot witnesses (Stage IV) */
+    double rechecks;              /* comparisons re-decided in float64 / exact integers */
+    double ms_layers;             /* device time of the last layer build */
+    double ms_rng;                /* device time of the last build_rng */
+    double ms_insert;             /* device time of the last insert_batch */
+    double ms_query;              /* device time of the last query_neighbors */
+    double ms_lune;               /* device time of the exhaustive lune kernel in the last build/insert */
+    double lune_bytes;            /* algorithmic bytes read by that kernel: (8*dp + 16) per witness test */
+    double exhaustive_pairs;      /* pairs left for the exhaustive scan after Stage V */
+    double lune_tests;            /* witness predicates evaluated by the exhaustive scan */
+    double reserved[3];
+} grng_stats;
+
+/* ABI version the library was built with (GRNG_ABI_VERSION). */
+int32_t grng_abi_version(void);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *grng_last_error(void);
+
+/* Create an index over n points of dimension d (row-major float32 [n][d],
+ * device memory).  Copies the points.  stream: a hipStream_t (NULL = null
+ * stream).  opt: host pointer, required.  Validates the grid contract on the
+ * device.  Errors: EINVAL (n < 1, d < 1 or d > 1024, null pointers, reserved
+ * fields non-zero, grid_exp out of range), ENOTGRID, ENOMEM, EDEVICE. */
+grng_status grng_create(grng_index **out, const float *points_dev, int64_t n, int32_t d,
+                        void *stream, const grng_options *opt);
+
+/* Build the GRNG of pivot layer `layer` (Section 2, Definition 1): pivots i, j
+ * are linked iff no pivot k has d(k,i) < d(i,j) - (2 r_i + r_j) and
+ * d(k,j) < d(i,j) - (r_i + 2 r_j).  Layer 0 is the coarsest and is built by
+ * brute force over all pivot triples; layer l > 0 is guided by layer l-1:
+ * fine pivots whose coarse relative-domain parents are unlinked are never
+ * linked (Section 3, Theorem 2), and coarse pivots are tried first as
+ * witnesses (Section 3, Stage IV).
+ * pivot_ids_dev: int32 [m] point ids, distinct, ascending.  radii_dev: float32
+ * [m] ball radii r_i >= 0 on the grid (a point x is in the domain of pivot p
+ * iff d(x,p) <= r_p; Section 1, pivot domain equation).  Layers must be built
+ * in order 0, 1, ...; building layer l again discards layers > l and the RNG.
+ * The pivots of layer l-1 must be a subset of those of layer l (Section 3,
+ * Theorem 2 needs nested layers).  Errors: EINVAL, ENOTGRID, ESTATE, ENOMEM,
+ * EDEVICE. */
+grng_status grng_build_grng_layer(grng_index *idx, int32_t layer, const int32_t *pivot_ids_dev,
+                                  const float *radii_dev, int64_t m);
+
+/* Build the exact RNG of all indexed points (Section 1, RNG definition:
+ * u, v linked iff no z has max(d(u,z), d(v,z)) < d(u,v); ties keep the edge).
+ * With at least one layer built, candidate pairs and witnesses are pruned by
+ * the finest layer (Section 2: Theorem 1, Propositions 1-2 for candidates,
+ * Stage IV pivot witnesses, Propositions 3-4 for witness domains); without a
+ * layer, every pair is tested against every point.  Errors: ENOMEM, EDEVICE. */
+grng_status grng_build_rng(grng_index *idx);
+
+/* Insert nb points (float32 [nb][d], device) with ids n..n+nb-1 and update
+ * the RNG to RNG(S u B) (Section 2: localization Stages I-VI for each new
+ * point against S u B, then Stage VII invalidation of existing edges by the
+ * new points, Proposition 5).  Pivot layers stay as built.  Requires a prior
+ * grng_build_rng.  Errors: EINVAL, ENOTGRID, ESTATE, ENOMEM, EDEVICE. */
+grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t nb);
+
+/* RNG neighbours of nq query points (float32 [nq][d], device) within S u {Q}
+ * for each query separately, without inserting them (Algorithm 1 output):
+ * x in S is a neighbour of Q iff no z in S \ {x} has
+ * max(d(Q,z), d(x,z)) < d(Q,x).  Output in CSR form: offsets_dev int64
+ * [nq+1] and nbrs_dev int32 [capacity], neighbours of each query ascending.
+ * If the total exceeds capacity, returns ECAPACITY with *needed set and
+ * offsets_dev filled; call again with a larger nbrs_dev.  Requires a prior
+ * grng_build_rng.  Errors: EINVAL, ENOTGRID, ESTATE, ECAPACITY, ENOMEM,
+ * EDEVICE. */
+grng_status grng_query_neighbors(grng_index *idx, const float *q_dev, int64_t nq, int64_t *offsets_dev,
+                                 int32_t *nbrs_dev, int64_t capacity, int64_t *needed);
+
+/* Copy an edge set into uv_dev (int32 [2*E], device): layer >= 0 gives the
+ * GRNG of that pivot layer as pairs of positions in its pivot list; layer = -1
+ * gives the exemplar RNG as point ids.  Canonical order (u < v, sorted).
+ * If E > capacity (in pairs), returns ECAPACITY with *num_edges = E and
+ * copies nothing.  uv_dev may be NULL with capacity 0 to query E.
+ * Errors: EINVAL, ESTATE, ECAPACITY, EDEVICE. */
+grng_status grng_get_edges(const grng_index *idx, int32_t layer, int32_t *uv_dev, int64_t capacity,
+                           int64_t *num_edges);
+
+/* Counters and device timings of the last calls (host struct). */
+grng_status grng_get_stats(const grng_index *idx, grng_stats *out);
+
+/* Release everything the index owns.  NULL is a no-op. */
+void grng_destroy(grng_index *idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRNG_H */

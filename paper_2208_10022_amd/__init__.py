@@ -1,0 +1,188 @@
+"""Python binding of the gfx950 exact RNG / GRNG library ``libgrng.so``.
+
+Argument marshalling only: every step of the build runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensor data pointers) and the
+current HIP stream; nothing here computes distances, lunes or edges.  The
+names follow the C ABI in ``include/grng.h``.  If the library is missing this
+module raises at load time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrng.so")
+
+GRNG_OK = 0
+STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_EDEVICE", -4: "GRNG_ENOTGRID",
+                -5: "GRNG_ECAPACITY", -6: "GRNG_ESTATE"}
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+ORDER_DISTANCE, ORDER_LEARNED = 0, 1
+
+# Entry points declared in include/grng.h (checked by the CPU tests).
+ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
+                 "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy")
+
+
+class GrngError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("grid_exp", C.c_int32), ("precision", C.c_int32), ("witness_order", C.c_int32),
+                ("use_graph", C.c_int32), ("autotune", C.c_int32), ("stage4_pivots", C.c_int32),
+                ("reserved_i", C.c_int32 * 2), ("reserved", C.c_uint64 * 4)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("n_edges", C.c_int64), ("n_layers", C.c_int64), ("orphans", C.c_int64),
+                ("distance_computations", C.c_double), ("witness_tests", C.c_double),
+                ("candidate_pairs", C.c_double), ("stage4_survivors", C.c_double), ("rechecks", C.c_double),
+                ("ms_layers", C.c_double), ("ms_rng", C.c_double), ("ms_insert", C.c_double),
+                ("ms_query", C.c_double), ("ms_lune", C.c_double), ("lune_bytes", C.c_double),
+                ("exhaustive_pairs", C.c_double), ("lune_tests", C.c_double), ("reserved", C.c_double * 3)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libgrng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgrng.so is not built; run paper_2208_10022_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        sig = {
+            "grng_abi_version": (i32, []),
+            "grng_last_error": (C.c_char_p, []),
+            "grng_create": (i32, [C.POINTER(vp), vp, i64, i32, vp, C.POINTER(Options)]),
+            "grng_build_grng_layer": (i32, [vp, i32, vp, vp, i64]),
+            "grng_build_rng": (i32, [vp]),
+            "grng_insert_batch": (i32, [vp, vp, i64]),
+            "grng_query_neighbors": (i32, [vp, vp, i64, vp, vp, i64, C.POINTER(i64)]),
+            "grng_get_edges": (i32, [vp, i32, vp, i64, C.POINTER(i64)]),
+            "grng_get_stats": (i32, [vp, C.POINTER(Stats)]),
+            "grng_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().grng_last_error().decode()
+
+
+def check(status: int) -> None:
+    if status != GRNG_OK:
+        raise GrngError(status, last_error())
+
+
+def _dev_ptr(t, dtype_name: str, ndim: int | None = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("expected dtype %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("expected %d dimensions" % ndim)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Index:
+    """An exact RNG / GRNG index over device-resident points (see include/grng.h)."""
+
+    def __init__(self, points, grid_exp: int, precision: int = PREC_FP64, witness_order: int = ORDER_DISTANCE,
+                 use_graph: int = 0, autotune: int = 0, stage4_pivots: int = 0, stream=None):
+        self._h = C.c_void_p()
+        self._stream = stream
+        opt = Options(grid_exp=grid_exp, precision=precision, witness_order=witness_order, use_graph=use_graph,
+                      autotune=autotune, stage4_pivots=stage4_pivots)
+        n, d = points.shape
+        check(lib().grng_create(C.byref(self._h), _dev_ptr(points, "float32", 2), n, d,
+                                _stream_handle(stream), C.byref(opt)))
+        self.d = d
+
+    def build_grng_layer(self, layer: int, pivot_ids, radii) -> None:
+        m = pivot_ids.numel()
+        if radii.numel() != m:
+            raise ValueError("pivot_ids and radii differ in length")
+        check(lib().grng_build_grng_layer(self._h, layer, _dev_ptr(pivot_ids, "int32", 1),
+                                          _dev_ptr(radii, "float32", 1), m))
+
+    def build_rng(self) -> None:
+        check(lib().grng_build_rng(self._h))
+
+    def insert_batch(self, points) -> None:
+        check(lib().grng_insert_batch(self._h, _dev_ptr(points, "float32", 2), points.shape[0]))
+
+    def query_neighbors(self, queries):
+        """Returns (offsets int64 [nq+1], neighbours int32 [total]) as device tensors."""
+        import torch
+        nq = queries.shape[0]
+        dev = queries.device
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+        cap = max(16 * nq, 1)
+        for _ in range(2):
+            nbrs = torch.empty(cap, dtype=torch.int32, device=dev)
+            needed = C.c_int64(0)
+            st = lib().grng_query_neighbors(self._h, _dev_ptr(queries, "float32", 2), nq, _dev_ptr(offsets, "int64"),
+                                            _dev_ptr(nbrs, "int32"), cap, C.byref(needed))
+            if st == -5:
+                cap = int(needed.value)
+                continue
+            check(st)
+            return offsets, nbrs[:int(needed.value)]
+        raise GrngError(-5, "query output kept growing")
+
+    def num_edges(self, layer: int = -1) -> int:
+        ne = C.c_int64(0)
+        st = lib().grng_get_edges(self._h, layer, None, 0, C.byref(ne))
+        if st not in (GRNG_OK, -5):
+            check(st)
+        return int(ne.value)
+
+    def edges(self, layer: int = -1):
+        """Canonical edge list as a device int32 tensor [E, 2] (u < v, sorted)."""
+        import torch
+        ne = self.num_edges(layer)
+        out = torch.empty((max(ne, 0), 2), dtype=torch.int32, device="cuda")
+        n2 = C.c_int64(0)
+        check(lib().grng_get_edges(self._h, layer, _dev_ptr(out, "int32") if ne else None, ne, C.byref(n2)))
+        return out
+
+    def stats(self) -> dict:
+        st = Stats()
+        check(lib().grng_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            lib().grng_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

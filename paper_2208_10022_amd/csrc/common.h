@@ -1,0 +1,216 @@
+// Internal declarations of the gfx950 exact RNG / GRNG library.
+// Not part of the public ABI (that is include/grng.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "grng.h"
+
+namespace grng {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws Error; the ABI layer turns it into a status.
+struct Error : std::runtime_error {
+    grng_status status;
+    Error(grng_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define GRNG_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::grng::Error(GRNG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GRNG_LAUNCHED() GRNG_HIP(hipGetLastError())
+
+inline void require(bool ok, grng_status s, const std::string &msg) {
+    if (!ok) throw Error(s, msg);
+}
+
+// ---------------------------------------------------------------------------
+// Owning device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t nbytes);            // throws ENOMEM; contents undefined
+    void ensure(size_t nbytes);           // grow (discarding contents) if smaller
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Sizes and constants.
+constexpr int kWave = 64;
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int pad4(int d) { return (d + 3) & ~3; }
+
+// Pivot layer: pivots, radii, their exact distances and the GRNG.
+struct Layer {
+    int64_t m = 0;
+    int32_t words = 0;         // uint64 words per bitset row: ceil(m / 64)
+    std::vector<int32_t> pid_host;
+    DevBuf pid;                // int32 [m] point ids
+    DevBuf rad;                // double [m] radii (exact grid values)
+    DevBuf radi;               // int64 [m] radii in grid units
+    DevBuf dpp2;               // double [m*m] exact squared distances
+    DevBuf dpp;                // double [m*m] distances (sqrt rounded to nearest)
+    DevBuf bits;               // uint64 [m*words] GRNG adjacency (no self bits)
+    DevBuf edges;              // int32 [2E] canonical pivot-position pairs
+    int64_t nedges = 0;
+    DevBuf parent_bits;        // uint64 [m*coarse_words]: coarse relative-domain parents (layer > 0)
+};
+
+// Per-point state of the finest-layer-guided RNG (all arrays in home order).
+struct PointState {
+    int64_t n = 0;
+    DevBuf perm;               // int32 [n] home-order position -> point id
+    DevBuf inv;                // int32 [n] point id -> home-order position
+    DevBuf Xh;                 // double [n*dp] coordinates in home order
+    DevBuf nrmh;               // double [n] squared norms in home order
+    DevBuf home;               // int32 [n] nearest pivot (position in layer)
+    DevBuf dhome;              // double [n] upper bound of d(x, p_home)
+    DevBuf grp_off;            // int32 [m+1] home-order range of each group
+    DevBuf dvor;               // double [m] upper bound of the group radius (max d(x, p_c))
+    DevBuf par_off;            // int64 [n+1] parents CSR
+    DevBuf par_idx;            // int32 [nnz]
+    DevBuf knn;                // int32 [n*K] nearest pivots (Stage IV witnesses)
+    DevBuf g_rows;             // uint64 [n*words] virtual-pivot GRNG(x) (domain radii)
+    DevBuf v_rows;             // uint64 [n*words] virtual-pivot GRNG of x over Voronoi groups
+    DevBuf g_cols;             // uint64 [m*nw] transposed g_rows (nw = ceil(n/64))
+    DevBuf v_cols;             // uint64 [m*nw] transposed v_rows
+    int64_t orphans = 0;
+};
+
+// Counters written by kernels (device, uint64 each).
+enum Counter {
+    C_DIST = 0,       // squared distances computed
+    C_WTEST,          // witness predicates evaluated
+    C_CAND,           // candidate pairs after Stages I-III
+    C_S4,             // survivors of Stage IV
+    C_RECHECK,        // exact re-decisions
+    C_SURV,           // pairs left for the exhaustive scan (after Stage V)
+    C_LUNE,           // witness predicates evaluated by the exhaustive scan
+    C_NUM
+};
+
+}  // namespace grng
+
+struct grng_index {
+    hipStream_t stream = nullptr;
+    grng_options opt{};
+    int32_t d = 0, dp = 0, q = 0;
+    int64_t n = 0, cap = 0;
+    double kmax = 0;           // largest |grid integer| seen so far
+    grng::DevBuf X;            // double [cap*dp] exact coordinates, rows zero-padded
+    grng::DevBuf nrm;          // double [cap] exact squared norms
+    std::vector<grng::Layer> layers;
+    grng::PointState ps;       // valid when rng_built
+    bool rng_built = false;
+    grng::DevBuf edges;        // int32 [2E] canonical exemplar RNG edges
+    int64_t nedges = 0;
+    grng::DevBuf counters;     // uint64 [C_NUM]
+    grng_stats stats{};
+};
+
+namespace grng {
+
+// ---------------------------------------------------------------------------
+// Launchers (one per kernel family; defined next to the kernels).
+
+// k_basic.hip
+void launch_grid_check(hipStream_t s, const float *x, int64_t count, double scale, uint64_t *kmax_bits,
+                       int32_t *bad);
+void launch_grid_check_f64(hipStream_t s, const double *x, int64_t count, double scale, uint64_t *kmax_bits,
+                           int32_t *bad);
+void launch_to_f64(hipStream_t s, const float *src, int64_t n, int d, int dp, double *dst, double *nrm);
+void launch_dist2(hipStream_t s, const double *A, const double *nA, int64_t na, const double *B,
+                  const double *nB, int64_t nb, int dp, double *out, int64_t ldo, bool use_mfma);
+void launch_sqrt(hipStream_t s, const double *in, double *out, int64_t count);
+void launch_gather_rows(hipStream_t s, const double *src, const int32_t *idx, int64_t n, int dp, double *dst);
+void launch_gather_f64(hipStream_t s, const double *src, const int32_t *idx, int64_t n, double *dst);
+void launch_iota_inverse(hipStream_t s, const int32_t *perm, int64_t n, int32_t *inv);
+void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out_excl);  // out has n+1
+void launch_scan_i32_to_i64(hipStream_t s, const int32_t *in, int64_t n, int64_t *out_excl);
+void launch_bits_transpose(hipStream_t s, const uint64_t *rows, int64_t n, int32_t words, int64_t m,
+                           uint64_t *cols);
+void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t count, uint64_t v);
+
+// k_pivots.hip
+void launch_grng_layer(hipStream_t s, int64_t m, const double *dpp, const double *dpp2, const double *rad,
+                       const int64_t *radi, int32_t q, const uint64_t *cand_bits, int32_t words,
+                       const int32_t *witness_first, int64_t nfirst, uint64_t *bits, uint64_t *counters);
+void launch_relative_parents(hipStream_t s, int64_t mc, const int32_t *coarse_pos_in_fine,
+                             const double *dpp2_fine, int64_t mf, const double *rad_c, const double *rad_f,
+                             uint64_t *parent_bits, int32_t cwords);
+void launch_guided_candidates(hipStream_t s, int64_t mf, const uint64_t *parent_bits, int32_t cwords,
+                              const uint64_t *coarse_bits, int64_t mc, uint64_t *cand_bits, int32_t fwords);
+void launch_point_pass1(hipStream_t s, int64_t n, int64_t m, const double *dxp, const double *rad,
+                        int32_t *home, double *d2home, int32_t *npar);
+void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const double *d2home,
+                         uint64_t *d2vor_bits, int32_t *gcount);
+void launch_point_pass2(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
+                        const double *rad, const double *dpp, const uint64_t *layer_bits, int32_t words,
+                        const double *dvor, const int32_t *gcount, const int64_t *par_off, int32_t *par_idx,
+                        int32_t K, int32_t *knn, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
+
+// k_rng.hip
+struct PairList {
+    int32_t *x;       // home-order position of the row point
+    int32_t *y;       // home-order position of the other point
+    double *d2;       // exact squared distance
+    uint64_t *count;  // number of pairs requested (may exceed cap)
+    int64_t cap;
+};
+constexpr int kPivWitness = 16;   // pivot witnesses per tile pair in the tiled pair kernel
+void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t *pknn);   // pknn [m][16]
+void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
+                       uint64_t *tv);
+void launch_tile_pairs(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *tv, int32_t words,
+                       const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU);
+void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const int32_t *tiles,
+                        int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
+                        const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
+                        const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
+                        uint64_t *dmax_bits, uint64_t *counters);
+void launch_pairs_all(hipStream_t s, int64_t n, int dp, const double *X, const double *nrm, PairList out,
+                      uint64_t *dmax_bits, uint64_t *counters);
+void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
+                            const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
+                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_dx);
+void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
+                        int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
+                        const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
+                        const int32_t *rel_grp, const double *rel_dx, uint8_t *alive, uint64_t *counters);
+void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
+                     int64_t n, int dp, const double *X, const double *nrm, uint8_t *alive, uint64_t *counters);
+
+// k_edges.hip
+void launch_edges_count(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py,
+                        const uint8_t *alive, const int32_t *perm, int32_t *deg);
+void launch_edges_fill(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,
+                       const int32_t *perm, const int64_t *off, int32_t *fillpos, int32_t *nbr);
+void launch_edges_emit(hipStream_t s, int64_t n, const int64_t *off, int32_t *nbr, int32_t *uv);
+void launch_bits_to_edges_count(hipStream_t s, int64_t m, const uint64_t *bits, int32_t words, int32_t *deg);
+void launch_bits_to_edges_emit(hipStream_t s, int64_t m, const uint64_t *bits, int32_t words, const int64_t *off,
+                               int32_t *uv);
+
+}  // namespace grng

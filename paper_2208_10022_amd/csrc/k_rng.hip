@@ -1,0 +1,680 @@
+// Exemplar-RNG kernels: candidate pairs and the lune-emptiness test.
+//
+// Pair (x, y) is an RNG edge iff no point z has max(d(x,z), d(y,z)) < d(x,y)
+// (Section 1, RNG definition; ties keep the edge).  Squared distances are
+// exact float64 values (grid contract), so each lune predicate below is the
+// exact decision.  Pruning follows Section 2:
+//   Stages I-III  pair kept only if every domain parent of y is in the
+//                 virtual-pivot GRNG of x and vice versa (Theorem 1 and
+//                 Propositions 1-2), and if the home cells of x and y survive
+//                 the same virtual-pivot test with cell radii;
+//   Stage IV      pivots as witnesses;
+//   Stages V-VI   exhaustive scan over points grouped by home cell, skipping a
+//                 whole cell when max(d(x,p), d(y,p)) - radius(p) >= d(x,y)
+//                 (Proposition 3) and a single point z of the cell when
+//                 max(d(x,p), d(y,p)) - d(z,p) >= d(x,y) (Proposition 4).
+//                 These skips use square roots, so they are taken only with a
+//                 safety margin (pruning less only costs work).
+//
+// Layout: points in home order (grouped by nearest pivot), coordinates as
+// zero-padded float64 rows of dp values.  One wave owns one row point x in
+// the pair enumeration and one pair in the lune scan; the 64 lanes stream
+// candidate points y (pairs) or witnesses z (lune scan) with coalesced row
+// loads, and a wave ballot ends the scan at the first witness.
+#include <algorithm>
+
+#include "common.h"
+
+namespace grng {
+
+namespace {
+
+constexpr int kMaxDp = 128;      // largest padded dimension kept in LDS per wave
+
+__device__ inline double dot_lds(const double *__restrict__ a_lds, const double *__restrict__ b, int dp) {
+    double acc = 0.0;
+    for (int t = 0; t < dp; t += 2) {
+        const double2 bv = *reinterpret_cast<const double2 *>(b + t);
+        acc = fma(a_lds[t], bv.x, acc);
+        acc = fma(a_lds[t + 1], bv.y, acc);
+    }
+    return acc;
+}
+
+__device__ inline double sqrt_lo(double v) { return sqrt(v) * (1.0 - 1e-15); }
+__device__ inline double sqrt_hi(double v) { return sqrt(v) * (1.0 + 1e-15); }
+
+// "a - b >= c" certainly, for non-negative a, b, c given as bounds.
+__device__ inline bool surely_ge(double a_lo, double b_hi, double c_hi) {
+    return a_lo - b_hi >= c_hi + 1e-13 * (a_lo + b_hi + c_hi);
+}
+
+__device__ inline void wave_append(PairList out, bool keep, int32_t x, int32_t y, double d2) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd((unsigned long long *)out.count, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0, kWave);
+    if (keep) {
+        const uint64_t slot = base + __popcll(m & ((1ull << lane) - 1ull));
+        if ((int64_t)slot < out.cap) {
+            out.x[slot] = x;
+            out.y[slot] = y;
+            out.d2[slot] = d2;
+        }
+    }
+}
+
+__device__ inline uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Candidate pairs guided by the pivot layer (Stages I-V), tiled.
+//
+// Points are split into tiles: chunks of at most 64 consecutive home-order
+// points of one home cell.  A workgroup takes a pair of tiles (T, U), T <= U,
+// whose cells survive each other's virtual-pivot test, and for the 64 x 64
+// pairs (x in T, y in U):
+//   * exact d^2(x, y) from an f64 MFMA tile (16x16x4 blocks, operands in LDS);
+//   * Stages I-III as bit masks: P(x) within GRNG(y) and P(y) within GRNG(x)
+//     from the transposed virtual-pivot bitsets, and the cell bits of both;
+//   * Stage IV: the pivots nearest to the two cells as witnesses, with exact
+//     d^2 to the pivots from two more MFMA tiles;
+//   * Stage V: each survivor is tested against the 128 points of T and U,
+//     already in LDS (one lane per witness, wave ballot for the verdict).
+// Survivors go to the global pair list for the exhaustive scan.
+constexpr int kTile = 64;
+constexpr int kPiv = 16;        // pivot witnesses per tile pair (one MFMA column block)
+constexpr int kQueue = 512;     // Stage IV survivors held in LDS for Stage V
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct TileLds {
+    double *X, *Y, *P;          // [64][ld], [64][ld], [16][ld] rows, ld = dp + 1
+    double *nX, *nY, *nP;       // norms
+    double *XP, *YP;            // [64][17] exact d^2 to the pivot witnesses
+    uint64_t *mX, *mY;          // candidate masks per x (over U) and per y (over T)
+    uint32_t *qpair;            // Stage V queue: i | j << 8
+    double *qd2;
+    int32_t *qcount;
+};
+
+__device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) {
+    // 64 bits of a bit row starting at bit `start` (bits past len are don't-care)
+    const int64_t w = start >> 6;
+    const int sh = (int)(start & 63);
+    uint64_t v = row[w] >> sh;
+    if (sh && ((start + len - 1) >> 6) > w) v |= row[w + 1] << (64 - sh);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_pairs_tiled(
+    int64_t ntp, const int32_t *__restrict__ tpT, const int32_t *__restrict__ tpU, const int32_t *__restrict__ tiles,
+    int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const int64_t *__restrict__ par_off,
+    const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ v_rows, const uint64_t *__restrict__ g_cols,
+    int32_t words, int64_t nw, const int32_t *__restrict__ pknn, int32_t K, const double *__restrict__ Xp,
+    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *counters) {
+    extern __shared__ double lds[];
+    const int ld = dp + 1;
+    TileLds L;
+    L.X = lds;
+    L.Y = L.X + kTile * ld;
+    L.P = L.Y + kTile * ld;
+    L.nX = L.P + kPiv * ld;
+    L.nY = L.nX + kTile;
+    L.nP = L.nY + kTile;
+    L.XP = L.nP + kPiv;
+    L.YP = L.XP + kTile * (kPiv + 1);
+    L.mX = (uint64_t *)(L.YP + kTile * (kPiv + 1));
+    L.mY = L.mX + kTile;
+    L.qd2 = (double *)(L.mY + kTile);
+    L.qpair = (uint32_t *)(L.qd2 + kQueue);
+    L.qcount = (int32_t *)(L.qpair + kQueue);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntests = 0;
+    for (int64_t tp = blockIdx.x; tp < ntp; tp += gridDim.x) {
+        const int32_t T = tpT[tp], U = tpU[tp];
+        const int32_t sT = tiles[3 * T], lT = tiles[3 * T + 1], a = tiles[3 * T + 2];
+        const int32_t sU = tiles[3 * U], lU = tiles[3 * U + 1], b = tiles[3 * U + 2];
+        // 1. rows, norms, pivot witnesses, candidate masks -> LDS
+        for (int e = tid; e < kTile * dp; e += 256) {
+            const int r = e / dp, c = e % dp;
+            L.X[r * ld + c] = r < lT ? Xh[(int64_t)(sT + r) * dp + c] : 0.0;
+            L.Y[r * ld + c] = r < lU ? Xh[(int64_t)(sU + r) * dp + c] : 0.0;
+        }
+        const int ka = (a == b) ? K : (K + 1) / 2;
+        for (int e = tid; e < kPiv * dp; e += 256) {
+            const int t = e / dp, c = e % dp;
+            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
+            L.P[t * ld + c] = Xp[(int64_t)pv * dp + c];
+        }
+        if (tid < kPiv) {
+            const int t = tid;
+            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
+            L.nP[t] = nrmp[pv];
+        }
+        if (tid < kTile) {
+            const int r = tid;
+            uint64_t mk = 0;
+            double nv = 0.0;
+            if (r < lT) {
+                const int64_t x = sT + r;
+                nv = nrmh[x];
+                mk = ((v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
+                for (int64_t q = par_off[x]; q < par_off[x + 1] && mk; ++q)
+                    mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sU, lU);
+            }
+            L.nX[r] = nv;
+            L.mX[r] = mk;
+        } else if (tid < 2 * kTile) {
+            const int r = tid - kTile;
+            uint64_t mk = 0;
+            double nv = 0.0;
+            if (r < lU) {
+                const int64_t y = sU + r;
+                nv = nrmh[y];
+                mk = ((v_rows[y * words + (a >> 6)] >> (a & 63)) & 1ull) ? ~0ull : 0ull;
+                for (int64_t q = par_off[y]; q < par_off[y + 1] && mk; ++q)
+                    mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sT, lT);
+            }
+            L.nY[r] = nv;
+            L.mY[r] = mk;
+        } else if (tid == 2 * kTile) {
+            *L.qcount = 0;
+        }
+        __syncthreads();
+        // 2. MFMA tiles: D_XY (each wave 32x32), and 16 rows of X.P^T and Y.P^T per wave.
+        const int il = lane & 15, kl = lane >> 4;
+        v4d acc[2][2];
+        v4d axp = {0.0, 0.0, 0.0, 0.0}, ayp = {0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) acc[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int kk = 0; kk < dp; kk += 4) {
+            double av[2], bv[2];
+            for (int u = 0; u < 2; ++u) av[u] = L.X[(wr * 32 + u * 16 + il) * ld + kk + kl];
+            for (int v = 0; v < 2; ++v) bv[v] = L.Y[(wc * 32 + v * 16 + il) * ld + kk + kl];
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
+            const double pv = L.P[il * ld + kk + kl];
+            axp = __builtin_amdgcn_mfma_f64_16x16x4f64(L.X[(w * 16 + il) * ld + kk + kl], pv, axp, 0, 0, 0);
+            ayp = __builtin_amdgcn_mfma_f64_16x16x4f64(L.Y[(w * 16 + il) * ld + kk + kl], pv, ayp, 0, 0, 0);
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int row = w * 16 + 4 * r + kl;
+            L.XP[row * (kPiv + 1) + il] = L.nX[row] + L.nP[il] - 2.0 * axp[r];
+            L.YP[row * (kPiv + 1) + il] = L.nY[row] + L.nP[il] - 2.0 * ayp[r];
+        }
+        __syncthreads();
+        // 3. candidates (Stages I-III) and pivot witnesses (Stage IV).
+        double d2[2][2][4];
+        uint32_t live = 0;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+                const int j = wc * 32 + v * 16 + il;
+                for (int r = 0; r < 4; ++r) {
+                    const int i = wr * 32 + u * 16 + 4 * r + kl;
+                    d2[u][v][r] = L.nX[i] + L.nY[j] - 2.0 * acc[u][v][r];
+                    const bool c = i < lT && j < lU && (T != U || j > i) && ((L.mX[i] >> j) & 1ull) &&
+                                   ((L.mY[j] >> i) & 1ull);
+                    if (c) live |= 1u << (u * 8 + v * 4 + r);
+                }
+            }
+        ncand += __popc(live);
+        for (int t = 0; t < K; ++t) {
+            if (!__ballot(live != 0)) break;
+            double yv[2], xv[2][4];
+            for (int v = 0; v < 2; ++v) yv[v] = L.YP[(wc * 32 + v * 16 + il) * (kPiv + 1) + t];
+            for (int u = 0; u < 2; ++u)
+                for (int r = 0; r < 4; ++r) xv[u][r] = L.XP[(wr * 32 + u * 16 + 4 * r + kl) * (kPiv + 1) + t];
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const uint32_t bit = 1u << (u * 8 + v * 4 + r);
+                        if ((live & bit) && fmax(xv[u][r], yv[v]) < d2[u][v][r]) live &= ~bit;
+                    }
+            ntests += 16;
+        }
+        ns4 += __popc(live);
+        // Stage V in rounds: move up to kQueue Stage IV survivors into the LDS
+        // queue, test them against the points of T and U, repeat until none is
+        // left (every survivor passes through Stage V, so the output is
+        // deterministic).
+        for (;;) {
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const uint32_t bit = 1u << (u * 8 + v * 4 + r);
+                        if (!(live & bit)) continue;
+                        const int slot = atomicAdd(L.qcount, 1);
+                        if (slot >= kQueue) continue;      // stays live for the next round
+                        live &= ~bit;
+                        const int i = wr * 32 + u * 16 + 4 * r + kl, j = wc * 32 + v * 16 + il;
+                        L.qpair[slot] = (uint32_t)i | ((uint32_t)j << 8);
+                        L.qd2[slot] = d2[u][v][r];
+                    }
+            __syncthreads();
+            const int qn = min(*L.qcount, kQueue);
+            for (int e = w; e < qn; e += 4) {
+                const uint32_t pr = L.qpair[e];
+                const int i = pr & 255, j = pr >> 8;
+                const double dd = L.qd2[e];
+                const double *xr = L.X + i * ld, *yr = L.Y + j * ld;
+                bool wit = false;
+                for (int half = 0; half < 2 && !wit; ++half) {
+                    const int zl = lane;
+                    const bool ok = half == 0 ? zl < lT : zl < lU;
+                    bool wz = false;
+                    if (ok) {
+                        const double *zr = (half == 0 ? L.X : L.Y) + zl * ld;
+                        const double nz = half == 0 ? L.nX[zl] : L.nY[zl];
+                        double sx = 0.0, sy = 0.0;
+                        for (int c = 0; c < dp; ++c) {
+                            sx = fma(xr[c], zr[c], sx);
+                            sy = fma(yr[c], zr[c], sy);
+                        }
+                        const double d2xz = L.nX[i] + nz - 2.0 * sx;
+                        const double d2yz = L.nY[j] + nz - 2.0 * sy;
+                        wz = d2xz < dd && d2yz < dd;
+                        ++ntests;
+                    }
+                    wit = __ballot(wz) != 0;
+                }
+                if (!wit && lane == 0) {
+                    const unsigned long long s0 = atomicAdd((unsigned long long *)out.count, 1ull);
+                    if ((int64_t)s0 < out.cap) {
+                        out.x[s0] = sT + i;
+                        out.y[s0] = sU + j;
+                        out.d2[s0] = dd;
+                    }
+                    atomicMax(&dmax_bits[sT + i], (unsigned long long)__double_as_longlong(dd));
+                    ++nsurv;
+                }
+            }
+            __syncthreads();
+            const bool more = *L.qcount > kQueue;
+            __syncthreads();
+            if (tid == 0) *L.qcount = 0;
+            __syncthreads();
+            if (!more) break;
+        }
+    }
+    ncand = wave_sum(ncand);
+    ns4 = wave_sum(ns4);
+    ntests = wave_sum(ntests);
+    nsurv = wave_sum(nsurv);
+    if (lane == 0) {
+        atomicAdd(&counters[C_CAND], (unsigned long long)ncand);
+        atomicAdd(&counters[C_S4], (unsigned long long)ns4);
+        atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
+    }
+}
+
+// Tile bookkeeping: OR of the cell bits of a tile's points; tile pairs whose
+// cells survive each other's virtual-pivot test; nearest pivots of each pivot.
+__global__ void k_tile_vmask(int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
+                             uint64_t *tv) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= ntiles * words) return;
+    const int64_t t = e / words;
+    const int32_t wd = (int32_t)(e % words);
+    const int32_t s = tiles[3 * t], l = tiles[3 * t + 1];
+    uint64_t acc = 0;
+    for (int r = 0; r < l; ++r) acc |= v_rows[(int64_t)(s + r) * words + wd];
+    tv[e] = acc;
+}
+
+__global__ __launch_bounds__(64) void k_tile_pairs(int64_t ntiles, const int32_t *tiles, const uint64_t *tv,
+                                                   int32_t words, const int64_t *off, int32_t *cnt, int32_t *oT,
+                                                   int32_t *oU) {
+    const int lane = threadIdx.x;
+    const int64_t T = blockIdx.x;
+    const int32_t a = tiles[3 * T + 2];
+    int64_t pos = off ? off[T] : 0;
+    int c = 0;
+    for (int64_t u0 = T; u0 < ntiles; u0 += 64) {
+        const int64_t U = u0 + lane;
+        bool keep = false;
+        if (U < ntiles) {
+            const int32_t b = tiles[3 * U + 2];
+            keep = ((tv[T * words + (b >> 6)] >> (b & 63)) & 1ull) && ((tv[U * words + (a >> 6)] >> (a & 63)) & 1ull);
+        }
+        const uint64_t m = __ballot(keep);
+        if (off && keep) {
+            const int64_t slot = pos + __popcll(m & ((1ull << lane) - 1ull));
+            oT[slot] = (int32_t)T;
+            oU[slot] = (int32_t)U;
+        }
+        pos += __popcll(m);
+        c += __popcll(m);
+    }
+    if (!off && lane == 0) cnt[T] = c;
+}
+
+__global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2, int32_t *pknn) {
+    const int lane = threadIdx.x;
+    const int64_t a = blockIdx.x;
+    double last = -1.0;
+    int64_t lastk = -1;
+    for (int t = 0; t < kPiv; ++t) {
+        double best = INFINITY;
+        int64_t bk = m;
+        for (int64_t k = lane; k < m; k += 64) {
+            const double v = dpp2[a * m + k];
+            const bool after = v > last || (v == last && k > lastk);
+            if (after && (v < best || (v == best && k < bk))) { best = v; bk = k; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, kWave);
+            const int64_t ok = __shfl_xor(bk, o, kWave);
+            if (ob < best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+        }
+        if (bk >= m) bk = a;    // fewer than kPiv pivots: repeat the pivot itself
+        else { last = best; lastk = bk; }
+        if (lane == 0) pknn[a * kPiv + t] = (int32_t)bk;
+    }
+}
+
+// All pairs i < j (no pivot layer).  Thread per pair, one block row per i.
+__global__ void k_pairs_all(int64_t n, int dp, const double *__restrict__ X, const double *__restrict__ nrm,
+                            PairList out, uint64_t *dmax_bits, unsigned long long *counters) {
+    const int64_t i = blockIdx.y;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool keep = j > i && j < n;
+    double d2 = 0.0;
+    if (keep) {
+        double acc = 0.0;
+        for (int t = 0; t < dp; ++t) acc = fma(X[i * dp + t], X[j * dp + t], acc);
+        d2 = nrm[i] + nrm[j] - 2.0 * acc;
+    }
+    wave_append(out, keep, (int32_t)i, (int32_t)j, d2);
+    const uint32_t c = wave_sum(keep ? 1u : 0u);
+    if ((threadIdx.x & 63) == 0 && c) {
+        atomicAdd(&counters[C_DIST], (unsigned long long)c);
+        atomicAdd(&counters[C_CAND], (unsigned long long)c);
+    }
+    (void)dmax_bits;
+}
+
+// ---------------------------------------------------------------------------
+// Witness cells relevant to a row point x: cell c may hold a witness of some
+// pair (x, y) of x only if d(x, p_c) - radius(c) < max_y d(x, y)
+// (Proposition 3 with the x-side distance alone).  pass 0 counts, pass 1
+// fills the cells sorted by d(x, p_c) ascending with their exact d^2(x, p_c).
+__global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, int32_t mpow2, const int32_t *perm,
+                                                        const double *dxp, const double *dvor, const int32_t *gcount,
+                                                        const uint64_t *dmax_bits, const int64_t *rel_off,
+                                                        int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
+                                                        int pass) {
+    extern __shared__ unsigned char smem[];
+    double *key = (double *)smem;
+    int32_t *kid = (int32_t *)(key + mpow2);
+    const int lane = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const double dmax2 = __longlong_as_double((long long)dmax_bits[i]);
+    const double dmax_hi = sqrt_hi(dmax2);
+    const double *row = dxp + (int64_t)perm[i] * m;
+    int cnt = 0;
+    for (int64_t k0 = 0; k0 < mpow2; k0 += 64) {
+        const int64_t k = k0 + lane;
+        bool keep = false;
+        double d2 = INFINITY;
+        if (k < m && dmax2 > 0.0 && gcount[k] > 0) {
+            d2 = row[k];
+            keep = !surely_ge(sqrt_lo(d2), dvor[k], dmax_hi);
+        }
+        cnt += __popcll(__ballot(keep));
+        if (pass == 1 && k < mpow2) {
+            key[k] = keep ? d2 : INFINITY;
+            kid[k] = (int32_t)k;
+        }
+    }
+    if (pass == 0) {
+        if (lane == 0) rel_cnt[i] = cnt;
+        return;
+    }
+    __syncthreads();
+    for (int32_t size = 2; size <= mpow2; size <<= 1) {
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int32_t t = lane; t < (mpow2 >> 1); t += 64) {
+                const int32_t lo = 2 * t - (t & (stride - 1));
+                const int32_t hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double ka = key[lo], kb = key[hi];
+                const int32_t ia = kid[lo], ib = kid[hi];
+                const bool gt = ka > kb || (ka == kb && ia > ib);
+                if (gt == up) {
+                    key[lo] = kb; key[hi] = ka;
+                    kid[lo] = ib; kid[hi] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t o = rel_off[i];
+    for (int t = lane; t < cnt; t += 64) {
+        rel_grp[o + t] = kid[t];
+        rel_d2x[o + t] = key[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exhaustive lune test of surviving pairs (Stages IV-VI).  One wave per pair.
+__global__ __launch_bounds__(256) void k_lune_guided(
+    int64_t npairs, const int32_t *__restrict__ px, const int32_t *__restrict__ py, const double *__restrict__ pd2,
+    int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const double *__restrict__ dhome,
+    const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
+    const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
+    const double *__restrict__ rel_d2x, uint8_t *__restrict__ alive, unsigned long long *counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    uint32_t ntests = 0, ndist = 0;
+    for (int64_t p = wave0; p < npairs; p += nwaves) {
+        const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
+        const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
+        const double d2 = pd2[p];
+        const double *xs = Xh + x * dp;
+        const double *ys = Xh + y * dp;
+        const double nrx = nrmh[x], nry = nrmh[y];
+        const double dxy_hi = sqrt_hi(d2);
+        bool dead = false;
+        const int64_t r0 = rel_off[x], r1 = rel_off[x + 1];
+        for (int64_t c0 = r0; c0 < r1 && !dead; c0 += 64) {
+            const int64_t c = c0 + lane;
+            bool scan = false;
+            double dxl = 0.0, dyl = 0.0;
+            int32_t g = 0;
+            if (c < r1) {
+                g = rel_grp[c];
+                const double d2x = rel_d2x[c];
+                const double d2y = nry + nrmp[g] - 2.0 * dot_lds(ys, Xp + (int64_t)g * dp, dp);
+                ++ndist;
+                ++ntests;
+                // Stage IV: the cell's pivot itself as a witness (exact).
+                if (d2x < d2 && d2y < d2) dead = true;
+                dxl = sqrt_lo(d2x);
+                dyl = sqrt_lo(d2y);
+                // Proposition 3: skip the cell when it lies wholly outside the lune.
+                scan = !surely_ge(fmax(dxl, dyl), dvor[g], dxy_hi);
+            }
+            if (__ballot(dead)) { dead = true; break; }
+            uint64_t cells = __ballot(scan);
+            while (cells && !dead) {
+                const int src = __ffsll((long long)cells) - 1;
+                cells &= cells - 1;
+                const int32_t gg = __shfl(g, src, kWave);
+                const double gx = __shfl(dxl, src, kWave), gy = __shfl(dyl, src, kWave);
+                const double gmax = fmax(gx, gy);
+                const int64_t z0 = grp_off[gg], z1 = grp_off[gg + 1];
+                for (int64_t zb = z0; zb < z1; zb += 64) {
+                    const int64_t z = zb + lane;
+                    bool wit = false;
+                    // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
+                    if (z < z1 && !surely_ge(gmax, dhome[z], dxy_hi)) {
+                        const double *zr = Xh + z * dp;
+                        const double d2xz = nrx + nrmh[z] - 2.0 * dot_lds(xs, zr, dp);
+                        ndist += 1;
+                        if (d2xz < d2) {
+                            const double d2yz = nry + nrmh[z] - 2.0 * dot_lds(ys, zr, dp);
+                            ndist += 1;
+                            wit = d2yz < d2;
+                        }
+                        ++ntests;
+                    }
+                    if (__ballot(wit)) { dead = true; break; }
+                }
+            }
+        }
+        if (lane == 0) alive[p] = dead ? 0 : 1;
+    }
+    ntests = wave_sum(ntests);
+    ndist = wave_sum(ndist);
+    if (lane == 0) {
+        atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_LUNE], (unsigned long long)ntests);
+        atomicAdd(&counters[C_DIST], (unsigned long long)ndist);
+    }
+}
+
+// Lune test against every point (no pivot layer).  One wave per pair.
+__global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t *__restrict__ px,
+                                                  const int32_t *__restrict__ py, const double *__restrict__ pd2,
+                                                  int64_t n, int dp, const double *__restrict__ X,
+                                                  const double *__restrict__ nrm, uint8_t *__restrict__ alive,
+                                                  unsigned long long *counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    uint32_t ntests = 0;
+    for (int64_t p = wave0; p < npairs; p += nwaves) {
+        const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
+        const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
+        const double d2 = pd2[p];
+        const double *xs = X + x * dp;
+        const double *ys = X + y * dp;
+        const double nrx = nrm[x], nry = nrm[y];
+        bool dead = false;
+        for (int64_t zb = 0; zb < n; zb += 64) {
+            const int64_t z = zb + lane;
+            bool wit = false;
+            if (z < n) {
+                const double *zr = X + z * dp;
+                const double d2xz = nrx + nrm[z] - 2.0 * dot_lds(xs, zr, dp);
+                const double d2yz = nry + nrm[z] - 2.0 * dot_lds(ys, zr, dp);
+                wit = d2xz < d2 && d2yz < d2;
+                ++ntests;
+            }
+            if (__ballot(wit)) { dead = true; break; }
+        }
+        if (lane == 0) alive[p] = dead ? 0 : 1;
+    }
+    ntests = wave_sum(ntests);
+    if (lane == 0) {
+        atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_LUNE], (unsigned long long)ntests);
+        atomicAdd(&counters[C_DIST], 2ull * ntests);
+    }
+}
+
+}  // namespace
+
+void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t *pknn) {
+    if (m == 0) return;
+    k_pivot_knn<<<(unsigned)m, 64, 0, s>>>(m, dpp2, pknn);
+    GRNG_LAUNCHED();
+}
+
+void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
+                       uint64_t *tv) {
+    if (ntiles == 0) return;
+    k_tile_vmask<<<(unsigned)div_up(ntiles * words, 256), 256, 0, s>>>(ntiles, tiles, v_rows, words, tv);
+    GRNG_LAUNCHED();
+}
+
+void launch_tile_pairs(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *tv, int32_t words,
+                       const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
+    if (ntiles == 0) return;
+    k_tile_pairs<<<(unsigned)ntiles, 64, 0, s>>>(ntiles, tiles, tv, words, off, cnt, oT, oU);
+    GRNG_LAUNCHED();
+}
+
+void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const int32_t *tiles,
+                        int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
+                        const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
+                        const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
+                        uint64_t *dmax_bits, uint64_t *counters) {
+    if (ntp == 0) return;
+    require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the pair kernel");
+    require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
+    const int ld = dp + 1;
+    const size_t lds = sizeof(double) * (size_t)(2 * kTile * ld + kPiv * ld + 2 * kTile + kPiv +
+                                                 2 * kTile * (kPiv + 1) + 2 * kTile + kQueue) +
+                       sizeof(uint32_t) * (kQueue + 2);
+    if (lds > 64 * 1024)
+        GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+    const int64_t grid = ntp < 65536 ? ntp : 65536;
+    k_pairs_tiled<<<(unsigned)grid, 256, lds, s>>>(ntp, tpT, tpU, tiles, dp, Xh, nrmh, par_off, par_idx, v_rows,
+                                                   g_cols, words, nw, pknn, K, Xp, nrmp, out,
+                                                   (unsigned long long *)dmax_bits, (unsigned long long *)counters);
+    GRNG_LAUNCHED();
+}
+
+void launch_pairs_all(hipStream_t s, int64_t n, int dp, const double *X, const double *nrm, PairList out,
+                      uint64_t *dmax_bits, uint64_t *counters) {
+    if (n < 2) return;
+    require(n <= 65535, GRNG_EINVAL, "brute-force pair enumeration limited to 65535 points");
+    dim3 g((unsigned)div_up(n, 256), (unsigned)n);
+    k_pairs_all<<<g, 256, 0, s>>>(n, dp, X, nrm, out, dmax_bits, (unsigned long long *)counters);
+    GRNG_LAUNCHED();
+}
+
+void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
+                            const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
+                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x) {
+    if (n == 0) return;
+    int32_t mp = 64;
+    while (mp < m) mp <<= 1;
+    const size_t lds = (size_t)mp * (sizeof(double) + sizeof(int32_t));
+    require(lds <= 160 * 1024, GRNG_EINVAL, "pivot layer too large for the witness-cell pass");
+    if (rel_off == nullptr) {
+        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, mp, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
+                                                       nullptr, nullptr, 0);
+    } else {
+        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, mp, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt,
+                                                       rel_grp, rel_d2x, 1);
+    }
+    GRNG_LAUNCHED();
+}
+
+void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
+                        int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
+                        const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
+                        const int32_t *rel_grp, const double *rel_d2x, uint8_t *alive, uint64_t *counters) {
+    if (npairs == 0) return;
+    require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
+    const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
+    k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xh, nrmh, dhome, grp_off, dvor,
+                                                              Xp, nrmp, rel_off, rel_grp, rel_d2x, alive,
+                                                              (unsigned long long *)counters);
+    GRNG_LAUNCHED();
+}
+
+void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
+                     int64_t n, int dp, const double *X, const double *nrm, uint8_t *alive, uint64_t *counters) {
+    if (npairs == 0) return;
+    require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
+    const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
+    k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, X, nrm, alive,
+                                                           (unsigned long long *)counters);
+    GRNG_LAUNCHED();
+}
+
+}  // namespace grng

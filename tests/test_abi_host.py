@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every declared symbol; host-side validation (CPU only).
+
+None of these tests launches device work: each call below returns from the
+library's argument checks before its first HIP call.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grng.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2208_10022_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_2208_10022_amd import build
+        build.build()
+    return P
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(grng_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declarations_match_binding(L):
+    assert declared_functions() == sorted(L.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = L.lib()
+    for f in declared_functions():
+        assert getattr(lib, f) is not None
+
+
+def test_struct_layouts_match_header(L, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "grng.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu\\n", sizeof(grng_options), sizeof(grng_stats),'
+                   ' offsetof(grng_options, reserved), offsetof(grng_stats, lune_bytes)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    a, b, c, d = map(int, subprocess.check_output([str(exe)]).split())
+    assert a == C.sizeof(L.Options) and b == C.sizeof(L.Stats)
+    assert c == L.Options.reserved.offset and d == L.Stats.lune_bytes.offset
+
+
+def test_host_validation_without_device(L):
+    lib = L.lib()
+    assert lib.grng_abi_version() == 1
+    h = C.c_void_p()
+    opt = L.Options(grid_exp=10)
+    assert lib.grng_create(None, C.c_void_p(8), 10, 2, None, C.byref(opt)) == -1
+    assert lib.grng_create(C.byref(h), None, 10, 2, None, C.byref(opt)) == -1
+    assert "points" in L.last_error()
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 0, 2, None, C.byref(opt)) == -1
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 0, None, C.byref(opt)) == -1
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, None) == -1
+    bad = L.Options(grid_exp=61)
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, C.byref(bad)) == -1
+    bad = L.Options(grid_exp=3, precision=7)
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, C.byref(bad)) == -1
+    bad = L.Options(grid_exp=3)
+    bad.reserved[2] = 1
+    assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, C.byref(bad)) == -1
+    ne = C.c_int64(0)
+    assert lib.grng_get_edges(None, -1, None, 0, C.byref(ne)) == -1
+    assert lib.grng_build_rng(None) == -1
+    assert lib.grng_build_grng_layer(None, 0, None, None, 1) == -1
+    assert lib.grng_insert_batch(None, None, 1) == -1
+    assert lib.grng_get_stats(None, None) == -1
+    lib.grng_destroy(None)

@@ -1,0 +1,182 @@
+"""GPU parity of the exact RNG / GRNG build against the oracle (needs an MI355X).
+
+Edge sets must be identical (integer output: bit-exact).  Every case runs
+through the C ABI via the Python binding.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, native, rng
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    import paper_2208_10022_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    P.lib()
+    return P
+
+
+def golden_edges(name):
+    rows = [ln.split() for ln in open(os.path.join(HERE, "golden", name)) if ln.strip() and not ln.startswith("#")]
+    return np.array(rows, dtype=np.int64).reshape(-1, 2)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_edges(G, X, q, layers=(), **kw):
+    idx = G.Index(to_dev(X), grid_exp=q, **kw)
+    for l, (pid, rad) in enumerate(layers):
+        idx.build_grng_layer(l, to_dev(np.asarray(pid, np.int32)), to_dev(np.asarray(rad, np.float32)))
+    idx.build_rng()
+    E = idx.edges().cpu().numpy().astype(np.int64)
+    lay = [idx.edges(l).cpu().numpy().astype(np.int64) for l in range(len(layers))]
+    st = idx.stats()
+    idx.close()
+    return E, lay, st
+
+
+def test_uniform2d_1000_bruteforce_matches_golden(G):
+    say("uniform2d n=1000 brute force")
+    W = synth.uniform2d(1000)
+    E, _, st = gpu_edges(G, W.X, W.q)
+    want = golden_edges("uniform2d_n1000_rng_edges.txt")
+    assert np.array_equal(E, want)
+    assert st["n_edges"] == len(want)
+
+
+def test_uniform2d_1000_guided_matches_golden(G):
+    say("uniform2d n=1000 with a 40-pivot layer")
+    W = synth.uniform2d(1000)
+    g = np.random.default_rng(3)
+    pid = np.sort(g.choice(1000, 40, replace=False)).astype(np.int32)
+    rad = synth.knn_radii(W.X, W.q, pid, 25)
+    E, lay, _ = gpu_edges(G, W.X, W.q, [(pid, rad)])
+    assert np.array_equal(E, golden_edges("uniform2d_n1000_rng_edges.txt"))
+    assert np.array_equal(lay[0], native.grng_edges(W.X[pid], rad, W.q))
+
+
+def test_clustered_3000_d16_matches_golden(G):
+    say("clustered n=3000 d=16 m=60")
+    W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
+    L = W.layers[0]
+    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    assert np.array_equal(E, golden_edges("clustered_n3000_d16_rng_edges.txt"))
+    assert np.array_equal(lay[0], golden_edges("clustered_n3000_d16_m60_grng_edges.txt"))
+    assert st["candidate_pairs"] > 0
+
+
+@pytest.mark.parametrize("n,d,m,clusters,seed", [
+    (1037, 2, 30, 4, 0), (2111, 3, 70, 6, 1), (1500, 5, 16, 3, 2), (777, 16, 100, 5, 3),
+    (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7)])
+def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed):
+    say("ragged", n, d, m, clusters, seed)
+    W = synth.clustered(n=n, d=d, clusters=clusters, m=m, knn=min(30, n - 1), sub=seed)
+    L = W.layers[0]
+    want = native.rng_edges(W.X, W.q)
+    E, lay, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    assert np.array_equal(E, want)
+    assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
+    Eb, _, _ = gpu_edges(G, W.X, W.q)
+    assert np.array_equal(Eb, want)
+
+
+def test_stage4_pivot_count_does_not_change_edges(G):
+    say("stage4 pivot count sweep")
+    W = synth.clustered(n=2500, d=8, clusters=6, m=80, knn=30, sub=11)
+    L = W.layers[0]
+    want = native.rng_edges(W.X, W.q)
+    for k in (1, 4, 9, 16):
+        E, _, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], stage4_pivots=k)
+        assert np.array_equal(E, want), k
+
+
+def test_degenerate_inputs(G):
+    say("degenerate inputs")
+    # one point, two points, all identical, 1-D path, boundary tie, collinear.
+    cases = [np.zeros((1, 3), np.float32), np.array([[0, 0], [1, 2]], np.float32),
+             np.zeros((7, 4), np.float32),
+             np.array([[5], [1], [9], [3], [7]], np.float32),
+             np.array([[0, 0], [5, 0], [3, 4]], np.float32),
+             np.array([[0, 0], [1, 0], [2, 0]], np.float32),
+             np.array([[0], [0], [1]], np.float32)]
+    for X in cases:
+        want = rng.rng_edges(exact.to_grid(X, 0))
+        E, _, _ = gpu_edges(G, X, 0)
+        assert np.array_equal(E, want), X
+        if len(X) >= 3:   # same with every point a zero-radius pivot (GRNG = RNG, Section 2)
+            pid = np.arange(len(X), dtype=np.int32)
+            E2, lay, _ = gpu_edges(G, X, 0, [(pid, np.zeros(len(X), np.float32))])
+            assert np.array_equal(E2, want)
+            assert np.array_equal(lay[0], want)
+
+
+def test_grid_lattice_with_pivots(G):
+    say("lattice 20x20 with pivots")
+    K = np.array([(i, j) for i in range(20) for j in range(20)], np.float32)
+    pid = np.arange(0, 400, 7, dtype=np.int32)
+    E, lay, _ = gpu_edges(G, K, 0, [(pid, np.full(len(pid), 2.0, np.float32))])
+    assert len(E) == 2 * 20 * 19
+    assert np.array_equal(E, rng.rng_edges(exact.to_grid(K, 0)))
+
+
+def test_error_statuses(G):
+    say("error statuses")
+    import torch
+    X = to_dev(np.array([[0.5, 0.25], [0.1, 0.3]], np.float32))
+    with pytest.raises(G.GrngError) as e:
+        G.Index(X, grid_exp=1)           # 0.1 is not a multiple of 2^-1
+    assert e.value.status == -4
+    Xn = to_dev(np.array([[0.0, np.nan]], np.float32))
+    with pytest.raises(G.GrngError) as e:
+        G.Index(Xn, grid_exp=4)
+    assert e.value.status == -4
+    W = synth.uniform2d(200)
+    idx = G.Index(to_dev(W.X), grid_exp=W.q)
+    with pytest.raises(G.GrngError) as e:
+        idx.build_grng_layer(1, to_dev(np.array([1, 2], np.int32)), to_dev(np.array([0.1, 0.1], np.float32)))
+    assert e.value.status == -6
+    with pytest.raises(G.GrngError) as e:
+        idx.build_grng_layer(0, to_dev(np.array([2, 1], np.int32)), to_dev(np.array([0.0, 0.0], np.float32)))
+    assert e.value.status == -1
+    with pytest.raises(G.GrngError) as e:
+        idx.edges()
+    assert e.value.status == -6
+    idx.build_rng()
+    assert idx.num_edges() == len(rng.rng_edges(exact.to_grid(W.X, W.q)))
+    idx.close()
+    del torch
+
+
+def test_clustered_full_size_sampled_rows(G):
+    """The 100k x 16-D, 32-cluster, 1,000-pivot workload in the bench's launch
+    configuration; sampled rows compared with the oracle one by one."""
+    say("clustered full size n=100000 d=16 m=1000")
+    W = synth.clustered()
+    L = W.layers[0]
+    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    assert np.all(E[:, 0] < E[:, 1])
+    assert np.all(np.diff(E[:, 0]) >= 0)
+    g = np.random.default_rng(99)
+    xs = g.choice(W.n, 48, replace=False)
+    rows = native.rng_rows(W.X, W.q, xs)
+    for x, row in zip(xs, rows):
+        got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
+        assert np.array_equal(got, row), x
+    # GRNG of the full 1,000-pivot layer in full.
+    assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
+    say("stats", st)
