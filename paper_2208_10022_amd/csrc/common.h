@@ -92,7 +92,6 @@ struct PointState {
     DevBuf dvor;               // double [m] upper bound of the group radius (max d(x, p_c))
     DevBuf par_off;            // int64 [n+1] parents CSR
     DevBuf par_idx;            // int32 [nnz]
-    DevBuf knn;                // int32 [n*K] nearest pivots (Stage IV witnesses)
     DevBuf g_rows;             // uint64 [n*words] virtual-pivot GRNG(x) (domain radii)
     DevBuf v_rows;             // uint64 [n*words] virtual-pivot GRNG of x over Voronoi groups
     DevBuf g_cols;             // uint64 [m*nw] transposed g_rows (nw = ceil(n/64))
@@ -168,9 +167,9 @@ void launch_point_pass1(hipStream_t s, int64_t n, int64_t m, const double *dxp, 
 void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const double *d2home,
                          uint64_t *d2vor_bits, int32_t *gcount);
 void launch_point_pass2(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
-                        const double *rad, const double *dpp, const uint64_t *layer_bits, int32_t words,
-                        const double *dvor, const int32_t *gcount, const int64_t *par_off, int32_t *par_idx,
-                        int32_t K, int32_t *knn, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
+                        const double *rad, const double *dpp, const double *dvor, const int32_t *gcount,
+                        const uint64_t *layer_bits, int32_t words, const int64_t *par_off, int32_t *par_idx,
+                        float *bd, float *bv, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
 
 // k_rng.hip
 struct PairList {

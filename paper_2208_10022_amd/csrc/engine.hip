@@ -380,14 +380,17 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
     ps.nrmh.alloc(sizeof(double) * (size_t)n);
     launch_gather_rows(s, idx->X.as<double>(), ps.perm.as<int32_t>(), n, dp, ps.Xh.as<double>());
     launch_gather_f64(s, idx->nrm.as<double>(), ps.perm.as<int32_t>(), n, ps.nrmh.as<double>());
-    // Parents, nearest pivots, virtual-pivot GRNG bitsets (Propositions 1-2).
+    // Parents and virtual-pivot GRNG bitsets (Propositions 1-2) as a tiled
+    // (min, max) product of point-pivot and shifted pivot-pivot distances.
+    DevBuf bd, bv;
+    bd.alloc(4 * (size_t)(m * m));
+    bv.alloc(4 * (size_t)(m * m));
     ps.par_idx.alloc(4 * (size_t)std::max<int64_t>(par_off[n], 1));
-    ps.knn.alloc(4 * (size_t)(n * K));
     ps.g_rows.alloc(8 * (size_t)(n * words));
     ps.v_rows.alloc(8 * (size_t)(n * words));
     launch_point_pass2(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), L.rad.as<double>(), L.dpp.as<double>(),
-                       L.bits.as<uint64_t>(), words, ps.dvor.as<double>(), gcount.as<int32_t>(),
-                       ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(), K, ps.knn.as<int32_t>(),
+                       ps.dvor.as<double>(), gcount.as<int32_t>(), L.bits.as<uint64_t>(), words,
+                       ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(), bd.as<float>(), bv.as<float>(),
                        ps.g_rows.as<uint64_t>(), ps.v_rows.as<uint64_t>(), ctr);
     const int64_t nw = div_up(n, 64);
     ps.g_cols.alloc(8 * (size_t)(m * nw));
@@ -426,7 +429,7 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
     Pairs P;
     DevBuf dmax;
     dmax.alloc(8 * (size_t)n);
-    int64_t cap = std::max<int64_t>(1 << 20, 16 * n);
+    int64_t cap = std::max<int64_t>(1 << 22, 64 * n);
     int64_t np = 0;
     std::vector<uint64_t> snapshot;
     d2h(snapshot, idx->counters.p, C_NUM, s);

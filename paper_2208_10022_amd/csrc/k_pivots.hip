@@ -10,7 +10,7 @@
 //    screen cannot separate the two sides (the only inexact step is sqrt).
 //  * Per-point passes for the exemplar RNG: domain parents (Section 1, pivot
 //    domain equation, exact), nearest pivot ("home" cell used to group
-//    witnesses), nearest pivots for Stage IV, and two virtual-pivot GRNG
+//    witnesses), and two virtual-pivot GRNG
 //    bitsets of each point (Section 2, Proposition 1 with the point as a zero
 //    radius pivot): one over the pivot domains (radii r) and one over the
 //    home cells (radius = cell radius, which covers every point, orphans
@@ -76,12 +76,11 @@ __global__ __launch_bounds__(256) void k_grng_layer(int64_t m, const double *dpp
         const int64_t k = s < nfirst ? wfirst[s] : s - nfirst;
         if (!linked || k == i || k == j) continue;
         ++tests;
-        const double dki = dpp[k * m + i];
-        const double dkj = dpp[k * m + j];
-        // Cheap exact pre-test: dk + c < dij needs dk < dij.
-        if (dki >= dij || dkj >= dij) continue;
-        if (side_lt(dki, c1, dij, dpp2[k * m + i], c1i, d2ij, s2, rechecks) &&
-            side_lt(dkj, c2, dij, dpp2[k * m + j], c2i, d2ij, s2, rechecks))
+        // Cheap exact pre-test on squared distances: dk + c < dij needs dk^2 < dij^2.
+        const double d2ki = dpp2[k * m + i], d2kj = dpp2[k * m + j];
+        if (d2ki >= d2ij || d2kj >= d2ij) continue;
+        if (side_lt(dpp[k * m + i], c1, dij, d2ki, c1i, d2ij, s2, rechecks) &&
+            side_lt(dpp[k * m + j], c2, dij, d2kj, c2i, d2ij, s2, rechecks))
             linked = false;
     }
     const uint64_t word = __ballot(linked);
@@ -152,8 +151,6 @@ __global__ void k_guided_candidates(int64_t mf, const uint64_t *pbits, int32_t c
     if (ok) {
         for (int32_t w = 0; w < cwords && ok; ++w) {
             uint64_t allowed = ~0ull;   // coarse pivots b allowed for the parents of j
-            uint64_t pi = pbits[i * cwords + 0];
-            (void)pi;
             // allowed_w = AND over parents a of i of (G_c[a] | {a}) restricted to word w
             for (int32_t wa = 0; wa < cwords; ++wa) {
                 uint64_t pw = pbits[i * cwords + wa];
@@ -209,105 +206,151 @@ __global__ void k_group_radius(int64_t n, const int32_t *home, const double *d2h
     atomicAdd(&gcount[home[x]], 1);
 }
 
-// Upper bound of sqrt for conservative pruning bounds.
-__device__ inline double sqrt_up(double v) { return sqrt(v) * (1.0 + 1e-15); }
-
-// Wave per point in home order.  LDS: sorted distances to pivots and indices.
-__global__ __launch_bounds__(64) void k_point_pass2(int64_t n, int64_t m, int32_t mpow2, const int32_t *perm,
-                                                    const double *dxp, const double *rad, const double *dpp,
-                                                    const uint64_t *layer_bits, int32_t words,
-                                                    const double *dvor, const int32_t *gcount,
-                                                    const int64_t *par_off, int32_t *par_idx, int32_t K,
-                                                    int32_t *knn, uint64_t *g_rows, uint64_t *v_rows,
-                                                    unsigned long long *counters) {
-    extern __shared__ unsigned char smem[];
-    double *key = (double *)smem;
-    int32_t *kid = (int32_t *)(key + mpow2);
-    const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
+// Exact domain parents of each point (Section 1, pivot domain equation), in
+// pivot order; one wave per point in home order.
+__global__ __launch_bounds__(256) void k_parents(int64_t n, int64_t m, const int32_t *__restrict__ perm,
+                                                 const double *__restrict__ dxp, const double *__restrict__ rad,
+                                                 const int64_t *__restrict__ par_off, int32_t *__restrict__ par_idx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    const int64_t x = perm[i];
-    const double *row = dxp + x * m;
-    // Parents (exact) in pivot order, and the distance table.
+    const double *row = dxp + (int64_t)perm[i] * m;
     int64_t pw = par_off[i];
-    for (int64_t k0 = 0; k0 < mpow2; k0 += 64) {
+    for (int64_t k0 = 0; k0 < m; k0 += 64) {
         const int64_t k = k0 + lane;
         bool par = false;
         if (k < m) {
-            const double d2 = row[k];
             const double r = rad[k];
-            par = d2 <= r * r;
-            key[k] = sqrt(d2);
-            kid[k] = (int32_t)k;
-        } else if (k < mpow2) {
-            key[k] = INFINITY;
-            kid[k] = (int32_t)k;
+            par = row[k] <= r * r;   // exact: r*r is exact on the grid
         }
         const uint64_t pm = __ballot(par);
         if (par) par_idx[pw + __popcll(pm & ((1ull << lane) - 1ull))] = (int32_t)k;
         pw += __popcll(pm);
     }
-    __syncthreads();
-    // Bitonic sort of (distance, index) ascending.
-    for (int32_t size = 2; size <= mpow2; size <<= 1) {
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t t = lane; t < (mpow2 >> 1); t += 64) {
-                const int32_t lo = 2 * t - (t & (stride - 1));
-                const int32_t hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const double a = key[lo], b = key[hi];
-                const int32_t ia = kid[lo], ib = kid[hi];
-                const bool gt = a > b || (a == b && ia > ib);
-                if (gt == up) {
-                    key[lo] = b; key[hi] = a;
-                    kid[lo] = ib; kid[hi] = ia;
-                }
+}
+
+// Shifted pivot distances for the virtual-pivot test, rounded up:
+// bd[k][j] = d(p_j, p_k) + r_j and bv[k][j] = d(p_j, p_k) + cellradius_j.
+__global__ void k_shifted_pivot_dists(int64_t m, const double *dpp, const double *rad, const double *dvor,
+                                      float *bd, float *bv) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= m * m) return;
+    const int64_t j = e % m;
+    const double d = dpp[e] * (1.0 + 1e-15);
+    bd[e] = __double2float_ru(d + rad[j]);
+    bv[e] = __double2float_ru(d + dvor[j]);
+}
+
+// Virtual-pivot GRNG bitsets of every point as a (min, max) matrix product.
+// For point x and pivot j with radius rad_j (Section 2, Proposition 1 with x
+// as a zero-radius pivot), j is dropped iff some pivot k has
+//     d(x,p_k) + rad_j < d(x,p_j)  and  d(p_j,p_k) + 2 rad_j < d(x,p_j),
+// i.e. iff  C[x][j] + rad_j < d(x,p_j)  with
+//     C[x][j] = min_k max(d(x,p_k), d(p_j,p_k) + rad_j).
+// Each workgroup computes a 64-point x 64-pivot tile of C for both radius
+// choices (domain radius and home-cell radius), 4 x 4 entries per thread,
+// with 32-pivot slices of both operands staged in LDS.  Operands are float32
+// rounded up, so C is an upper bound and dropping j stays sound (a dropped
+// pivot is dropped by the exact test too).
+constexpr int kVT_X = 64, kVT_J = 64, kVT_K = 32;
+__global__ __launch_bounds__(256) void k_vgrng_tiles(
+    int64_t n, int64_t m, const int32_t *__restrict__ perm, const double *__restrict__ dxp,
+    const float *__restrict__ bd, const float *__restrict__ bv, const double *__restrict__ rad,
+    const double *__restrict__ dvor, const int32_t *__restrict__ gcount, const int64_t *__restrict__ par_off,
+    const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ layer_bits, int32_t words,
+    uint64_t *__restrict__ g_rows, uint64_t *__restrict__ v_rows, unsigned long long *counters) {
+    __shared__ float sA[kVT_X][kVT_K + 1];
+    __shared__ float sD[kVT_K][kVT_J];
+    __shared__ float sV[kVT_K][kVT_J];
+    __shared__ uint64_t sCand[kVT_X];
+    __shared__ unsigned long long sG[kVT_X], sVb[kVT_X];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int64_t x0 = blockIdx.x * (int64_t)kVT_X;
+    const int64_t j0 = blockIdx.y * (int64_t)kVT_J;
+    const int32_t wj = (int32_t)(j0 >> 6);
+    if (tid < kVT_X) {
+        // Theorem 1 candidates: pivots linked to (or equal to) every parent of x.
+        const int64_t i = x0 + tid;
+        uint64_t c = 0;
+        if (i < n) {
+            c = ~0ull;
+            for (int64_t t = par_off[i]; t < par_off[i + 1]; ++t) {
+                const int32_t p = par_idx[t];
+                uint64_t row = layer_bits[(int64_t)p * words + wj];
+                if ((p >> 6) == wj) row |= 1ull << (p & 63);
+                c &= row;
             }
-            __syncthreads();
+        }
+        sCand[tid] = c;
+        sG[tid] = 0;
+        sVb[tid] = 0;
+    }
+    float cD[4][4], cV[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) cD[r][c] = cV[r][c] = INFINITY;
+    for (int64_t k0 = 0; k0 < m; k0 += kVT_K) {
+        __syncthreads();
+        for (int e = tid; e < kVT_X * kVT_K; e += 256) {
+            const int r = e / kVT_K, kk = e % kVT_K;
+            const int64_t i = x0 + r, k = k0 + kk;
+            float v = INFINITY;
+            if (i < n && k < m) v = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + k]) * (1.0 + 1e-15));
+            sA[r][kk] = v;
+        }
+        for (int e = tid; e < kVT_K * kVT_J; e += 256) {
+            const int kk = e / kVT_J, jj = e % kVT_J;
+            const int64_t k = k0 + kk, j = j0 + jj;
+            const bool ok = k < m && j < m;
+            sD[kk][jj] = ok ? bd[k * m + j] : INFINITY;
+            sV[kk][jj] = ok ? bv[k * m + j] : INFINITY;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kVT_K; ++kk) {
+            float a[4], d[4], v[4];
+            for (int r = 0; r < 4; ++r) a[r] = sA[ty + 16 * r][kk];
+            for (int c = 0; c < 4; ++c) {
+                d[c] = sD[kk][tx + 16 * c];
+                v[c] = sV[kk][tx + 16 * c];
+            }
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    cD[r][c] = fminf(cD[r][c], fmaxf(a[r], d[c]));
+                    cV[r][c] = fminf(cV[r][c], fmaxf(a[r], v[c]));
+                }
         }
     }
-    for (int32_t t = lane; t < K; t += 64) knn[i * K + t] = t < m ? kid[t] : kid[0];
-    const int64_t p0 = par_off[i], p1 = par_off[i + 1];
-    uint32_t tests = 0;
-    for (int32_t w = 0; w < words; ++w) {
-        const int64_t j = (int64_t)w * 64 + lane;
-        const bool valid = j < m;
-        // Candidates for GRNG(x) (Theorem 1): linked to, or equal to, every parent.
-        bool candD = valid;
-        for (int64_t t = p0; t < p1 && candD; ++t) {
-            const int32_t p = par_idx[t];
-            candD = (p == j) || ((layer_bits[(int64_t)p * words + w] >> lane) & 1ull);
-        }
-        bool candV = valid && gcount[j] > 0;
-        const double dj = valid ? sqrt(row[j]) : 0.0;
-        const double rj = valid ? rad[j] : 0.0;
-        const double vj = valid ? dvor[j] : 0.0;
-        const double mj = 1e-12 * (dj + 3.0 * fmax(rj, vj)) + 1e-300;
-        // Prune when some pivot k lies in the G-lune of (x, 0) and (p_j, radius):
-        //   d(x,k) + rad < d(x,j)  and  d(j,k) + 2 rad < d(x,j), with margin.
-        const double tD = dj - rj - mj, tV = dj - vj - mj;
-        bool liveD = candD && tD > 0.0, liveV = candV && tV > 0.0;
-        bool keepD = candD, keepV = candV;
-        for (int32_t s = 0; s < m; ++s) {
-            const double dk = key[s];
-            liveD = liveD && keepD && dk < tD;
-            liveV = liveV && keepV && dk < tV;
-            if (!__ballot(liveD || liveV)) break;
-            if (!(liveD || liveV)) continue;
-            const int32_t k = kid[s];
-            const double djk = dpp[(int64_t)k * m + j];
-            ++tests;
-            if (liveD && djk + 2.0 * rj < dj - mj) keepD = false;
-            if (liveV && djk + 2.0 * vj < dj - mj) keepV = false;
-        }
-        const uint64_t gd = __ballot(keepD), gv = __ballot(keepV);
-        if (lane == 0) {
-            g_rows[i * words + w] = gd;
-            v_rows[i * words + w] = gv;
+    // Epilogue: keep bits.
+    for (int r = 0; r < 4; ++r) {
+        const int xr = ty + 16 * r;
+        const int64_t i = x0 + xr;
+        if (i >= n) continue;
+        const double *row = dxp + (int64_t)perm[i] * m;
+        for (int c = 0; c < 4; ++c) {
+            const int jc = tx + 16 * c;
+            const int64_t j = j0 + jc;
+            if (j >= m) continue;
+            const double dj = sqrt(row[j]) * (1.0 - 1e-15);
+            const double rj = rad[j], vj = dvor[j];
+            const double mj = 1e-6 * (dj + 3.0 * fmax(rj, vj)) + 1e-300;
+            const bool candD = (sCand[xr] >> jc) & 1ull;
+            const bool candV = gcount[j] > 0;
+            const bool keepD = candD && !((double)cD[r][c] + rj < dj - mj);
+            const bool keepV = candV && !((double)cV[r][c] + vj < dj - mj);
+            if (keepD) atomicOr(&sG[xr], 1ull << jc);
+            if (keepV) atomicOr(&sVb[xr], 1ull << jc);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) tests += __shfl_xor(tests, o, kWave);
-    if (lane == 0) atomicAdd(&counters[C_WTEST], (unsigned long long)tests);
+    __syncthreads();
+    if (tid < kVT_X && x0 + tid < n) {
+        g_rows[(x0 + tid) * words + wj] = sG[tid];
+        v_rows[(x0 + tid) * words + wj] = sVb[tid];
+    }
+    if (tid == 0) {
+        const int64_t rows = (n - x0) < kVT_X ? (n - x0) : kVT_X;
+        const int64_t cols = (m - j0) < kVT_J ? (m - j0) : kVT_J;
+        atomicAdd(&counters[C_WTEST], (unsigned long long)(2 * rows * cols * m));
+    }
 }
 
 }  // namespace
@@ -361,17 +404,17 @@ void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const do
 }
 
 void launch_point_pass2(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
-                        const double *rad, const double *dpp, const uint64_t *layer_bits, int32_t words,
-                        const double *dvor, const int32_t *gcount, const int64_t *par_off, int32_t *par_idx,
-                        int32_t K, int32_t *knn, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
+                        const double *rad, const double *dpp, const double *dvor, const int32_t *gcount,
+                        const uint64_t *layer_bits, int32_t words, const int64_t *par_off, int32_t *par_idx,
+                        float *bd, float *bv, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
     if (n == 0) return;
-    int32_t mp = 64;
-    while (mp < m) mp <<= 1;
-    const size_t lds = (size_t)mp * (sizeof(double) + sizeof(int32_t));
-    require(lds <= 160 * 1024, GRNG_EINVAL, "pivot layer too large for the per-point pass");
-    k_point_pass2<<<(unsigned)n, 64, lds, s>>>(n, m, mp, perm, dxp, rad, dpp, layer_bits, words, dvor, gcount,
-                                               par_off, par_idx, K, knn, g_rows, v_rows,
-                                               (unsigned long long *)counters);
+    k_parents<<<(unsigned)div_up(n, 4), 256, 0, s>>>(n, m, perm, dxp, rad, par_off, par_idx);
+    GRNG_LAUNCHED();
+    k_shifted_pivot_dists<<<(unsigned)div_up(m * m, 256), 256, 0, s>>>(m, dpp, rad, dvor, bd, bv);
+    GRNG_LAUNCHED();
+    dim3 g((unsigned)div_up(n, kVT_X), (unsigned)div_up(m, kVT_J));
+    k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits, words,
+                                    g_rows, v_rows, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 

@@ -180,3 +180,38 @@ def test_clustered_full_size_sampled_rows(G):
     # GRNG of the full 1,000-pivot layer in full.
     assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
     say("stats", st)
+
+
+def test_grng_layer_exact_ties_use_the_integer_predicate(G):
+    """G-lune ties at large coordinates (Definition 1 uses a strict "<"):
+    k = (3F, 4F) is exactly on the generalized-lune boundary of i = (0, 0),
+    j = (6F, 8F) with r_i = 2F, r_j = F, so (i, j) stays linked; moving k by
+    one grid unit inward breaks the link."""
+    say("grng exact ties")
+    F = 2 ** 20
+    from oracle import grng as ogr
+    for k in ([3 * F, 4 * F], [3 * F, 4 * F - 1], [3 * F + 1, 4 * F]):
+        P = np.array([[0, 0], [6 * F, 8 * F], k, [12 * F, 0], [0, 9 * F]], np.float32)
+        R = np.array([2 * F, F, 0, F, 3], np.float32)
+        want = ogr.grng_edges(exact.to_grid(P, 0), R.astype(np.int64))
+        idx = G.Index(to_dev(P), grid_exp=0)
+        idx.build_grng_layer(0, to_dev(np.arange(5, dtype=np.int32)), to_dev(R))
+        got = idx.edges(0).cpu().numpy().astype(np.int64)
+        st = idx.stats()
+        idx.close()
+        assert np.array_equal(got, want), k
+        if k == [3 * F, 4 * F]:
+            assert st["rechecks"] > 0
+
+
+@pytest.mark.parametrize("n,d,mf,mc,seed", [(6000, 32, 240, 12, 0), (3000, 8, 150, 20, 1)])
+def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed):
+    """Coarse layer -> guided fine layer (Theorem 2) -> RNG, on the
+    8-dimensional-subspace workload family at reduced size."""
+    say("three layers", n, d, mf, mc, seed)
+    W = synth.subspace3(n=n, d=d, m_fine=mf, m_coarse=mc, sub=seed)
+    (Lc, Lf) = W.layers
+    E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)])
+    assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
+    assert np.array_equal(lay[1], native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q))
+    assert np.array_equal(E, native.rng_edges(W.X, W.q))
