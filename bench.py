@@ -20,8 +20,38 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Published MI355X peaks, and the VALU issue peak derived from unit counts:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s (one
+# float32 min or max per lane per cycle; packed FP32 is not used).
 MI355X_HBM_GBS = 8000.0
 MI355X_FP64_TFLOPS = 78.6
+MI355X_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def roofline(st: dict) -> dict:
+    """Roofline entry for the main kernel that took the longest in the last build.
+
+    virtual-pivot (min,max) kernel: ALU-bound, 2 VALU ops (one max, one min)
+        per (point, pivot j, pivot k) triple for each of the two radius choices:
+        algorithmic ops = 2 * vgrng_ops.
+    tiled pair kernel: MFMA f64 tiles, algorithmic flops = pairs_flops.
+    exhaustive lune kernel: witness rows streamed, algorithmic bytes =
+        (8 dp + 16) per witness test = lune_bytes.
+    """
+    kernels = {"vgrng": st["ms_vgrng"], "pairs": st["ms_pairs"], "lune": st["ms_lune"]}
+    k = max(kernels, key=kernels.get)
+    ms = kernels[k]
+    if k == "vgrng":
+        ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12
+        return {"kernel": "k_vgrng_tiles", "bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS,
+                "unit": "Tops/s (fp32 min/max)", "frac": ach / MI355X_VALU_TOPS, "traffic": None, "ms": ms}
+    if k == "pairs":
+        ach = st["pairs_flops"] / (ms / 1e3) / 1e12
+        return {"kernel": "k_pairs_tiled", "bound": "mfma", "achieved": ach, "peak": MI355X_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / MI355X_FP64_TFLOPS, "traffic": None, "ms": ms}
+    ach = st["lune_bytes"] / (ms / 1e3) / 1e9
+    return {"kernel": "k_lune_guided", "bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+            "frac": ach / MI355X_HBM_GBS, "traffic": None, "ms": ms}
 
 
 def parse():
@@ -32,6 +62,8 @@ def parse():
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
     return ap.parse_args()
 
 
@@ -68,6 +100,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration_mb:
+        src = torch.ones(args.copy_calibration_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration_mb, "copies": 3}))
+        return
 
     import synth
     import paper_2208_10022_amd as P
@@ -129,10 +170,16 @@ def main():
         "distance_computations": st["distance_computations"],
         "candidate_pairs": st["candidate_pairs"],
         "stage4_survivors": st["stage4_survivors"],
+        "exhaustive_pairs": st["exhaustive_pairs"],
+        "lune_tests": st["lune_tests"],
+        "tile_pairs": st["tile_pairs"],
         "orphans": st["orphans"],
         "ms_layer": st["ms_layers"],
         "ms_rng": st["ms_rng"],
+        "ms_vgrng": st["ms_vgrng"],
+        "ms_pairs": st["ms_pairs"],
         "ms_lune": st["ms_lune"],
+        "roofline": roofline(st),
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

@@ -91,20 +91,26 @@ typedef struct grng_stats {
     int64_t n_edges;              /* exemplar RNG edges (after build_rng / insert_batch) */
     int64_t n_layers;             /* pivot layers built */
     int64_t orphans;              /* points in no pivot domain of the finest layer */
+    int64_t tile_pairs;           /* 64-point tile pairs scanned for candidate pairs */
+    int64_t reserved_i[3];
     double distance_computations; /* squared distances produced (the paper's cost unit, Section 1) */
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
     double stage4_survivors;      /* pairs left after pivot witnesses (Stage IV) */
+    double exhaustive_pairs;      /* pairs left for the exhaustive scan after Stage V */
+    double lune_tests;            /* witness predicates evaluated by the exhaustive scan */
     double rechecks;              /* comparisons re-decided in float64 / exact integers */
     double ms_layers;             /* device time of the last layer build */
     double ms_rng;                /* device time of the last build_rng */
     double ms_insert;             /* device time of the last insert_batch */
     double ms_query;              /* device time of the last query_neighbors */
-    double ms_lune;               /* device time of the exhaustive lune kernel in the last build/insert */
-    double lune_bytes;            /* algorithmic bytes read by that kernel: (8*dp + 16) per witness test */
-    double exhaustive_pairs;      /* pairs left for the exhaustive scan after Stage V */
-    double lune_tests;            /* witness predicates evaluated by the exhaustive scan */
-    double reserved[3];
+    double ms_vgrng;              /* device time of the virtual-pivot (min,max) kernel in the last build */
+    double ms_pairs;              /* device time of the tiled candidate-pair kernel in the last build */
+    double ms_lune;               /* device time of the exhaustive lune kernel in the last build */
+    double vgrng_ops;             /* (min,max) pairs evaluated by the virtual-pivot kernel: 2 n m^2 */
+    double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair */
+    double lune_bytes;            /* algorithmic bytes read by the lune kernel: (8 dp + 16) per witness test */
+    double reserved[4];
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

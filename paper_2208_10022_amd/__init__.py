@@ -39,14 +39,17 @@ class Options(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_edges", C.c_int64), ("n_layers", C.c_int64), ("orphans", C.c_int64),
+                ("tile_pairs", C.c_int64), ("reserved_i", C.c_int64 * 3),
                 ("distance_computations", C.c_double), ("witness_tests", C.c_double),
-                ("candidate_pairs", C.c_double), ("stage4_survivors", C.c_double), ("rechecks", C.c_double),
+                ("candidate_pairs", C.c_double), ("stage4_survivors", C.c_double),
+                ("exhaustive_pairs", C.c_double), ("lune_tests", C.c_double), ("rechecks", C.c_double),
                 ("ms_layers", C.c_double), ("ms_rng", C.c_double), ("ms_insert", C.c_double),
-                ("ms_query", C.c_double), ("ms_lune", C.c_double), ("lune_bytes", C.c_double),
-                ("exhaustive_pairs", C.c_double), ("lune_tests", C.c_double), ("reserved", C.c_double * 3)]
+                ("ms_query", C.c_double), ("ms_vgrng", C.c_double), ("ms_pairs", C.c_double),
+                ("ms_lune", C.c_double), ("vgrng_ops", C.c_double), ("pairs_flops", C.c_double),
+                ("lune_bytes", C.c_double), ("reserved", C.c_double * 4)]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
 
 
 _lib = None

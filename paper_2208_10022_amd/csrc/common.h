@@ -108,7 +108,9 @@ enum Counter {
     C_RECHECK,        // exact re-decisions
     C_SURV,           // pairs left for the exhaustive scan (after Stage V)
     C_LUNE,           // witness predicates evaluated by the exhaustive scan
-    C_NUM
+    C_WORK0,          // 8 work counters for dynamic scheduling (one per XCD)
+    C_WORK_END = C_WORK0 + 8,
+    C_NUM = C_WORK_END
 };
 
 }  // namespace grng
@@ -189,16 +191,19 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const in
                         int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
                         const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
                         const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
-                        uint64_t *dmax_bits, uint64_t *counters);
+                        uint64_t *dmax_bits, uint64_t *work, uint64_t *counters);
 void launch_pairs_all(hipStream_t s, int64_t n, int dp, const double *X, const double *nrm, PairList out,
                       uint64_t *dmax_bits, uint64_t *counters);
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_dx);
+void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
+                            int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
-                        const int32_t *rel_grp, const double *rel_dx, uint8_t *alive, uint64_t *counters);
+                        const int32_t *rel_grp, const double *rel_dx, uint8_t *alive, uint64_t *work,
+                        uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *X, const double *nrm, uint8_t *alive, uint64_t *counters);
 

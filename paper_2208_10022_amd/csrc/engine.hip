@@ -312,7 +312,12 @@ void build_rng_brute(grng_index *idx, DevBuf &edges, int64_t &ne, double &ms_lun
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), nullptr, edges, ne);
 }
 
-void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &ne, double &ms_lune) {
+struct BuildTimes {
+    double vgrng = 0, pairs = 0, lune = 0;
+    int64_t tile_pairs = 0;
+};
+
+void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &ne, BuildTimes &bt) {
     hipStream_t s = idx->stream;
     const Layer &L = idx->layers.back();
     const int64_t n = idx->n, m = L.m;
@@ -388,10 +393,14 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
     ps.par_idx.alloc(4 * (size_t)std::max<int64_t>(par_off[n], 1));
     ps.g_rows.alloc(8 * (size_t)(n * words));
     ps.v_rows.alloc(8 * (size_t)(n * words));
-    launch_point_pass2(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), L.rad.as<double>(), L.dpp.as<double>(),
-                       ps.dvor.as<double>(), gcount.as<int32_t>(), L.bits.as<uint64_t>(), words,
-                       ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(), bd.as<float>(), bv.as<float>(),
-                       ps.g_rows.as<uint64_t>(), ps.v_rows.as<uint64_t>(), ctr);
+    {
+        EventTimer vt(s);
+        launch_point_pass2(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), L.rad.as<double>(), L.dpp.as<double>(),
+                           ps.dvor.as<double>(), gcount.as<int32_t>(), L.bits.as<uint64_t>(), words,
+                           ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(), bd.as<float>(), bv.as<float>(),
+                           ps.g_rows.as<uint64_t>(), ps.v_rows.as<uint64_t>(), ctr);
+        bt.vgrng = vt.stop();
+    }
     const int64_t nw = div_up(n, 64);
     ps.g_cols.alloc(8 * (size_t)(m * nw));
     ps.v_cols.alloc(8 * (size_t)(m * nw));
@@ -437,10 +446,13 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
         P.reserve(cap);
         zero(P.count, s);
         zero(dmax, s);
+        EventTimer pt(s);
         launch_pairs_tiled(s, ntp, tpT.as<int32_t>(), tpU.as<int32_t>(), d_tiles.as<int32_t>(), dp, ps.Xh.as<double>(),
                            ps.nrmh.as<double>(), ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(),
                            ps.v_rows.as<uint64_t>(), ps.g_cols.as<uint64_t>(), words, nw, pknn.as<int32_t>(), K,
-                           Xp.as<double>(), nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr);
+                           Xp.as<double>(), nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
+        bt.pairs = pt.stop();
+        bt.tile_pairs = ntp;
         std::vector<uint64_t> h;
         d2h(h, P.count.p, 1, s);
         np = (int64_t)h[0];
@@ -466,6 +478,22 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
     launch_relevant_groups(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), ps.dvor.as<double>(),
                            gcount.as<int32_t>(), dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(),
                            rel_grp.as<int32_t>(), rel_d2x.as<double>());
+    // Order the survivors by row point: neighbouring pairs then share their
+    // witness cells, which the lune kernel keeps in one XCD's L2.
+    {
+        DevBuf cnt, roff, sx, sy, sd2;
+        cnt.alloc(4 * (size_t)std::max<int64_t>(n + 1, 2));
+        zero(cnt, s);
+        roff.alloc(8 * (size_t)(n + 1));
+        sx.alloc(4 * (size_t)std::max<int64_t>(np, 1));
+        sy.alloc(4 * (size_t)std::max<int64_t>(np, 1));
+        sd2.alloc(8 * (size_t)std::max<int64_t>(np, 1));
+        launch_pairs_sort_rows(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), n, cnt.as<int32_t>(),
+                               roff.as<int64_t>(), sx.as<int32_t>(), sy.as<int32_t>(), sd2.as<double>());
+        P.x = std::move(sx);
+        P.y = std::move(sy);
+        P.d2 = std::move(sd2);
+    }
     // Stages IV-VI: exhaustive lune test of the survivors.
     DevBuf alive;
     alive.alloc((size_t)std::max<int64_t>(np, 8));
@@ -473,8 +501,8 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), dp, ps.Xh.as<double>(),
                        ps.nrmh.as<double>(), ps.dhome.as<double>(), ps.grp_off.as<int32_t>(), ps.dvor.as<double>(),
                        Xp.as<double>(), nrmp.as<double>(), rel_off.as<int64_t>(), rel_grp.as<int32_t>(),
-                       rel_d2x.as<double>(), alive.as<uint8_t>(), ctr);
-    ms_lune = lt.stop();
+                       rel_d2x.as<double>(), alive.as<uint8_t>(), ctr + C_WORK0, ctr);
+    bt.lune = lt.stop();
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), ps.perm.as<int32_t>(), edges,
                    ne);
 }
@@ -486,13 +514,13 @@ void do_build_rng(grng_index *idx) {
     reset_counters(idx);
     DevBuf edges;
     int64_t ne = 0;
-    double ms_lune = 0.0;
+    BuildTimes bt;
     PointState ps;
     if (idx->layers.empty()) {
         require(idx->n <= 65535, GRNG_EINVAL, "without a pivot layer build_rng is limited to 65535 points");
-        build_rng_brute(idx, edges, ne, ms_lune);
+        build_rng_brute(idx, edges, ne, bt.lune);
     } else {
-        build_rng_guided(idx, ps, edges, ne, ms_lune);
+        build_rng_guided(idx, ps, edges, ne, bt);
     }
     const double ms = timer.stop();
     uint64_t c[C_NUM];
@@ -504,7 +532,15 @@ void do_build_rng(grng_index *idx) {
     idx->stats.n_edges = ne;
     idx->stats.orphans = idx->ps.orphans;
     idx->stats.ms_rng = ms;
-    idx->stats.ms_lune = ms_lune;
+    idx->stats.ms_vgrng = bt.vgrng;
+    idx->stats.ms_pairs = bt.pairs;
+    idx->stats.ms_lune = bt.lune;
+    idx->stats.tile_pairs = bt.tile_pairs;
+    {
+        const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
+        idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * m;
+        idx->stats.pairs_flops = 2.0 * idx->dp * (64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs;
+    }
     idx->stats.distance_computations = (double)c[C_DIST];
     idx->stats.witness_tests = (double)c[C_WTEST];
     idx->stats.candidate_pairs = (double)c[C_CAND];

@@ -87,20 +87,10 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
 //     already in LDS (one lane per witness, wave ballot for the verdict).
 // Survivors go to the global pair list for the exhaustive scan.
 constexpr int kTile = 64;
+constexpr int kXcds = 8;       // XCDs of an MI355X; workgroups are dealt to them round-robin
 constexpr int kPiv = 16;        // pivot witnesses per tile pair (one MFMA column block)
-constexpr int kQueue = 512;     // Stage IV survivors held in LDS for Stage V
 
 typedef double v4d __attribute__((ext_vector_type(4)));
-
-struct TileLds {
-    double *X, *Y, *P;          // [64][ld], [64][ld], [16][ld] rows, ld = dp + 1
-    double *nX, *nY, *nP;       // norms
-    double *XP, *YP;            // [64][17] exact d^2 to the pivot witnesses
-    uint64_t *mX, *mY;          // candidate masks per x (over U) and per y (over T)
-    uint32_t *qpair;            // Stage V queue: i | j << 8
-    double *qd2;
-    int32_t *qcount;
-};
 
 __device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) {
     // 64 bits of a bit row starting at bit `start` (bits past len are don't-care)
@@ -116,46 +106,60 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
     int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const int64_t *__restrict__ par_off,
     const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ v_rows, const uint64_t *__restrict__ g_cols,
     int32_t words, int64_t nw, const int32_t *__restrict__ pknn, int32_t K, const double *__restrict__ Xp,
-    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *counters) {
+    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *work,
+    unsigned long long *counters) {
+    // LDS: rows of T, U and the pivot witnesses (ld = dp + 1 doubles per row),
+    // norms, d^2 to the pivots (float, rounded up), candidate masks and the
+    // 64 x 64 bit mask of Stage IV survivors.
     extern __shared__ double lds[];
     const int ld = dp + 1;
-    TileLds L;
-    L.X = lds;
-    L.Y = L.X + kTile * ld;
-    L.P = L.Y + kTile * ld;
-    L.nX = L.P + kPiv * ld;
-    L.nY = L.nX + kTile;
-    L.nP = L.nY + kTile;
-    L.XP = L.nP + kPiv;
-    L.YP = L.XP + kTile * (kPiv + 1);
-    L.mX = (uint64_t *)(L.YP + kTile * (kPiv + 1));
-    L.mY = L.mX + kTile;
-    L.qd2 = (double *)(L.mY + kTile);
-    L.qpair = (uint32_t *)(L.qd2 + kQueue);
-    L.qcount = (int32_t *)(L.qpair + kQueue);
+    double *sX = lds, *sY = sX + kTile * ld, *sP = sY + kTile * ld;
+    double *nX = sP + kPiv * ld, *nY = nX + kTile, *nP = nY + kTile;
+    uint64_t *mX = (uint64_t *)(nP + kPiv), *mY = mX + kTile, *surv = mY + kTile;
+    float *XP = (float *)(surv + kTile), *YP = XP + kTile * (kPiv + 1);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = w >> 1, wc = w & 1;
+    const int il = lane & 15, kl = lane >> 4;
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntests = 0;
-    for (int64_t tp = blockIdx.x; tp < ntp; tp += gridDim.x) {
+    __shared__ int64_t s_tp;
+    const int xcd0 = blockIdx.x % kXcds;
+    int xr = 0;
+    for (;;) {
+        // Dynamic, XCD-aware scheduling (tile pairs are sorted by T: the
+        // c-th eighth goes to XCD c first, then the XCDs help each other).
+        if (tid == 0) {
+            int64_t got = -1;
+            while (xr < kXcds) {
+                const int c = (xcd0 + xr) % kXcds;
+                const int64_t lo = ntp * c / kXcds, hi = ntp * (c + 1) / kXcds;
+                const int64_t t = (int64_t)atomicAdd(&work[c], 1ull);
+                if (lo + t < hi) { got = lo + t; break; }
+                ++xr;
+            }
+            s_tp = got;
+        }
+        __syncthreads();
+        const int64_t tp = s_tp;
+        __syncthreads();
+        if (tp < 0) break;
         const int32_t T = tpT[tp], U = tpU[tp];
         const int32_t sT = tiles[3 * T], lT = tiles[3 * T + 1], a = tiles[3 * T + 2];
         const int32_t sU = tiles[3 * U], lU = tiles[3 * U + 1], b = tiles[3 * U + 2];
         // 1. rows, norms, pivot witnesses, candidate masks -> LDS
         for (int e = tid; e < kTile * dp; e += 256) {
             const int r = e / dp, c = e % dp;
-            L.X[r * ld + c] = r < lT ? Xh[(int64_t)(sT + r) * dp + c] : 0.0;
-            L.Y[r * ld + c] = r < lU ? Xh[(int64_t)(sU + r) * dp + c] : 0.0;
+            sX[r * ld + c] = r < lT ? Xh[(int64_t)(sT + r) * dp + c] : 0.0;
+            sY[r * ld + c] = r < lU ? Xh[(int64_t)(sU + r) * dp + c] : 0.0;
         }
         const int ka = (a == b) ? K : (K + 1) / 2;
         for (int e = tid; e < kPiv * dp; e += 256) {
             const int t = e / dp, c = e % dp;
             const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
-            L.P[t * ld + c] = Xp[(int64_t)pv * dp + c];
+            sP[t * ld + c] = Xp[(int64_t)pv * dp + c];
         }
         if (tid < kPiv) {
             const int t = tid;
             const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
-            L.nP[t] = nrmp[pv];
+            nP[t] = nrmp[pv];
         }
         if (tid < kTile) {
             const int r = tid;
@@ -167,9 +171,12 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
                 mk = ((v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
                 for (int64_t q = par_off[x]; q < par_off[x + 1] && mk; ++q)
                     mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sU, lU);
+                if (T == U) mk &= r == 63 ? 0ull : (~0ull << (r + 1));   // y > x inside one tile
+                mk &= lU == 64 ? ~0ull : ((1ull << lU) - 1ull);
             }
-            L.nX[r] = nv;
-            L.mX[r] = mk;
+            nX[r] = nv;
+            mX[r] = mk;
+            surv[r] = 0;
         } else if (tid < 2 * kTile) {
             const int r = tid - kTile;
             uint64_t mk = 0;
@@ -181,105 +188,86 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
                 for (int64_t q = par_off[y]; q < par_off[y + 1] && mk; ++q)
                     mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sT, lT);
             }
-            L.nY[r] = nv;
-            L.mY[r] = mk;
-        } else if (tid == 2 * kTile) {
-            *L.qcount = 0;
+            nY[r] = nv;
+            mY[r] = mk;
         }
         __syncthreads();
-        // 2. MFMA tiles: D_XY (each wave 32x32), and 16 rows of X.P^T and Y.P^T per wave.
-        const int il = lane & 15, kl = lane >> 4;
-        v4d acc[2][2];
-        v4d axp = {0.0, 0.0, 0.0, 0.0}, ayp = {0.0, 0.0, 0.0, 0.0};
-        for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 2; ++v) acc[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int kk = 0; kk < dp; kk += 4) {
-            double av[2], bv[2];
-            for (int u = 0; u < 2; ++u) av[u] = L.X[(wr * 32 + u * 16 + il) * ld + kk + kl];
-            for (int v = 0; v < 2; ++v) bv[v] = L.Y[(wc * 32 + v * 16 + il) * ld + kk + kl];
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 2; ++v)
-                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
-            const double pv = L.P[il * ld + kk + kl];
-            axp = __builtin_amdgcn_mfma_f64_16x16x4f64(L.X[(w * 16 + il) * ld + kk + kl], pv, axp, 0, 0, 0);
-            ayp = __builtin_amdgcn_mfma_f64_16x16x4f64(L.Y[(w * 16 + il) * ld + kk + kl], pv, ayp, 0, 0, 0);
-        }
-        for (int r = 0; r < 4; ++r) {
-            const int row = w * 16 + 4 * r + kl;
-            L.XP[row * (kPiv + 1) + il] = L.nX[row] + L.nP[il] - 2.0 * axp[r];
-            L.YP[row * (kPiv + 1) + il] = L.nY[row] + L.nP[il] - 2.0 * ayp[r];
-        }
-        __syncthreads();
-        // 3. candidates (Stages I-III) and pivot witnesses (Stage IV).
-        double d2[2][2][4];
-        uint32_t live = 0;
-        for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 2; ++v) {
-                const int j = wc * 32 + v * 16 + il;
-                for (int r = 0; r < 4; ++r) {
-                    const int i = wr * 32 + u * 16 + 4 * r + kl;
-                    d2[u][v][r] = L.nX[i] + L.nY[j] - 2.0 * acc[u][v][r];
-                    const bool c = i < lT && j < lU && (T != U || j > i) && ((L.mX[i] >> j) & 1ull) &&
-                                   ((L.mY[j] >> i) & 1ull);
-                    if (c) live |= 1u << (u * 8 + v * 4 + r);
-                }
+        // 2a. d^2 from the 64 rows of T and U to the 16 pivot witnesses (MFMA f64).
+        {
+            v4d axp = {0.0, 0.0, 0.0, 0.0}, ayp = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < dp; kk += 4) {
+                const double pv = sP[il * ld + kk + kl];
+                axp = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(w * 16 + il) * ld + kk + kl], pv, axp, 0, 0, 0);
+                ayp = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[(w * 16 + il) * ld + kk + kl], pv, ayp, 0, 0, 0);
             }
-        ncand += __popc(live);
-        for (int t = 0; t < K; ++t) {
-            if (!__ballot(live != 0)) break;
-            double yv[2], xv[2][4];
-            for (int v = 0; v < 2; ++v) yv[v] = L.YP[(wc * 32 + v * 16 + il) * (kPiv + 1) + t];
-            for (int u = 0; u < 2; ++u)
-                for (int r = 0; r < 4; ++r) xv[u][r] = L.XP[(wr * 32 + u * 16 + 4 * r + kl) * (kPiv + 1) + t];
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 2; ++v)
-                    for (int r = 0; r < 4; ++r) {
-                        const uint32_t bit = 1u << (u * 8 + v * 4 + r);
-                        if ((live & bit) && fmax(xv[u][r], yv[v]) < d2[u][v][r]) live &= ~bit;
-                    }
-            ntests += 16;
+            for (int r = 0; r < 4; ++r) {
+                const int row = w * 16 + 4 * r + kl;
+                XP[row * (kPiv + 1) + il] = __double2float_ru(nX[row] + nP[il] - 2.0 * axp[r]);
+                YP[row * (kPiv + 1) + il] = __double2float_ru(nY[row] + nP[il] - 2.0 * ayp[r]);
+            }
         }
-        ns4 += __popc(live);
-        // Stage V in rounds: move up to kQueue Stage IV survivors into the LDS
-        // queue, test them against the points of T and U, repeat until none is
-        // left (every survivor passes through Stage V, so the output is
-        // deterministic).
-        for (;;) {
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 2; ++v)
-                    for (int r = 0; r < 4; ++r) {
-                        const uint32_t bit = 1u << (u * 8 + v * 4 + r);
-                        if (!(live & bit)) continue;
-                        const int slot = atomicAdd(L.qcount, 1);
-                        if (slot >= kQueue) continue;      // stays live for the next round
-                        live &= ~bit;
-                        const int i = wr * 32 + u * 16 + 4 * r + kl, j = wc * 32 + v * 16 + il;
-                        L.qpair[slot] = (uint32_t)i | ((uint32_t)j << 8);
-                        L.qd2[slot] = d2[u][v][r];
-                    }
-            __syncthreads();
-            const int qn = min(*L.qcount, kQueue);
-            for (int e = w; e < qn; e += 4) {
-                const uint32_t pr = L.qpair[e];
-                const int i = pr & 255, j = pr >> 8;
-                const double dd = L.qd2[e];
-                const double *xr = L.X + i * ld, *yr = L.Y + j * ld;
+        __syncthreads();
+        // 2b. Each wave: its 4 16x16 blocks of D_XY, one at a time; Stages I-IV.
+        for (int blk = 0; blk < 4; ++blk) {
+            const int rb = (w >> 1) * 32 + (blk >> 1) * 16, cb = (w & 1) * 32 + (blk & 1) * 16;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kk = 0; kk < dp; kk += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(rb + il) * ld + kk + kl], sY[(cb + il) * ld + kk + kl],
+                                                           acc, 0, 0, 0);
+            const int j = cb + il;
+            double d2[4];
+            uint32_t live = 0;
+            const uint64_t myj = mY[j];
+            for (int r = 0; r < 4; ++r) {
+                const int i = rb + 4 * r + kl;
+                d2[r] = nX[i] + nY[j] - 2.0 * acc[r];
+                if (((mX[i] >> j) & 1ull) && ((myj >> i) & 1ull)) live |= 1u << r;
+            }
+            ncand += __popc(live);
+            // Stage IV: min over pivots of max(d^2(x,p), d^2(y,p)) from values
+            // rounded up; below d^2(x,y) proves a witness.
+            float cmin[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+            for (int t0 = 0; t0 < K; t0 += 4) {
+                if (!__ballot(live != 0)) break;
+                ntests += __popc(live) * (uint32_t)min(4, K - t0);
+                for (int t = t0; t < t0 + 4 && t < K; ++t) {
+                    const float yv = YP[j * (kPiv + 1) + t];
+                    for (int r = 0; r < 4; ++r)
+                        cmin[r] = fminf(cmin[r], fmaxf(XP[(rb + 4 * r + kl) * (kPiv + 1) + t], yv));
+                }
+                for (int r = 0; r < 4; ++r)
+                    if ((double)cmin[r] < d2[r]) live &= ~(1u << r);
+            }
+            ns4 += __popc(live);
+            for (int r = 0; r < 4; ++r)
+                if (live & (1u << r)) atomicOr((unsigned long long *)&surv[rb + 4 * r + kl], 1ull << j);
+        }
+        __syncthreads();
+        // 3. Stage V: each wave walks rows w, w+4, ...; every Stage IV survivor
+        // of the row is tested against the points of T and U (one lane per witness).
+        for (int i = w; i < lT; i += 4) {
+            uint64_t row = surv[i];
+            const double *xr = sX + i * ld;
+            while (row) {
+                const int j = __ffsll((long long)row) - 1;
+                row &= row - 1;
+                const double *yr = sY + j * ld;
+                double sxy = 0.0;
+                for (int c = 0; c < dp; ++c) sxy = fma(xr[c], yr[c], sxy);
+                const double dd = nX[i] + nY[j] - 2.0 * sxy;   // exact
                 bool wit = false;
                 for (int half = 0; half < 2 && !wit; ++half) {
-                    const int zl = lane;
-                    const bool ok = half == 0 ? zl < lT : zl < lU;
                     bool wz = false;
-                    if (ok) {
-                        const double *zr = (half == 0 ? L.X : L.Y) + zl * ld;
-                        const double nz = half == 0 ? L.nX[zl] : L.nY[zl];
+                    if (lane < (half == 0 ? lT : lU)) {
+                        const double *zr = (half == 0 ? sX : sY) + lane * ld;
+                        const double nz = half == 0 ? nX[lane] : nY[lane];
                         double sx = 0.0, sy = 0.0;
                         for (int c = 0; c < dp; ++c) {
-                            sx = fma(xr[c], zr[c], sx);
-                            sy = fma(yr[c], zr[c], sy);
+                            const double zc = zr[c];
+                            sx = fma(xr[c], zc, sx);
+                            sy = fma(yr[c], zc, sy);
                         }
-                        const double d2xz = L.nX[i] + nz - 2.0 * sx;
-                        const double d2yz = L.nY[j] + nz - 2.0 * sy;
-                        wz = d2xz < dd && d2yz < dd;
+                        wz = (nX[i] + nz - 2.0 * sx) < dd && (nY[j] + nz - 2.0 * sy) < dd;
                         ++ntests;
                     }
                     wit = __ballot(wz) != 0;
@@ -295,13 +283,8 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
                     ++nsurv;
                 }
             }
-            __syncthreads();
-            const bool more = *L.qcount > kQueue;
-            __syncthreads();
-            if (tid == 0) *L.qcount = 0;
-            __syncthreads();
-            if (!more) break;
         }
+        __syncthreads();
     }
     ncand = wave_sum(ncand);
     ns4 = wave_sum(ns4);
@@ -313,6 +296,24 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
         atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
     }
+}
+
+// Counting sort of the pair list by row point (stable within a row is not
+// needed: the lune verdict of a pair does not depend on its position).
+__global__ void k_pairs_count_rows(int64_t np, const int32_t *px, int32_t *cnt) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < np) atomicAdd(&cnt[px[p]], 1);
+}
+
+__global__ void k_pairs_scatter_rows(int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
+                                     const int64_t *off, int32_t *fill, int32_t *ox, int32_t *oy, double *od2) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int32_t x = px[p];
+    const int64_t s = off[x] + atomicAdd(&fill[x], 1);
+    ox[s] = x;
+    oy[s] = py[p];
+    od2[s] = pd2[p];
 }
 
 // Tile bookkeeping: OR of the cell bits of a tile's points; tile pairs whose
@@ -471,12 +472,29 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const double *__restrict__ dhome,
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
     const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
-    const double *__restrict__ rel_d2x, uint8_t *__restrict__ alive, unsigned long long *counters) {
+    const double *__restrict__ rel_d2x, uint8_t *__restrict__ alive, unsigned long long *work,
+    unsigned long long *counters) {
+    // Dynamic, XCD-aware scheduling: workgroups are dealt round-robin to the
+    // 8 XCDs, so a wave on XCD c takes pairs one at a time from the c-th
+    // contiguous eighth of the list (sorted by row point: its witness cells
+    // stay in that XCD's L2), then helps the other eighths.  Pair costs vary
+    // by orders of magnitude, so static assignment would leave long tails.
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int xcd0 = blockIdx.x % kXcds;
+    int xr = 0;
     uint32_t ntests = 0, ndist = 0;
-    for (int64_t p = wave0; p < npairs; p += nwaves) {
+    for (;;) {
+        int64_t p = -1;
+        while (xr < kXcds) {
+            const int c = (xcd0 + xr) % kXcds;
+            const int64_t lo = npairs * c / kXcds, hi = npairs * (c + 1) / kXcds;
+            unsigned long long t = 0;
+            if (lane == 0) t = atomicAdd(&work[c], 1ull);
+            t = __shfl(t, 0, kWave);
+            if (lo + (int64_t)t < hi) { p = lo + (int64_t)t; break; }
+            ++xr;
+        }
+        if (p < 0) break;
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
         const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
         const double d2 = pd2[p];
@@ -513,20 +531,28 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 const double gx = __shfl(dxl, src, kWave), gy = __shfl(dyl, src, kWave);
                 const double gmax = fmax(gx, gy);
                 const int64_t z0 = grp_off[gg], z1 = grp_off[gg + 1];
-                for (int64_t zb = z0; zb < z1; zb += 64) {
-                    const int64_t z = zb + lane;
+                // Four 64-point chunks per ballot: more loads in flight per wave.
+                for (int64_t zb = z0; zb < z1; zb += 256) {
                     bool wit = false;
-                    // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
-                    if (z < z1 && !surely_ge(gmax, dhome[z], dxy_hi)) {
-                        const double *zr = Xh + z * dp;
-                        const double d2xz = nrx + nrmh[z] - 2.0 * dot_lds(xs, zr, dp);
-                        ndist += 1;
-                        if (d2xz < d2) {
-                            const double d2yz = nry + nrmh[z] - 2.0 * dot_lds(ys, zr, dp);
-                            ndist += 1;
-                            wit = d2yz < d2;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t z = zb + 64 * u + lane;
+                        // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
+                        if (z < z1 && !surely_ge(gmax, dhome[z], dxy_hi)) {
+                            const double *zr = Xh + z * dp;
+                            const double nz = nrmh[z];
+                            double sx = 0.0, sy = 0.0;
+                            for (int c = 0; c < dp; c += 2) {
+                                const double2 zv = *reinterpret_cast<const double2 *>(zr + c);
+                                sx = fma(xs[c], zv.x, sx);
+                                sx = fma(xs[c + 1], zv.y, sx);
+                                sy = fma(ys[c], zv.x, sy);
+                                sy = fma(ys[c + 1], zv.y, sy);
+                            }
+                            wit = wit || ((nrx + nz - 2.0 * sx) < d2 && (nry + nz - 2.0 * sy) < d2);
+                            ndist += 2;
+                            ++ntests;
                         }
-                        ++ntests;
                     }
                     if (__ballot(wit)) { dead = true; break; }
                 }
@@ -609,21 +635,22 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const in
                         int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
                         const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
                         const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
-                        uint64_t *dmax_bits, uint64_t *counters) {
+                        uint64_t *dmax_bits, uint64_t *work, uint64_t *counters) {
     if (ntp == 0) return;
+    launch_fill_u64(s, work, kXcds, 0ull);
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the pair kernel");
     require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
     const int ld = dp + 1;
-    const size_t lds = sizeof(double) * (size_t)(2 * kTile * ld + kPiv * ld + 2 * kTile + kPiv +
-                                                 2 * kTile * (kPiv + 1) + 2 * kTile + kQueue) +
-                       sizeof(uint32_t) * (kQueue + 2);
+    const size_t lds = sizeof(double) * (size_t)(2 * kTile * ld + kPiv * ld + 2 * kTile + kPiv + 3 * kTile) +
+                       sizeof(float) * (size_t)(2 * kTile * (kPiv + 1));
     if (lds > 64 * 1024)
         GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
-    const int64_t grid = ntp < 65536 ? ntp : 65536;
+    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(ntp, 256 * 8));
     k_pairs_tiled<<<(unsigned)grid, 256, lds, s>>>(ntp, tpT, tpU, tiles, dp, Xh, nrmh, par_off, par_idx, v_rows,
                                                    g_cols, words, nw, pknn, K, Xp, nrmp, out,
-                                                   (unsigned long long *)dmax_bits, (unsigned long long *)counters);
+                                                   (unsigned long long *)dmax_bits, (unsigned long long *)work,
+                                                   (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
@@ -654,15 +681,29 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
     GRNG_LAUNCHED();
 }
 
+void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
+                            int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2) {
+    if (np == 0) return;
+    k_pairs_count_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, cnt);
+    GRNG_LAUNCHED();
+    launch_scan_i32_to_i64(s, cnt, n, off);
+    launch_fill_u64(s, (uint64_t *)cnt, div_up(n, 2), 0ull);
+    k_pairs_scatter_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, py, pd2, off, cnt, ox, oy, od2);
+    GRNG_LAUNCHED();
+}
+
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
-                        const int32_t *rel_grp, const double *rel_d2x, uint8_t *alive, uint64_t *counters) {
+                        const int32_t *rel_grp, const double *rel_d2x, uint8_t *alive, uint64_t *work,
+                        uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
-    const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
+    launch_fill_u64(s, work, kXcds, 0ull);
+    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 8));
     k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xh, nrmh, dhome, grp_off, dvor,
                                                               Xp, nrmp, rel_off, rel_grp, rel_d2x, alive,
+                                                              (unsigned long long *)work,
                                                               (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
