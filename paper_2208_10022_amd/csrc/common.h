@@ -79,24 +79,39 @@ struct Layer {
     DevBuf parent_bits;        // uint64 [m*coarse_words]: coarse relative-domain parents (layer > 0)
 };
 
-// Per-point state of the finest-layer-guided RNG (all arrays in home order).
+// A point set prepared against the finest pivot layer, in home order (grouped
+// by nearest pivot).  For the indexed set the home cells are also the witness
+// groups (grp_off, dvor, gcount, dhome); for a query set only the home order,
+// parents and virtual-pivot bits are used.
 struct PointState {
     int64_t n = 0;
-    DevBuf perm;               // int32 [n] home-order position -> point id
-    DevBuf inv;                // int32 [n] point id -> home-order position
-    DevBuf Xh;                 // double [n*dp] coordinates in home order
-    DevBuf nrmh;               // double [n] squared norms in home order
-    DevBuf home;               // int32 [n] nearest pivot (position in layer)
-    DevBuf dhome;              // double [n] upper bound of d(x, p_home)
-    DevBuf grp_off;            // int32 [m+1] home-order range of each group
-    DevBuf dvor;               // double [m] upper bound of the group radius (max d(x, p_c))
-    DevBuf par_off;            // int64 [n+1] parents CSR
-    DevBuf par_idx;            // int32 [nnz]
-    DevBuf g_rows;             // uint64 [n*words] virtual-pivot GRNG(x) (domain radii)
-    DevBuf v_rows;             // uint64 [n*words] virtual-pivot GRNG of x over Voronoi groups
-    DevBuf g_cols;             // uint64 [m*nw] transposed g_rows (nw = ceil(n/64))
-    DevBuf v_cols;             // uint64 [m*nw] transposed v_rows
+    int64_t ntiles = 0;
+    int64_t nw = 0;                // words of a transposed bit row: ceil(n / 64)
     int64_t orphans = 0;
+    std::vector<int32_t> h_perm;   // home-order position -> index in the set
+    std::vector<int32_t> h_off;    // [m+1] home-order start of each home cell
+    DevBuf perm;                   // int32 [n]
+    DevBuf inv;                    // int32 [n] index -> home-order position
+    DevBuf Xh, nrmh;               // double [n][dp], [n]
+    DevBuf home;                   // int32 [n] home cell (pivot position)
+    DevBuf dhome;                  // double [n] upper bound of d(x, p_home)
+    DevBuf grp_off;                // int32 [m+1]
+    DevBuf dvor;                   // double [m] upper bound of the cell radius
+    DevBuf gcount;                 // int32 [m] cell sizes
+    DevBuf par_off, par_idx;       // parents CSR (int64 [n+1], int32)
+    DevBuf g_rows, v_rows;         // uint64 [n][words] virtual-pivot bits (domains / cells)
+    DevBuf g_cols;                 // uint64 [m][nw] transposed g_rows
+    DevBuf tiles;                  // int32 [ntiles][3]
+    DevBuf tv;                     // uint64 [ntiles][words] OR of v_rows over the tile
+    DevBuf is_new, tnew;           // uint8 [n], [ntiles] (insertion only)
+    DevBuf dxp;                    // double [n][m] exact d^2 to the pivots, input order
+};
+
+// Pivot-side tables of the finest layer used by every pass over points.
+struct LayerAux {
+    DevBuf Xp, nrmp;               // pivot coordinates and norms
+    DevBuf pknn;                   // int32 [m][16] nearest pivots of each pivot
+    DevBuf bd, bv;                 // float [m][m] shifted pivot distances (virtual-pivot test)
 };
 
 // Counters written by kernels (device, uint64 each).
@@ -124,7 +139,8 @@ struct grng_index {
     grng::DevBuf X;            // double [cap*dp] exact coordinates, rows zero-padded
     grng::DevBuf nrm;          // double [cap] exact squared norms
     std::vector<grng::Layer> layers;
-    grng::PointState ps;       // valid when rng_built
+    grng::PointState ps;       // valid when rng_built (with a layer)
+    grng::LayerAux aux;        // valid when rng_built (with a layer)
     bool rng_built = false;
     grng::DevBuf edges;        // int32 [2E] canonical exemplar RNG edges
     int64_t nedges = 0;
@@ -168,44 +184,71 @@ void launch_point_pass1(hipStream_t s, int64_t n, int64_t m, const double *dxp, 
                         int32_t *home, double *d2home, int32_t *npar);
 void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const double *d2home,
                          uint64_t *d2vor_bits, int32_t *gcount);
-void launch_point_pass2(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
-                        const double *rad, const double *dpp, const double *dvor, const int32_t *gcount,
-                        const uint64_t *layer_bits, int32_t words, const int64_t *par_off, int32_t *par_idx,
-                        float *bd, float *bv, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
+void launch_parents(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const double *rad,
+                    const int64_t *par_off, int32_t *par_idx);
+void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, const double *rad, const double *dvor,
+                                float *bd, float *bv);
+void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
+                  const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
+                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, uint64_t *g_rows, uint64_t *v_rows,
+                  uint64_t *counters);
 
 // k_rng.hip
 struct PairList {
-    int32_t *x;       // home-order position of the row point
-    int32_t *y;       // home-order position of the other point
+    int32_t *x;       // position of the row point (in its own point set, home order)
+    int32_t *y;       // position of the other point (home order of the indexed set)
     double *d2;       // exact squared distance
     uint64_t *count;  // number of pairs requested (may exceed cap)
     int64_t cap;
 };
+
+// One side of the tiled pair enumeration (device pointers, home order).
+struct PointsView {
+    const double *Xh;        // [n][dp] coordinates
+    const double *nrmh;      // [n] squared norms
+    const int64_t *par_off;  // [n+1] parents CSR
+    const int32_t *par_idx;
+    const uint64_t *v_rows;  // [n][words] cell bits of the virtual-pivot test
+    const uint64_t *g_cols;  // [m][nw] transposed domain bits of the virtual-pivot test
+    int64_t nw;
+    const int32_t *tiles;    // [ntiles][3]: start, length (<= 64), home cell
+    const uint8_t *is_new;   // [n] inserted in this batch (insertion only), else null
+};
+enum PairMode { PM_SELF = 1, PM_NEW_ONLY = 2 };
+
 constexpr int kPivWitness = 16;   // pivot witnesses per tile pair in the tiled pair kernel
 void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t *pknn);   // pknn [m][16]
 void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
                        uint64_t *tv);
-void launch_tile_pairs(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *tv, int32_t words,
-                       const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU);
-void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const int32_t *tiles,
-                        int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
-                        const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
-                        const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
-                        uint64_t *dmax_bits, uint64_t *work, uint64_t *counters);
-void launch_pairs_all(hipStream_t s, int64_t n, int dp, const double *X, const double *nrm, PairList out,
-                      uint64_t *dmax_bits, uint64_t *counters);
+void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const uint64_t *tvA, const uint8_t *newA,
+                       int64_t ntB, const int32_t *tilesB, const uint64_t *tvB, const uint8_t *newB, int32_t words,
+                       int mode, const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU);
+void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const PointsView &A,
+                        const PointsView &B, int mode, int dp, int32_t words, const int32_t *pknn, int32_t K,
+                        const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
+                        uint64_t *counters);
+void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,
+                      const double *nrmB, int dp, bool self, PairList out, uint64_t *counters);
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
-                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_dx);
+                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x);
 void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
-                        int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
-                        const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
-                        const int32_t *rel_grp, const double *rel_dx, uint8_t *alive, uint64_t *work,
-                        uint64_t *counters);
+                        int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
+                        const double *dhome, const int32_t *zstart, const int32_t *grp_off, const double *dvor,
+                        const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
+                        const double *rel_d2x, uint8_t *alive, uint64_t *work, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
-                     int64_t n, int dp, const double *X, const double *nrm, uint8_t *alive, uint64_t *counters);
+                     int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
+                     int64_t z_from, uint8_t *alive, uint64_t *counters);
+void launch_pair_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *Xh,
+                    const double *nrmh, double *d2, uint64_t *dmax_bits);
+void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,
+                      const int32_t *qperm, const int32_t *perm, int64_t nq, int32_t *deg, const int64_t *off,
+                      int32_t *fill, int32_t *nbr, int pass);
+void launch_sort_segments(hipStream_t s, int64_t nseg, const int64_t *off, int32_t *vals);
+void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py);
 
 // k_edges.hip
 void launch_edges_count(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py,

@@ -298,16 +298,15 @@ void build_rng_brute(grng_index *idx, DevBuf &edges, int64_t &ne, double &ms_lun
     Pairs P;
     P.reserve(n * (n - 1) / 2);
     zero(P.count, s);
-    DevBuf dmax;
-    dmax.alloc(8 * (size_t)n);
-    launch_pairs_all(s, n, idx->dp, idx->X.as<double>(), idx->nrm.as<double>(), P.view(), dmax.as<uint64_t>(),
-                     idx->counters.as<uint64_t>());
+    launch_pairs_all(s, n, idx->X.as<double>(), idx->nrm.as<double>(), n, idx->X.as<double>(), idx->nrm.as<double>(),
+                     idx->dp, true, P.view(), idx->counters.as<uint64_t>());
     const int64_t np = n * (n - 1) / 2;
     DevBuf alive;
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
-    launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), n, idx->dp,
-                    idx->X.as<double>(), idx->nrm.as<double>(), alive.as<uint8_t>(), idx->counters.as<uint64_t>());
+    launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), n, idx->dp, idx->X.as<double>(),
+                    idx->nrm.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0, alive.as<uint8_t>(),
+                    idx->counters.as<uint64_t>());
     ms_lune = lt.stop();
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), nullptr, edges, ne);
 }
@@ -317,169 +316,206 @@ struct BuildTimes {
     int64_t tile_pairs = 0;
 };
 
-void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &ne, BuildTimes &bt) {
+// Pivot-side tables of the finest layer (coordinates, nearest pivots).
+void prepare_aux(grng_index *idx, const Layer &L, LayerAux &aux) {
     hipStream_t s = idx->stream;
-    const Layer &L = idx->layers.back();
-    const int64_t n = idx->n, m = L.m;
+    const int64_t m = L.m;
+    const int dp = idx->dp;
+    aux.Xp.alloc(sizeof(double) * (size_t)(m * dp));
+    aux.nrmp.alloc(sizeof(double) * (size_t)m);
+    launch_gather_rows(s, idx->X.as<double>(), L.pid.as<int32_t>(), m, dp, aux.Xp.as<double>());
+    launch_gather_f64(s, idx->nrm.as<double>(), L.pid.as<int32_t>(), m, aux.nrmp.as<double>());
+    aux.pknn.alloc(4 * (size_t)(m * kPivWitness));
+    launch_pivot_knn(s, m, L.dpp2.as<double>(), aux.pknn.as<int32_t>());
+    aux.bd.alloc(4 * (size_t)(m * m));
+    aux.bv.alloc(4 * (size_t)(m * m));
+}
+
+// Prepare a point set against the finest layer L.
+//   cells == nullptr: P is the indexed set; its home cells become the witness
+//     groups (cell radii, sizes) and the shifted pivot tables in aux are filled.
+//   cells != nullptr: P is a query set; cell radii and sizes come from `cells`.
+// is_new (host, optional): per input index, 1 for points inserted in this batch.
+void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double *X, const double *nrm, int64_t n,
+                    const PointState *cells, const std::vector<uint8_t> *is_new, PointState &P, BuildTimes &bt) {
+    hipStream_t s = idx->stream;
+    const int64_t m = L.m;
     const int dp = idx->dp;
     const int32_t words = L.words;
-    const int32_t K = idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK;
     uint64_t *ctr = idx->counters.as<uint64_t>();
-    // A1: exact point-pivot distances (MFMA f64 tiles), original order [n][m].
-    DevBuf Xp, nrmp, dxp;
-    Xp.alloc(sizeof(double) * (size_t)(m * dp));
-    nrmp.alloc(sizeof(double) * (size_t)m);
-    launch_gather_rows(s, idx->X.as<double>(), L.pid.as<int32_t>(), m, dp, Xp.as<double>());
-    launch_gather_f64(s, idx->nrm.as<double>(), L.pid.as<int32_t>(), m, nrmp.as<double>());
-    dxp.alloc(sizeof(double) * (size_t)(n * m));
-    launch_dist2(s, idx->X.as<double>(), idx->nrm.as<double>(), n, Xp.as<double>(), nrmp.as<double>(), m, dp,
-                 dxp.as<double>(), m, true);
-    // A2: parents count, home cell, cell radius.
+    const bool indexed = cells == nullptr;
+    P.n = n;
+    // A1: exact point-pivot distances (MFMA f64 tiles), input order [n][m].
+    P.dxp.alloc(sizeof(double) * (size_t)(n * m));
+    launch_dist2(s, X, nrm, n, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, P.dxp.as<double>(), m, true);
+    // A2: parent counts, home cell, cell radius.
     DevBuf home, d2home, npar, d2vor, gcount;
     home.alloc(4 * (size_t)n);
     d2home.alloc(8 * (size_t)n);
     npar.alloc(4 * (size_t)n);
-    d2vor.alloc(8 * (size_t)m);
-    gcount.alloc(4 * (size_t)m);
-    zero(d2vor, s);
-    zero(gcount, s);
-    launch_point_pass1(s, n, m, dxp.as<double>(), L.rad.as<double>(), home.as<int32_t>(), d2home.as<double>(),
+    launch_point_pass1(s, n, m, P.dxp.as<double>(), L.rad.as<double>(), home.as<int32_t>(), d2home.as<double>(),
                        npar.as<int32_t>());
-    launch_group_radius(s, n, home.as<int32_t>(), d2home.as<double>(), d2vor.as<uint64_t>(), gcount.as<int32_t>());
-    // Home order: stable counting sort by home cell (host; O(n)).
-    std::vector<int32_t> h_home, h_npar, h_gcount;
-    std::vector<double> h_d2home, h_d2vor;
+    std::vector<int32_t> h_home, h_npar, h_gcount((size_t)m, 0);
+    std::vector<double> h_d2home, h_d2vor((size_t)m, 0.0);
     d2h(h_home, home.p, (size_t)n, s);
     d2h(h_npar, npar.p, (size_t)n, s);
-    d2h(h_d2home, d2home.p, (size_t)n, s);
-    d2h(h_gcount, gcount.p, (size_t)m, s);
-    d2h(h_d2vor, d2vor.p, (size_t)m, s);
-    std::vector<int32_t> off((size_t)m + 1, 0), perm((size_t)n), home_h((size_t)n);
-    for (int64_t c = 0; c < m; ++c) off[c + 1] = off[c] + h_gcount[c];
+    if (indexed) d2h(h_d2home, d2home.p, (size_t)n, s);
+    // Home order: stable counting sort by home cell (host, O(n)).
+    for (int64_t x = 0; x < n; ++x) ++h_gcount[h_home[x]];
+    P.h_off.assign((size_t)m + 1, 0);
+    for (int64_t c = 0; c < m; ++c) P.h_off[c + 1] = P.h_off[c] + h_gcount[c];
+    P.h_perm.resize((size_t)n);
     {
-        std::vector<int32_t> pos(off.begin(), off.end() - 1);
-        for (int64_t x = 0; x < n; ++x) perm[pos[h_home[x]]++] = (int32_t)x;
+        std::vector<int32_t> pos(P.h_off.begin(), P.h_off.end() - 1);
+        for (int64_t x = 0; x < n; ++x) P.h_perm[pos[h_home[x]]++] = (int32_t)x;
     }
+    std::vector<int32_t> home_h((size_t)n);
     std::vector<int64_t> par_off((size_t)n + 1, 0);
-    std::vector<double> dhome((size_t)n), dvor((size_t)m);
-    int64_t orphans = 0;
+    std::vector<double> dhome;
+    P.orphans = 0;
+    if (indexed) dhome.resize((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
-        const int32_t x = perm[i];
+        const int32_t x = P.h_perm[i];
         home_h[i] = h_home[x];
         par_off[i + 1] = par_off[i] + h_npar[x];
-        dhome[i] = std::sqrt(h_d2home[x]) * (1.0 + 1e-15);   // upper bound of d(x, p_home)
-        orphans += h_npar[x] == 0;
+        P.orphans += h_npar[x] == 0;
+        if (indexed) {
+            dhome[i] = std::sqrt(h_d2home[x]) * (1.0 + 1e-15);   // upper bound of d(x, p_home)
+            h_d2vor[h_home[x]] = std::max(h_d2vor[h_home[x]], h_d2home[x]);
+        }
     }
-    for (int64_t c = 0; c < m; ++c) dvor[c] = std::sqrt(h_d2vor[c]) * (1.0 + 1e-15);
-    ps.n = n;
-    ps.orphans = orphans;
-    h2d(ps.perm, perm, s);
-    h2d(ps.home, home_h, s);
-    h2d(ps.grp_off, off, s);
-    h2d(ps.par_off, par_off, s);
-    h2d(ps.dhome, dhome, s);
-    h2d(ps.dvor, dvor, s);
-    ps.inv.alloc(4 * (size_t)n);
-    launch_iota_inverse(s, ps.perm.as<int32_t>(), n, ps.inv.as<int32_t>());
-    ps.Xh.alloc(sizeof(double) * (size_t)(n * dp));
-    ps.nrmh.alloc(sizeof(double) * (size_t)n);
-    launch_gather_rows(s, idx->X.as<double>(), ps.perm.as<int32_t>(), n, dp, ps.Xh.as<double>());
-    launch_gather_f64(s, idx->nrm.as<double>(), ps.perm.as<int32_t>(), n, ps.nrmh.as<double>());
-    // Parents and virtual-pivot GRNG bitsets (Propositions 1-2) as a tiled
-    // (min, max) product of point-pivot and shifted pivot-pivot distances.
-    DevBuf bd, bv;
-    bd.alloc(4 * (size_t)(m * m));
-    bv.alloc(4 * (size_t)(m * m));
-    ps.par_idx.alloc(4 * (size_t)std::max<int64_t>(par_off[n], 1));
-    ps.g_rows.alloc(8 * (size_t)(n * words));
-    ps.v_rows.alloc(8 * (size_t)(n * words));
+    h2d(P.perm, P.h_perm, s);
+    h2d(P.home, home_h, s);
+    h2d(P.par_off, par_off, s);
+    if (indexed) {
+        std::vector<double> dvor((size_t)m);
+        for (int64_t c = 0; c < m; ++c) dvor[c] = std::sqrt(h_d2vor[c]) * (1.0 + 1e-15);   // upper bound of the cell radius
+        h2d(P.grp_off, P.h_off, s);
+        h2d(P.dhome, dhome, s);
+        h2d(P.dvor, dvor, s);
+        h2d(P.gcount, h_gcount, s);
+        launch_shifted_pivot_dists(s, m, L.dpp.as<double>(), L.rad.as<double>(), P.dvor.as<double>(),
+                                   aux.bd.as<float>(), aux.bv.as<float>());
+    }
+    const PointState &C = indexed ? P : *cells;
+    P.inv.alloc(4 * (size_t)n);
+    launch_iota_inverse(s, P.perm.as<int32_t>(), n, P.inv.as<int32_t>());
+    P.Xh.alloc(sizeof(double) * (size_t)(n * dp));
+    P.nrmh.alloc(sizeof(double) * (size_t)n);
+    launch_gather_rows(s, X, P.perm.as<int32_t>(), n, dp, P.Xh.as<double>());
+    launch_gather_f64(s, nrm, P.perm.as<int32_t>(), n, P.nrmh.as<double>());
+    // Parents and virtual-pivot bitsets (Propositions 1-2) as a tiled (min, max) product.
+    P.par_idx.alloc(4 * (size_t)std::max<int64_t>(par_off[n], 1));
+    launch_parents(s, n, m, P.perm.as<int32_t>(), P.dxp.as<double>(), L.rad.as<double>(), P.par_off.as<int64_t>(),
+                   P.par_idx.as<int32_t>());
+    P.g_rows.alloc(8 * (size_t)(n * words));
+    P.v_rows.alloc(8 * (size_t)(n * words));
     {
         EventTimer vt(s);
-        launch_point_pass2(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), L.rad.as<double>(), L.dpp.as<double>(),
-                           ps.dvor.as<double>(), gcount.as<int32_t>(), L.bits.as<uint64_t>(), words,
-                           ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(), bd.as<float>(), bv.as<float>(),
-                           ps.g_rows.as<uint64_t>(), ps.v_rows.as<uint64_t>(), ctr);
-        bt.vgrng = vt.stop();
+        launch_vgrng(s, n, m, P.perm.as<int32_t>(), P.dxp.as<double>(), aux.bd.as<float>(), aux.bv.as<float>(),
+                     L.rad.as<double>(), C.dvor.as<double>(), C.gcount.as<int32_t>(), P.par_off.as<int64_t>(),
+                     P.par_idx.as<int32_t>(), L.bits.as<uint64_t>(), words, P.g_rows.as<uint64_t>(),
+                     P.v_rows.as<uint64_t>(), ctr);
+        bt.vgrng += vt.stop();
     }
-    const int64_t nw = div_up(n, 64);
-    ps.g_cols.alloc(8 * (size_t)(m * nw));
-    ps.v_cols.alloc(8 * (size_t)(m * nw));
-    launch_bits_transpose(s, ps.g_rows.as<uint64_t>(), n, words, m, ps.g_cols.as<uint64_t>());
-    launch_bits_transpose(s, ps.v_rows.as<uint64_t>(), n, words, m, ps.v_cols.as<uint64_t>());
-    // Tiles: chunks of <= 64 home-order points of one cell; tile pairs whose
-    // cells survive each other's virtual-pivot test (Stage II with cell radii).
+    P.nw = div_up(n, 64);
+    P.g_cols.alloc(8 * (size_t)(m * P.nw));
+    launch_bits_transpose(s, P.g_rows.as<uint64_t>(), n, words, m, P.g_cols.as<uint64_t>());
+    // Tiles: chunks of <= 64 home-order points of one home cell.
     std::vector<int32_t> tiles;
+    std::vector<uint8_t> tnew, newh;
+    if (is_new) newh.resize((size_t)n);
     for (int64_t c = 0; c < m; ++c)
-        for (int32_t st = off[c]; st < off[c + 1]; st += 64) {
+        for (int32_t st = P.h_off[c]; st < P.h_off[c + 1]; st += 64) {
+            const int32_t len = std::min<int32_t>(64, P.h_off[c + 1] - st);
             tiles.push_back(st);
-            tiles.push_back(std::min<int32_t>(64, off[c + 1] - st));
+            tiles.push_back(len);
             tiles.push_back((int32_t)c);
+            if (is_new) {
+                uint8_t any = 0;
+                for (int32_t r = st; r < st + len; ++r) {
+                    newh[r] = (*is_new)[P.h_perm[r]];
+                    any |= newh[r];
+                }
+                tnew.push_back(any);
+            }
         }
-    const int64_t ntiles = (int64_t)tiles.size() / 3;
-    DevBuf d_tiles, tv, tcnt, toff, tpT, tpU, pknn;
-    h2d(d_tiles, tiles, s);
-    tv.alloc(8 * (size_t)(ntiles * words));
-    launch_tile_vmask(s, ntiles, d_tiles.as<int32_t>(), ps.v_rows.as<uint64_t>(), words, tv.as<uint64_t>());
-    tcnt.alloc(4 * (size_t)ntiles);
-    toff.alloc(8 * (size_t)(ntiles + 1));
-    launch_tile_pairs(s, ntiles, d_tiles.as<int32_t>(), tv.as<uint64_t>(), words, nullptr, tcnt.as<int32_t>(), nullptr,
-                      nullptr);
-    launch_scan_i32_to_i64(s, tcnt.as<int32_t>(), ntiles, toff.as<int64_t>());
+    P.ntiles = (int64_t)tiles.size() / 3;
+    h2d(P.tiles, tiles, s);
+    P.tv.alloc(8 * (size_t)std::max<int64_t>(P.ntiles * words, 1));
+    launch_tile_vmask(s, P.ntiles, P.tiles.as<int32_t>(), P.v_rows.as<uint64_t>(), words, P.tv.as<uint64_t>());
+    if (is_new) {
+        h2d(P.is_new, newh, s);
+        h2d(P.tnew, tnew, s);
+    }
+}
+
+PointsView view_of(const PointState &P, bool with_new) {
+    return PointsView{P.Xh.as<double>(),   P.nrmh.as<double>(),  P.par_off.as<int64_t>(),
+                      P.par_idx.as<int32_t>(), P.v_rows.as<uint64_t>(), P.g_cols.as<uint64_t>(),
+                      P.nw,                 P.tiles.as<int32_t>(), with_new ? P.is_new.as<uint8_t>() : nullptr};
+}
+
+// Stages I-V over candidate tile pairs of A (row side) x B (indexed side).
+void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const PointState &A, const PointState &B,
+               int mode, Pairs &P, DevBuf &dmax, int64_t &np, BuildTimes &bt) {
+    hipStream_t s = idx->stream;
+    const int32_t words = L.words;
+    const int32_t K = idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK;
+    uint64_t *ctr = idx->counters.as<uint64_t>();
+    const bool with_new = (mode & PM_NEW_ONLY) != 0;
+    DevBuf tcnt, toff, tpT, tpU;
+    tcnt.alloc(4 * (size_t)std::max<int64_t>(A.ntiles, 1));
+    toff.alloc(8 * (size_t)(A.ntiles + 1));
+    const uint8_t *na = with_new ? A.tnew.as<uint8_t>() : nullptr, *nb = with_new ? B.tnew.as<uint8_t>() : nullptr;
+    launch_tile_pairs(s, A.ntiles, A.tiles.as<int32_t>(), A.tv.as<uint64_t>(), na, B.ntiles, B.tiles.as<int32_t>(),
+                      B.tv.as<uint64_t>(), nb, words, mode, nullptr, tcnt.as<int32_t>(), nullptr, nullptr);
+    launch_scan_i32_to_i64(s, tcnt.as<int32_t>(), A.ntiles, toff.as<int64_t>());
     std::vector<int64_t> ntp_h;
-    d2h(ntp_h, toff.as<int64_t>() + ntiles, 1, s);
+    d2h(ntp_h, toff.as<int64_t>() + A.ntiles, 1, s);
     const int64_t ntp = ntp_h[0];
     tpT.alloc(4 * (size_t)std::max<int64_t>(ntp, 1));
     tpU.alloc(4 * (size_t)std::max<int64_t>(ntp, 1));
-    launch_tile_pairs(s, ntiles, d_tiles.as<int32_t>(), tv.as<uint64_t>(), words, toff.as<int64_t>(),
-                      tcnt.as<int32_t>(), tpT.as<int32_t>(), tpU.as<int32_t>());
-    pknn.alloc(4 * (size_t)(m * kPivWitness));
-    launch_pivot_knn(s, m, L.dpp2.as<double>(), pknn.as<int32_t>());
-    // Stages I-V over the tile pairs -> pairs left for the exhaustive scan.
-    Pairs P;
-    DevBuf dmax;
-    dmax.alloc(8 * (size_t)n);
-    int64_t cap = std::max<int64_t>(1 << 22, 64 * n);
-    int64_t np = 0;
+    launch_tile_pairs(s, A.ntiles, A.tiles.as<int32_t>(), A.tv.as<uint64_t>(), na, B.ntiles, B.tiles.as<int32_t>(),
+                      B.tv.as<uint64_t>(), nb, words, mode, toff.as<int64_t>(), tcnt.as<int32_t>(), tpT.as<int32_t>(),
+                      tpU.as<int32_t>());
+    dmax.alloc(8 * (size_t)std::max<int64_t>(A.n, 1));
+    int64_t cap = std::max<int64_t>(1 << 22, 64 * A.n);
     std::vector<uint64_t> snapshot;
     d2h(snapshot, idx->counters.p, C_NUM, s);
+    const PointsView va = view_of(A, with_new), vb = view_of(B, with_new);
     for (int attempt = 0; attempt < 3; ++attempt) {
         P.reserve(cap);
         zero(P.count, s);
         zero(dmax, s);
         EventTimer pt(s);
-        launch_pairs_tiled(s, ntp, tpT.as<int32_t>(), tpU.as<int32_t>(), d_tiles.as<int32_t>(), dp, ps.Xh.as<double>(),
-                           ps.nrmh.as<double>(), ps.par_off.as<int64_t>(), ps.par_idx.as<int32_t>(),
-                           ps.v_rows.as<uint64_t>(), ps.g_cols.as<uint64_t>(), words, nw, pknn.as<int32_t>(), K,
-                           Xp.as<double>(), nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
-        bt.pairs = pt.stop();
-        bt.tile_pairs = ntp;
+        launch_pairs_tiled(s, ntp, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, idx->dp, words,
+                           aux.pknn.as<int32_t>(), K, aux.Xp.as<double>(), aux.nrmp.as<double>(), P.view(),
+                           dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
+        bt.pairs += pt.stop();
         std::vector<uint64_t> h;
         d2h(h, P.count.p, 1, s);
         np = (int64_t)h[0];
         if (np <= cap) break;
         require(attempt < 2, GRNG_EDEVICE, "survivor count changed between identical passes");
-        // Rerun with room for every survivor, from the counters as they were.
-        cap = np;
+        cap = np;   // rerun with room for every survivor, from the counters as they were
         GRNG_HIP(hipMemcpyAsync(idx->counters.p, snapshot.data(), 8 * C_NUM, hipMemcpyHostToDevice, s));
         GRNG_HIP(hipStreamSynchronize(s));
     }
-    // Witness cells per row point (Proposition 3, x side), sorted by distance.
-    DevBuf rel_cnt, rel_off, rel_grp, rel_d2x;
-    rel_cnt.alloc(4 * (size_t)n);
-    rel_off.alloc(8 * (size_t)(n + 1));
-    launch_relevant_groups(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), ps.dvor.as<double>(),
-                           gcount.as<int32_t>(), dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr,
-                           nullptr);
-    launch_scan_i32_to_i64(s, rel_cnt.as<int32_t>(), n, rel_off.as<int64_t>());
-    std::vector<int64_t> tot;
-    d2h(tot, rel_off.as<int64_t>() + n, 1, s);
-    rel_grp.alloc(4 * (size_t)std::max<int64_t>(tot[0], 1));
-    rel_d2x.alloc(8 * (size_t)std::max<int64_t>(tot[0], 1));
-    launch_relevant_groups(s, n, m, ps.perm.as<int32_t>(), dxp.as<double>(), ps.dvor.as<double>(),
-                           gcount.as<int32_t>(), dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(),
-                           rel_grp.as<int32_t>(), rel_d2x.as<double>());
-    // Order the survivors by row point: neighbouring pairs then share their
-    // witness cells, which the lune kernel keeps in one XCD's L2.
+    bt.tile_pairs += ntp;
+}
+
+// Stages IV-VI: sort pairs by row point, list the witness cells of each row
+// point (Proposition 3, x side), then the exhaustive lune scan.
+//   X: row side (indexed set or query set), S: indexed set (witnesses).
+//   cell_filter: cells that may hold witnesses (S.gcount, or new-point counts).
+//   zstart: first witness position per cell (Stage VII: the inserted points), or null.
+void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const PointState &X, const PointState &S,
+                    Pairs &P, int64_t np, const DevBuf &dmax, const int32_t *cell_filter, const int32_t *zstart,
+                    DevBuf &alive, BuildTimes &bt) {
+    hipStream_t s = idx->stream;
+    const int64_t n = X.n, m = L.m;
+    uint64_t *ctr = idx->counters.as<uint64_t>();
     {
         DevBuf cnt, roff, sx, sy, sd2;
         cnt.alloc(4 * (size_t)std::max<int64_t>(n + 1, 2));
@@ -494,17 +530,61 @@ void build_rng_guided(grng_index *idx, PointState &ps, DevBuf &edges, int64_t &n
         P.y = std::move(sy);
         P.d2 = std::move(sd2);
     }
-    // Stages IV-VI: exhaustive lune test of the survivors.
-    DevBuf alive;
+    DevBuf rel_cnt, rel_off, rel_grp, rel_d2x;
+    rel_cnt.alloc(4 * (size_t)n);
+    rel_off.alloc(8 * (size_t)(n + 1));
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
+                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr);
+    launch_scan_i32_to_i64(s, rel_cnt.as<int32_t>(), n, rel_off.as<int64_t>());
+    std::vector<int64_t> tot;
+    d2h(tot, rel_off.as<int64_t>() + n, 1, s);
+    rel_grp.alloc(4 * (size_t)std::max<int64_t>(tot[0], 1));
+    rel_d2x.alloc(8 * (size_t)std::max<int64_t>(tot[0], 1));
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
+                           dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(),
+                           rel_d2x.as<double>());
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
-    launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), dp, ps.Xh.as<double>(),
-                       ps.nrmh.as<double>(), ps.dhome.as<double>(), ps.grp_off.as<int32_t>(), ps.dvor.as<double>(),
-                       Xp.as<double>(), nrmp.as<double>(), rel_off.as<int64_t>(), rel_grp.as<int32_t>(),
-                       rel_d2x.as<double>(), alive.as<uint8_t>(), ctr + C_WORK0, ctr);
-    bt.lune = lt.stop();
-    pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), ps.perm.as<int32_t>(), edges,
-                   ne);
+    launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
+                       X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.dhome.as<double>(), zstart,
+                       S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),
+                       rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), alive.as<uint8_t>(),
+                       ctr + C_WORK0, ctr);
+    bt.lune += lt.stop();
+}
+
+void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &edges, int64_t &ne, BuildTimes &bt) {
+    const Layer &L = idx->layers.back();
+    prepare_aux(idx, L, aux);
+    prepare_points(idx, L, aux, idx->X.as<double>(), idx->nrm.as<double>(), idx->n, nullptr, nullptr, ps, bt);
+    Pairs P;
+    DevBuf dmax, alive;
+    int64_t np = 0;
+    run_pairs(idx, L, aux, ps, ps, PM_SELF, P, dmax, np, bt);
+    run_exhaustive(idx, L, aux, ps, ps, P, np, dmax, ps.gcount.as<int32_t>(), nullptr, alive, bt);
+    pairs_to_edges(idx->stream, idx->n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(),
+                   ps.perm.as<int32_t>(), edges, ne);
+    ps.dxp.release();   // only needed while building
+}
+
+void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
+    uint64_t c[C_NUM];
+    read_counters(idx, c);
+    idx->stats.ms_vgrng = bt.vgrng;
+    idx->stats.ms_pairs = bt.pairs;
+    idx->stats.ms_lune = bt.lune;
+    idx->stats.tile_pairs = bt.tile_pairs;
+    idx->stats.distance_computations = (double)c[C_DIST];
+    idx->stats.witness_tests = (double)c[C_WTEST];
+    idx->stats.candidate_pairs = (double)c[C_CAND];
+    idx->stats.stage4_survivors = (double)c[C_S4];
+    idx->stats.rechecks = (double)c[C_RECHECK];
+    idx->stats.exhaustive_pairs = (double)c[C_SURV];
+    idx->stats.lune_tests = (double)c[C_LUNE];
+    idx->stats.lune_bytes = (double)c[C_LUNE] * (8.0 * idx->dp + 16.0);
+    const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
+    idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * m;
+    idx->stats.pairs_flops = 2.0 * idx->dp * (64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs;
 }
 
 void do_build_rng(grng_index *idx) {
@@ -516,39 +596,212 @@ void do_build_rng(grng_index *idx) {
     int64_t ne = 0;
     BuildTimes bt;
     PointState ps;
+    LayerAux aux;
     if (idx->layers.empty()) {
         require(idx->n <= 65535, GRNG_EINVAL, "without a pivot layer build_rng is limited to 65535 points");
         build_rng_brute(idx, edges, ne, bt.lune);
     } else {
-        build_rng_guided(idx, ps, edges, ne, bt);
+        build_rng_guided(idx, ps, aux, edges, ne, bt);
     }
     const double ms = timer.stop();
-    uint64_t c[C_NUM];
-    read_counters(idx, c);
     idx->edges = std::move(edges);
     idx->nedges = ne;
     idx->ps = std::move(ps);
+    idx->aux = std::move(aux);
     idx->rng_built = true;
     idx->stats.n_edges = ne;
     idx->stats.orphans = idx->ps.orphans;
     idx->stats.ms_rng = ms;
-    idx->stats.ms_vgrng = bt.vgrng;
-    idx->stats.ms_pairs = bt.pairs;
-    idx->stats.ms_lune = bt.lune;
-    idx->stats.tile_pairs = bt.tile_pairs;
-    {
-        const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
-        idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * m;
-        idx->stats.pairs_flops = 2.0 * idx->dp * (64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs;
+    fill_build_stats(idx, bt);
+}
+
+// Convert and validate a float32 point batch into exact float64 rows.
+double upload_points(grng_index *idx, const float *pts, int64_t count, DevBuf &X, DevBuf &nrm, const char *what) {
+    require(pts != nullptr, GRNG_EINVAL, std::string(what) + " pointer is NULL");
+    const double km = std::max(grid_validate(idx, pts, count * (int64_t)idx->d, what), idx->kmax);
+    check_magnitude(idx, km);
+    X.alloc(sizeof(double) * (size_t)(count * idx->dp));
+    nrm.alloc(sizeof(double) * (size_t)count);
+    launch_to_f64(idx->stream, pts, count, idx->d, idx->dp, X.as<double>(), nrm.as<double>());
+    return km;
+}
+
+void do_query(grng_index *idx, const float *q, int64_t nq, int64_t *offsets, int32_t *nbrs, int64_t capacity,
+              int64_t *needed) {
+    require(idx != nullptr && offsets != nullptr && needed != nullptr, GRNG_EINVAL, "NULL argument");
+    require(nq >= 1 && nq <= (int64_t)INT32_MAX - 1, GRNG_EINVAL, "nq must be >= 1");
+    require(capacity >= 0, GRNG_EINVAL, "capacity must be >= 0");
+    require(idx->rng_built, GRNG_ESTATE, "build_rng must run before query_neighbors");
+    hipStream_t s = idx->stream;
+    EventTimer timer(s);
+    reset_counters(idx);
+    DevBuf Xq, nq2;
+    upload_points(idx, q, nq, Xq, nq2, "queries");
+    Pairs P;
+    DevBuf alive;
+    int64_t np = 0;
+    const int32_t *qperm = nullptr, *sperm = nullptr;
+    PointState Q;
+    BuildTimes bt;
+    if (idx->layers.empty()) {
+        require(nq <= 65535, GRNG_EINVAL, "without a pivot layer query_neighbors takes at most 65535 queries");
+        np = nq * idx->n;
+        P.reserve(np);
+        zero(P.count, s);
+        launch_pairs_all(s, nq, Xq.as<double>(), nq2.as<double>(), idx->n, idx->X.as<double>(), idx->nrm.as<double>(),
+                         idx->dp, false, P.view(), idx->counters.as<uint64_t>());
+        alive.alloc((size_t)std::max<int64_t>(np, 8));
+        EventTimer lt(s);
+        launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->n, idx->dp,
+                        Xq.as<double>(), nq2.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0,
+                        alive.as<uint8_t>(), idx->counters.as<uint64_t>());
+        bt.lune = lt.stop();
+    } else {
+        const Layer &L = idx->layers.back();
+        PointState &S = idx->ps;
+        prepare_points(idx, L, idx->aux, Xq.as<double>(), nq2.as<double>(), nq, &S, nullptr, Q, bt);
+        DevBuf dmax;
+        run_pairs(idx, L, idx->aux, Q, S, 0, P, dmax, np, bt);
+        run_exhaustive(idx, L, idx->aux, Q, S, P, np, dmax, S.gcount.as<int32_t>(), nullptr, alive, bt);
+        qperm = Q.perm.as<int32_t>();
+        sperm = S.perm.as<int32_t>();
     }
-    idx->stats.distance_computations = (double)c[C_DIST];
+    // CSR per query, neighbours ascending.
+    DevBuf deg, fill;
+    deg.alloc(4 * (size_t)std::max<int64_t>(nq, 2));
+    fill.alloc(4 * (size_t)std::max<int64_t>(nq, 2));
+    zero(deg, s);
+    zero(fill, s);
+    launch_query_csr(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), qperm, sperm, nq,
+                     deg.as<int32_t>(), nullptr, nullptr, nullptr, 0);
+    launch_scan_i32_to_i64(s, deg.as<int32_t>(), nq, offsets);
+    std::vector<int64_t> tot;
+    d2h(tot, offsets + nq, 1, s);
+    *needed = tot[0];
+    if (tot[0] > capacity) throw Error(GRNG_ECAPACITY, "neighbour buffer too small");
+    if (tot[0] > 0) {
+        require(nbrs != nullptr, GRNG_EINVAL, "neighbour pointer is NULL");
+        launch_query_csr(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), qperm, sperm, nq,
+                         deg.as<int32_t>(), offsets, fill.as<int32_t>(), nbrs, 1);
+        launch_sort_segments(s, nq, offsets, nbrs);
+    }
+    idx->stats.ms_query = timer.stop();
+    uint64_t c[C_NUM];
+    read_counters(idx, c);
     idx->stats.witness_tests = (double)c[C_WTEST];
-    idx->stats.candidate_pairs = (double)c[C_CAND];
-    idx->stats.stage4_survivors = (double)c[C_S4];
-    idx->stats.rechecks = (double)c[C_RECHECK];
-    idx->stats.exhaustive_pairs = (double)c[C_SURV];
     idx->stats.lune_tests = (double)c[C_LUNE];
-    idx->stats.lune_bytes = (double)c[C_LUNE] * (8.0 * idx->dp + 16.0);
+}
+
+void do_insert(grng_index *idx, const float *pts, int64_t nb) {
+    require(idx != nullptr, GRNG_EINVAL, "index is NULL");
+    require(nb >= 1, GRNG_EINVAL, "nb must be >= 1");
+    require(idx->n + nb <= (int64_t)INT32_MAX - 1, GRNG_EINVAL, "too many points");
+    require(idx->rng_built, GRNG_ESTATE, "build_rng must run before insert_batch");
+    hipStream_t s = idx->stream;
+    EventTimer timer(s);
+    reset_counters(idx);
+    DevBuf Xb, nrmb;
+    const double kmax_new = upload_points(idx, pts, nb, Xb, nrmb, "points");
+    const int64_t n0 = idx->n, n1 = n0 + nb;
+    const int dp = idx->dp;
+    // New point arena: old rows then the batch (ids n0 .. n1-1).
+    DevBuf X1, nrm1;
+    X1.alloc(sizeof(double) * (size_t)(n1 * dp));
+    nrm1.alloc(sizeof(double) * (size_t)n1);
+    GRNG_HIP(hipMemcpyAsync(X1.p, idx->X.p, sizeof(double) * (size_t)(n0 * dp), hipMemcpyDeviceToDevice, s));
+    GRNG_HIP(hipMemcpyAsync(X1.as<double>() + n0 * dp, Xb.p, sizeof(double) * (size_t)(nb * dp),
+                            hipMemcpyDeviceToDevice, s));
+    GRNG_HIP(hipMemcpyAsync(nrm1.p, idx->nrm.p, sizeof(double) * (size_t)n0, hipMemcpyDeviceToDevice, s));
+    GRNG_HIP(hipMemcpyAsync(nrm1.as<double>() + n0, nrmb.p, sizeof(double) * (size_t)nb, hipMemcpyDeviceToDevice, s));
+    DevBuf edges;
+    int64_t ne = 0;
+    BuildTimes bt;
+    PointState ps;
+    if (idx->layers.empty()) {
+        // Without a pivot layer the insertion is a plain exhaustive rebuild.
+        require(n1 <= 65535, GRNG_EINVAL, "without a pivot layer the index is limited to 65535 points");
+        std::swap(idx->X, X1);
+        std::swap(idx->nrm, nrm1);
+        const int64_t n_save = idx->n;
+        idx->n = n1;
+        try {
+            build_rng_brute(idx, edges, ne, bt.lune);
+        } catch (...) {
+            std::swap(idx->X, X1);
+            std::swap(idx->nrm, nrm1);
+            idx->n = n_save;
+            throw;
+        }
+    } else {
+        const Layer &L = idx->layers.back();
+        LayerAux &aux = idx->aux;
+        std::vector<uint8_t> is_new((size_t)n1, 0);
+        for (int64_t x = n0; x < n1; ++x) is_new[x] = 1;
+        prepare_points(idx, L, aux, X1.as<double>(), nrm1.as<double>(), n1, nullptr, &is_new, ps, bt);
+        // Localization of the new points (Stages I-VI) against S u B: pairs with a new end.
+        Pairs Pn;
+        DevBuf dmax_n, alive_n;
+        int64_t np_n = 0;
+        run_pairs(idx, L, aux, ps, ps, PM_SELF | PM_NEW_ONLY, Pn, dmax_n, np_n, bt);
+        run_exhaustive(idx, L, aux, ps, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
+        // Stage VII (Proposition 5): an existing edge survives iff no inserted
+        // point lies in its lune; only the inserted points are witnesses (home
+        // cells keep old points first, so they are a suffix of each cell).
+        const int64_t m = L.m;
+        std::vector<int32_t> newcount((size_t)m, 0), zst((size_t)m);
+        for (int64_t c = 0; c < m; ++c) {
+            int32_t old = 0;
+            for (int32_t r = ps.h_off[c]; r < ps.h_off[c + 1]; ++r) old += ps.h_perm[r] < n0;
+            zst[c] = ps.h_off[c] + old;
+            newcount[c] = ps.h_off[c + 1] - zst[c];
+        }
+        DevBuf d_newcount, d_zst;
+        h2d(d_newcount, newcount, s);
+        h2d(d_zst, zst, s);
+        const int64_t ne0 = idx->nedges;
+        Pairs Po;
+        Po.reserve(ne0);
+        DevBuf dmax_o, alive_o;
+        dmax_o.alloc(8 * (size_t)n1);
+        zero(dmax_o, s);
+        launch_edges_to_pairs(s, ne0, idx->edges.as<int32_t>(), ps.inv.as<int32_t>(), Po.x.as<int32_t>(),
+                              Po.y.as<int32_t>());
+        launch_pair_d2(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), dp, ps.Xh.as<double>(), ps.nrmh.as<double>(),
+                       Po.d2.as<double>(), dmax_o.as<uint64_t>());
+        run_exhaustive(idx, L, aux, ps, ps, Po, ne0, dmax_o, d_newcount.as<int32_t>(), d_zst.as<int32_t>(), alive_o,
+                       bt);
+        // Merge: surviving old edges and new edges.
+        Pairs Pm;
+        Pm.reserve(ne0 + np_n);
+        DevBuf alive_m;
+        alive_m.alloc((size_t)std::max<int64_t>(ne0 + np_n, 8));
+        auto cat = [&](DevBuf &dst, const DevBuf &a, const DevBuf &b, size_t el, int64_t na, int64_t nb2) {
+            if (na) GRNG_HIP(hipMemcpyAsync(dst.p, a.p, el * (size_t)na, hipMemcpyDeviceToDevice, s));
+            if (nb2)
+                GRNG_HIP(hipMemcpyAsync(static_cast<char *>(dst.p) + el * (size_t)na, b.p, el * (size_t)nb2,
+                                        hipMemcpyDeviceToDevice, s));
+        };
+        cat(Pm.x, Po.x, Pn.x, 4, ne0, np_n);
+        cat(Pm.y, Po.y, Pn.y, 4, ne0, np_n);
+        cat(alive_m, alive_o, alive_n, 1, ne0, np_n);
+        pairs_to_edges(s, n1, ne0 + np_n, Pm.x.as<int32_t>(), Pm.y.as<int32_t>(), alive_m.as<uint8_t>(),
+                       ps.perm.as<int32_t>(), edges, ne);
+        ps.dxp.release();
+        idx->ps = std::move(ps);
+        std::swap(idx->X, X1);
+        std::swap(idx->nrm, nrm1);
+        idx->n = n1;
+    }
+    const double ms = timer.stop();
+    idx->cap = idx->n;
+    idx->kmax = kmax_new;
+    idx->edges = std::move(edges);
+    idx->nedges = ne;
+    idx->stats.n_points = idx->n;
+    idx->stats.n_edges = ne;
+    idx->stats.orphans = idx->ps.orphans;
+    idx->stats.ms_insert = ms;
+    fill_build_stats(idx, bt);
 }
 
 void do_get_edges(const grng_index *idx, int32_t layer, int32_t *uv, int64_t capacity, int64_t *num) {
@@ -641,23 +894,12 @@ grng_status grng_build_rng(grng_index *idx) {
 }
 
 grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t nb) {
-    return guarded([&] {
-        require(idx != nullptr && points_dev != nullptr, GRNG_EINVAL, "NULL argument");
-        require(nb >= 1, GRNG_EINVAL, "nb must be >= 1");
-        throw Error(GRNG_ESTATE, "insert_batch is not available in this build");
-    });
+    return guarded([&] { do_insert(idx, points_dev, nb); });
 }
 
 grng_status grng_query_neighbors(grng_index *idx, const float *q_dev, int64_t nq, int64_t *offsets_dev,
                                  int32_t *nbrs_dev, int64_t capacity, int64_t *needed) {
-    return guarded([&] {
-        require(idx != nullptr && q_dev != nullptr && offsets_dev != nullptr && needed != nullptr, GRNG_EINVAL,
-                "NULL argument");
-        (void)nq;
-        (void)nbrs_dev;
-        (void)capacity;
-        throw Error(GRNG_ESTATE, "query_neighbors is not available in this build");
-    });
+    return guarded([&] { do_query(idx, q_dev, nq, offsets_dev, nbrs_dev, capacity, needed); });
 }
 
 grng_status grng_get_edges(const grng_index *idx, int32_t layer, int32_t *uv_dev, int64_t capacity,

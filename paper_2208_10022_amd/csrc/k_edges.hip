@@ -90,9 +90,89 @@ __global__ void k_bits_emit(int64_t m, const uint64_t *bits, int32_t words, cons
     }
 }
 
+// Exact d^2 of listed pairs (one set, home order) and the per-row maximum.
+__global__ void k_pair_d2(int64_t np, const int32_t *px, const int32_t *py, int dp, const double *Xh,
+                          const double *nrmh, double *d2, unsigned long long *dmax_bits) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int64_t x = px[p], y = py[p];
+    double acc = 0.0;
+    for (int t = 0; t < dp; ++t) acc = fma(Xh[x * dp + t], Xh[y * dp + t], acc);
+    const double v = nrmh[x] + nrmh[y] - 2.0 * acc;
+    d2[p] = v;
+    atomicMax(&dmax_bits[x], (unsigned long long)__double_as_longlong(v));
+}
+
+// Query output: pass 0 counts neighbours per query, pass 1 scatters the
+// neighbour's point id into the query's CSR segment.
+__global__ void k_query_csr(int64_t np, const int32_t *px, const int32_t *py, const uint8_t *alive,
+                            const int32_t *qperm, const int32_t *perm, int32_t *deg, const int64_t *off,
+                            int32_t *fill, int32_t *nbr, int pass) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= np || !alive[p]) return;
+    const int32_t q = qperm ? qperm[px[p]] : px[p];
+    const int32_t v = perm ? perm[py[p]] : py[p];
+    if (pass == 0) {
+        atomicAdd(&deg[q], 1);
+    } else {
+        nbr[off[q] + atomicAdd(&fill[q], 1)] = v;
+    }
+}
+
+__global__ void k_sort_segments(int64_t nseg, const int64_t *off, int32_t *vals) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nseg) return;
+    const int64_t b = off[i], e = off[i + 1];
+    for (int64_t s = b + 1; s < e; ++s) {
+        const int32_t v = vals[s];
+        int64_t t = s - 1;
+        while (t >= b && vals[t] > v) {
+            vals[t + 1] = vals[t];
+            --t;
+        }
+        vals[t + 1] = v;
+    }
+}
+
+// Existing edges (point ids) -> pairs of home-order positions.
+__global__ void k_edges_to_pairs(int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    px[e] = inv[uv[2 * e]];
+    py[e] = inv[uv[2 * e + 1]];
+}
+
 inline unsigned grid1(int64_t work) { return (unsigned)(div_up(work, 256) < 1 ? 1 : div_up(work, 256)); }
 
 }  // namespace
+
+void launch_pair_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *Xh,
+                    const double *nrmh, double *d2, uint64_t *dmax_bits) {
+    if (np == 0) return;
+    k_pair_d2<<<grid1(np), 256, 0, s>>>(np, px, py, dp, Xh, nrmh, d2, (unsigned long long *)dmax_bits);
+    GRNG_LAUNCHED();
+}
+
+void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,
+                      const int32_t *qperm, const int32_t *perm, int64_t nq, int32_t *deg, const int64_t *off,
+                      int32_t *fill, int32_t *nbr, int pass) {
+    (void)nq;
+    if (npairs == 0) return;
+    k_query_csr<<<grid1(npairs), 256, 0, s>>>(npairs, px, py, alive, qperm, perm, deg, off, fill, nbr, pass);
+    GRNG_LAUNCHED();
+}
+
+void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py) {
+    if (ne == 0) return;
+    k_edges_to_pairs<<<grid1(ne), 256, 0, s>>>(ne, uv, inv, px, py);
+    GRNG_LAUNCHED();
+}
+
+void launch_sort_segments(hipStream_t s, int64_t nseg, const int64_t *off, int32_t *vals) {
+    if (nseg == 0) return;
+    k_sort_segments<<<grid1(nseg), 256, 0, s>>>(nseg, off, vals);
+    GRNG_LAUNCHED();
+}
 
 void launch_edges_count(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,
                         const int32_t *perm, int32_t *deg) {

@@ -403,16 +403,27 @@ void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const do
     GRNG_LAUNCHED();
 }
 
-void launch_point_pass2(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
-                        const double *rad, const double *dpp, const double *dvor, const int32_t *gcount,
-                        const uint64_t *layer_bits, int32_t words, const int64_t *par_off, int32_t *par_idx,
-                        float *bd, float *bv, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
+void launch_parents(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const double *rad,
+                    const int64_t *par_off, int32_t *par_idx) {
     if (n == 0) return;
     k_parents<<<(unsigned)div_up(n, 4), 256, 0, s>>>(n, m, perm, dxp, rad, par_off, par_idx);
     GRNG_LAUNCHED();
+}
+
+void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, const double *rad, const double *dvor,
+                                float *bd, float *bv) {
+    if (m == 0) return;
     k_shifted_pivot_dists<<<(unsigned)div_up(m * m, 256), 256, 0, s>>>(m, dpp, rad, dvor, bd, bv);
     GRNG_LAUNCHED();
+}
+
+void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
+                  const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
+                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, uint64_t *g_rows, uint64_t *v_rows,
+                  uint64_t *counters) {
+    if (n == 0) return;
     dim3 g((unsigned)div_up(n, kVT_X), (unsigned)div_up(m, kVT_J));
+    require(g.y <= 65535u, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
     k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits, words,
                                     g_rows, v_rows, (unsigned long long *)counters);
     GRNG_LAUNCHED();

@@ -101,13 +101,13 @@ __device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) 
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_pairs_tiled(
-    int64_t ntp, const int32_t *__restrict__ tpT, const int32_t *__restrict__ tpU, const int32_t *__restrict__ tiles,
-    int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const int64_t *__restrict__ par_off,
-    const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ v_rows, const uint64_t *__restrict__ g_cols,
-    int32_t words, int64_t nw, const int32_t *__restrict__ pknn, int32_t K, const double *__restrict__ Xp,
-    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *work,
-    unsigned long long *counters) {
+__global__ __launch_bounds__(256) void k_pairs_tiled(int64_t ntp, const int32_t *__restrict__ tpT,
+                                                    const int32_t *__restrict__ tpU, PointsView A, PointsView B,
+                                                    int mode, int dp, int32_t words, const int32_t *__restrict__ pknn,
+                                                    int32_t K, const double *__restrict__ Xp,
+                                                    const double *__restrict__ nrmp, PairList out,
+                                                    unsigned long long *dmax_bits, unsigned long long *work,
+                                                    unsigned long long *counters) {
     // LDS: rows of T, U and the pivot witnesses (ld = dp + 1 doubles per row),
     // norms, d^2 to the pivots (float, rounded up), candidate masks and the
     // 64 x 64 bit mask of Stage IV survivors.
@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
     float *XP = (float *)(surv + kTile), *YP = XP + kTile * (kPiv + 1);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int il = lane & 15, kl = lane >> 4;
+    const bool self = (mode & PM_SELF) != 0;
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntests = 0;
     __shared__ int64_t s_tp;
     const int xcd0 = blockIdx.x % kXcds;
@@ -142,13 +143,13 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
         __syncthreads();
         if (tp < 0) break;
         const int32_t T = tpT[tp], U = tpU[tp];
-        const int32_t sT = tiles[3 * T], lT = tiles[3 * T + 1], a = tiles[3 * T + 2];
-        const int32_t sU = tiles[3 * U], lU = tiles[3 * U + 1], b = tiles[3 * U + 2];
+        const int32_t sT = A.tiles[3 * T], lT = A.tiles[3 * T + 1], a = A.tiles[3 * T + 2];
+        const int32_t sU = B.tiles[3 * U], lU = B.tiles[3 * U + 1], b = B.tiles[3 * U + 2];
         // 1. rows, norms, pivot witnesses, candidate masks -> LDS
         for (int e = tid; e < kTile * dp; e += 256) {
             const int r = e / dp, c = e % dp;
-            sX[r * ld + c] = r < lT ? Xh[(int64_t)(sT + r) * dp + c] : 0.0;
-            sY[r * ld + c] = r < lU ? Xh[(int64_t)(sU + r) * dp + c] : 0.0;
+            sX[r * ld + c] = r < lT ? A.Xh[(int64_t)(sT + r) * dp + c] : 0.0;
+            sY[r * ld + c] = r < lU ? B.Xh[(int64_t)(sU + r) * dp + c] : 0.0;
         }
         const int ka = (a == b) ? K : (K + 1) / 2;
         for (int e = tid; e < kPiv * dp; e += 256) {
@@ -162,16 +163,20 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
             nP[t] = nrmp[pv];
         }
         if (tid < kTile) {
+            // wave 0: rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
             const int r = tid;
+            uint64_t newU = ~0ull;
+            if (mode & PM_NEW_ONLY) newU = __ballot(r < lU && B.is_new[sU + r]);
             uint64_t mk = 0;
             double nv = 0.0;
             if (r < lT) {
                 const int64_t x = sT + r;
-                nv = nrmh[x];
-                mk = ((v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
-                for (int64_t q = par_off[x]; q < par_off[x + 1] && mk; ++q)
-                    mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sU, lU);
-                if (T == U) mk &= r == 63 ? 0ull : (~0ull << (r + 1));   // y > x inside one tile
+                nv = A.nrmh[x];
+                mk = ((A.v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
+                for (int64_t q = A.par_off[x]; q < A.par_off[x + 1] && mk; ++q)
+                    mk &= bits_at(B.g_cols + (int64_t)A.par_idx[q] * B.nw, sU, lU);
+                if (self && T == U) mk &= r == 63 ? 0ull : (~0ull << (r + 1));   // y > x inside one tile
+                if ((mode & PM_NEW_ONLY) && !A.is_new[x]) mk &= newU;           // a new point on one side
                 mk &= lU == 64 ? ~0ull : ((1ull << lU) - 1ull);
             }
             nX[r] = nv;
@@ -183,10 +188,12 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
             double nv = 0.0;
             if (r < lU) {
                 const int64_t y = sU + r;
-                nv = nrmh[y];
-                mk = ((v_rows[y * words + (a >> 6)] >> (a & 63)) & 1ull) ? ~0ull : 0ull;
-                for (int64_t q = par_off[y]; q < par_off[y + 1] && mk; ++q)
-                    mk &= bits_at(g_cols + (int64_t)par_idx[q] * nw, sT, lT);
+                nv = B.nrmh[y];
+                // The cell test needs the row points inside the cell ball of a:
+                // true for indexed points, not for queries.
+                mk = (!self || ((B.v_rows[y * words + (a >> 6)] >> (a & 63)) & 1ull)) ? ~0ull : 0ull;
+                for (int64_t q = B.par_off[y]; q < B.par_off[y + 1] && mk; ++q)
+                    mk &= bits_at(A.g_cols + (int64_t)B.par_idx[q] * A.nw, sT, lT);
             }
             nY[r] = nv;
             mY[r] = mk;
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(
                 for (int c = 0; c < dp; ++c) sxy = fma(xr[c], yr[c], sxy);
                 const double dd = nX[i] + nY[j] - 2.0 * sxy;   // exact
                 bool wit = false;
-                for (int half = 0; half < 2 && !wit; ++half) {
+                for (int half = self ? 0 : 1; half < 2 && !wit; ++half) {
                     bool wz = false;
                     if (lane < (half == 0 ? lT : lU)) {
                         const double *zr = (half == 0 ? sX : sY) + lane * ld;
@@ -330,20 +337,27 @@ __global__ void k_tile_vmask(int64_t ntiles, const int32_t *tiles, const uint64_
     tv[e] = acc;
 }
 
-__global__ __launch_bounds__(64) void k_tile_pairs(int64_t ntiles, const int32_t *tiles, const uint64_t *tv,
-                                                   int32_t words, const int64_t *off, int32_t *cnt, int32_t *oT,
-                                                   int32_t *oU) {
+__global__ __launch_bounds__(64) void k_tile_pairs(int64_t ntA, const int32_t *tilesA, const uint64_t *tvA,
+                                                   const uint8_t *newA, int64_t ntB, const int32_t *tilesB,
+                                                   const uint64_t *tvB, const uint8_t *newB, int32_t words, int mode,
+                                                   const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
     const int lane = threadIdx.x;
     const int64_t T = blockIdx.x;
-    const int32_t a = tiles[3 * T + 2];
+    const int32_t a = tilesA[3 * T + 2];
+    const bool tnew = newA ? newA[T] != 0 : false;
     int64_t pos = off ? off[T] : 0;
     int c = 0;
-    for (int64_t u0 = T; u0 < ntiles; u0 += 64) {
+    for (int64_t u0 = (mode & PM_SELF) ? T : 0; u0 < ntB; u0 += 64) {
         const int64_t U = u0 + lane;
         bool keep = false;
-        if (U < ntiles) {
-            const int32_t b = tiles[3 * U + 2];
-            keep = ((tv[T * words + (b >> 6)] >> (b & 63)) & 1ull) && ((tv[U * words + (a >> 6)] >> (a & 63)) & 1ull);
+        if (U < ntB) {
+            const int32_t b = tilesB[3 * U + 2];
+            // Cell b must survive the virtual-pivot test of some point of T; when
+            // the row points are indexed points (their cell balls contain them),
+            // cell a must also survive the test of some point of U.
+            keep = (tvA[T * words + (b >> 6)] >> (b & 63)) & 1ull;
+            if (keep && (mode & PM_SELF)) keep = (tvB[U * words + (a >> 6)] >> (a & 63)) & 1ull;
+            if ((mode & PM_NEW_ONLY) && !tnew && !newB[U]) keep = false;
         }
         const uint64_t m = __ballot(keep);
         if (off && keep) {
@@ -381,17 +395,19 @@ __global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2,
     }
 }
 
-// All pairs i < j (no pivot layer).  Thread per pair, one block row per i.
-__global__ void k_pairs_all(int64_t n, int dp, const double *__restrict__ X, const double *__restrict__ nrm,
-                            PairList out, uint64_t *dmax_bits, unsigned long long *counters) {
+// All pairs (no pivot layer): i < j within one set, or every (i, j) across
+// two sets.  Thread per pair, one block row per i.
+__global__ void k_pairs_all(int64_t nA, const double *__restrict__ XA, const double *__restrict__ nrmA, int64_t nB,
+                            const double *__restrict__ XB, const double *__restrict__ nrmB, int dp, int self,
+                            PairList out, unsigned long long *counters) {
     const int64_t i = blockIdx.y;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool keep = j > i && j < n;
+    const bool keep = j < nB && (!self || j > i);
     double d2 = 0.0;
     if (keep) {
         double acc = 0.0;
-        for (int t = 0; t < dp; ++t) acc = fma(X[i * dp + t], X[j * dp + t], acc);
-        d2 = nrm[i] + nrm[j] - 2.0 * acc;
+        for (int t = 0; t < dp; ++t) acc = fma(XA[i * dp + t], XB[j * dp + t], acc);
+        d2 = nrmA[i] + nrmB[j] - 2.0 * acc;
     }
     wave_append(out, keep, (int32_t)i, (int32_t)j, d2);
     const uint32_t c = wave_sum(keep ? 1u : 0u);
@@ -399,7 +415,6 @@ __global__ void k_pairs_all(int64_t n, int dp, const double *__restrict__ X, con
         atomicAdd(&counters[C_DIST], (unsigned long long)c);
         atomicAdd(&counters[C_CAND], (unsigned long long)c);
     }
-    (void)dmax_bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -469,7 +484,8 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, in
 // Exhaustive lune test of surviving pairs (Stages IV-VI).  One wave per pair.
 __global__ __launch_bounds__(256) void k_lune_guided(
     int64_t npairs, const int32_t *__restrict__ px, const int32_t *__restrict__ py, const double *__restrict__ pd2,
-    int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh, const double *__restrict__ dhome,
+    int dp, const double *__restrict__ Xx, const double *__restrict__ nrmx, const double *__restrict__ Xh,
+    const double *__restrict__ nrmh, const double *__restrict__ dhome, const int32_t *__restrict__ zstart,
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
     const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
     const double *__restrict__ rel_d2x, uint8_t *__restrict__ alive, unsigned long long *work,
@@ -498,9 +514,9 @@ __global__ __launch_bounds__(256) void k_lune_guided(
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
         const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
         const double d2 = pd2[p];
-        const double *xs = Xh + x * dp;
+        const double *xs = Xx + x * dp;
         const double *ys = Xh + y * dp;
-        const double nrx = nrmh[x], nry = nrmh[y];
+        const double nrx = nrmx[x], nry = nrmh[y];
         const double dxy_hi = sqrt_hi(d2);
         bool dead = false;
         const int64_t r0 = rel_off[x], r1 = rel_off[x + 1];
@@ -515,8 +531,9 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 const double d2y = nry + nrmp[g] - 2.0 * dot_lds(ys, Xp + (int64_t)g * dp, dp);
                 ++ndist;
                 ++ntests;
-                // Stage IV: the cell's pivot itself as a witness (exact).
-                if (d2x < d2 && d2y < d2) dead = true;
+                // Stage IV: the cell's pivot itself as a witness (exact); not
+                // when only part of each cell may witness (zstart given).
+                if (!zstart && d2x < d2 && d2y < d2) dead = true;
                 dxl = sqrt_lo(d2x);
                 dyl = sqrt_lo(d2y);
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
@@ -530,7 +547,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 const int32_t gg = __shfl(g, src, kWave);
                 const double gx = __shfl(dxl, src, kWave), gy = __shfl(dyl, src, kWave);
                 const double gmax = fmax(gx, gy);
-                const int64_t z0 = grp_off[gg], z1 = grp_off[gg + 1];
+                const int64_t z0 = zstart ? zstart[gg] : grp_off[gg], z1 = grp_off[gg + 1];
                 // Four 64-point chunks per ballot: more loads in flight per wave.
                 for (int64_t zb = z0; zb < z1; zb += 256) {
                     bool wit = false;
@@ -572,9 +589,10 @@ __global__ __launch_bounds__(256) void k_lune_guided(
 // Lune test against every point (no pivot layer).  One wave per pair.
 __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t *__restrict__ px,
                                                   const int32_t *__restrict__ py, const double *__restrict__ pd2,
-                                                  int64_t n, int dp, const double *__restrict__ X,
-                                                  const double *__restrict__ nrm, uint8_t *__restrict__ alive,
-                                                  unsigned long long *counters) {
+                                                  int64_t n, int dp, const double *__restrict__ Xx,
+                                                  const double *__restrict__ nrmx, const double *__restrict__ X,
+                                                  const double *__restrict__ nrm, int64_t z_from,
+                                                  uint8_t *__restrict__ alive, unsigned long long *counters) {
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -583,11 +601,11 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
         const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
         const double d2 = pd2[p];
-        const double *xs = X + x * dp;
+        const double *xs = Xx + x * dp;
         const double *ys = X + y * dp;
-        const double nrx = nrm[x], nry = nrm[y];
+        const double nrx = nrmx[x], nry = nrm[y];
         bool dead = false;
-        for (int64_t zb = 0; zb < n; zb += 64) {
+        for (int64_t zb = z_from; zb < n; zb += 64) {
             const int64_t z = zb + lane;
             bool wit = false;
             if (z < n) {
@@ -624,22 +642,23 @@ void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, cons
     GRNG_LAUNCHED();
 }
 
-void launch_tile_pairs(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *tv, int32_t words,
-                       const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
-    if (ntiles == 0) return;
-    k_tile_pairs<<<(unsigned)ntiles, 64, 0, s>>>(ntiles, tiles, tv, words, off, cnt, oT, oU);
+void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const uint64_t *tvA, const uint8_t *newA,
+                       int64_t ntB, const int32_t *tilesB, const uint64_t *tvB, const uint8_t *newB, int32_t words,
+                       int mode, const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
+    if (ntA == 0) return;
+    k_tile_pairs<<<(unsigned)ntA, 64, 0, s>>>(ntA, tilesA, tvA, newA, ntB, tilesB, tvB, newB, words, mode, off, cnt, oT,
+                                              oU);
     GRNG_LAUNCHED();
 }
 
-void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const int32_t *tiles,
-                        int dp, const double *Xh, const double *nrmh, const int64_t *par_off, const int32_t *par_idx,
-                        const uint64_t *v_rows, const uint64_t *g_cols, int32_t words, int64_t nw,
-                        const int32_t *pknn, int32_t K, const double *Xp, const double *nrmp, PairList out,
-                        uint64_t *dmax_bits, uint64_t *work, uint64_t *counters) {
+void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const PointsView &A,
+                        const PointsView &B, int mode, int dp, int32_t words, const int32_t *pknn, int32_t K,
+                        const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
+                        uint64_t *counters) {
     if (ntp == 0) return;
-    launch_fill_u64(s, work, kXcds, 0ull);
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the pair kernel");
     require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
+    launch_fill_u64(s, work, kXcds, 0ull);
     const int ld = dp + 1;
     const size_t lds = sizeof(double) * (size_t)(2 * kTile * ld + kPiv * ld + 2 * kTile + kPiv + 3 * kTile) +
                        sizeof(float) * (size_t)(2 * kTile * (kPiv + 1));
@@ -647,19 +666,18 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const in
         GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(ntp, 256 * 8));
-    k_pairs_tiled<<<(unsigned)grid, 256, lds, s>>>(ntp, tpT, tpU, tiles, dp, Xh, nrmh, par_off, par_idx, v_rows,
-                                                   g_cols, words, nw, pknn, K, Xp, nrmp, out,
+    k_pairs_tiled<<<(unsigned)grid, 256, lds, s>>>(ntp, tpT, tpU, A, B, mode, dp, words, pknn, K, Xp, nrmp, out,
                                                    (unsigned long long *)dmax_bits, (unsigned long long *)work,
                                                    (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
-void launch_pairs_all(hipStream_t s, int64_t n, int dp, const double *X, const double *nrm, PairList out,
-                      uint64_t *dmax_bits, uint64_t *counters) {
-    if (n < 2) return;
-    require(n <= 65535, GRNG_EINVAL, "brute-force pair enumeration limited to 65535 points");
-    dim3 g((unsigned)div_up(n, 256), (unsigned)n);
-    k_pairs_all<<<g, 256, 0, s>>>(n, dp, X, nrm, out, dmax_bits, (unsigned long long *)counters);
+void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,
+                      const double *nrmB, int dp, bool self, PairList out, uint64_t *counters) {
+    if (nA == 0 || nB == 0) return;
+    require(nA <= 65535, GRNG_EINVAL, "brute-force pair enumeration limited to 65535 row points");
+    dim3 g((unsigned)div_up(nB, 256), (unsigned)nA);
+    k_pairs_all<<<g, 256, 0, s>>>(nA, XA, nrmA, nB, XB, nrmB, dp, self ? 1 : 0, out, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
@@ -693,7 +711,8 @@ void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const 
 }
 
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
-                        int dp, const double *Xh, const double *nrmh, const double *dhome, const int32_t *grp_off,
+                        int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
+                        const double *dhome, const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
                         const int32_t *rel_grp, const double *rel_d2x, uint8_t *alive, uint64_t *work,
                         uint64_t *counters) {
@@ -701,7 +720,7 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     launch_fill_u64(s, work, kXcds, 0ull);
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 8));
-    k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xh, nrmh, dhome, grp_off, dvor,
+    k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, zstart, grp_off, dvor,
                                                               Xp, nrmp, rel_off, rel_grp, rel_d2x, alive,
                                                               (unsigned long long *)work,
                                                               (unsigned long long *)counters);
@@ -709,11 +728,12 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
 }
 
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
-                     int64_t n, int dp, const double *X, const double *nrm, uint8_t *alive, uint64_t *counters) {
+                     int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
+                     int64_t z_from, uint8_t *alive, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
-    k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, X, nrm, alive,
+    k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, Xx, nrmx, X, nrm, z_from, alive,
                                                            (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
