@@ -186,6 +186,58 @@ grng_status grng_get_stats(const grng_index *idx, grng_stats *out);
 /* Release everything the index owns.  NULL is a no-op. */
 void grng_destroy(grng_index *idx);
 
+/* ---- Learned witness-domain ranking ---------------------------------------
+ * The exhaustive scan (Section 2, Stages V-VI) visits the candidate witness
+ * domains of a pair until one holds a witness.  The order never changes an
+ * edge (every domain that can hold a witness is still visited until one is
+ * found); it changes only how many witness tests are spent.  A small MLP,
+ *     h = relu(f W1 + b1),  s = h . w2 + b2,
+ * scores each candidate domain from GRNG_MLP_FEATURES scale-free features
+ * (distances of x and y to the domain's pivot, the domain's covering radius
+ * and pivot radius, its Proposition 3 margin and size, all relative to
+ * d(x,y)).  Parameters are one float32 device vector of grng_mlp_params()
+ * values laid out [W1 (features x hidden, row-major), b1, w2, b2].  The loss
+ * is the mean binary cross-entropy with logits against "the domain holds a
+ * witness".  Training samples come from the last grng_build_rng. */
+#define GRNG_MLP_FEATURES 8
+#define GRNG_MLP_HIDDEN 64
+
+/* Number of parameters: F*H + 2H + 1 = 641. */
+int32_t grng_mlp_params(void);
+
+/* Loss and its gradient on n samples.  feats_dev: float32 [n][8] (device),
+ * labels_dev: uint8 [n] in {0,1} (device), grad_dev: float32 [params]
+ * (device, written), *loss: host float.  Blocks of samples are reduced in a
+ * fixed order, so the result is deterministic.  stream: hipStream_t or NULL. */
+grng_status grng_mlp_grad(const float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
+                          float *grad_dev, float *loss, void *stream);
+
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step size
+ * lr) on theta_dev in place; *loss = loss after the last step. */
+grng_status grng_mlp_train(float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
+                           int32_t steps, float lr, float *loss, void *stream);
+
+/* Scores of n feature rows with the weights rounded to bf16 (nearest-even)
+ * and float32 accumulation: the same arithmetic the scan uses. */
+grng_status grng_mlp_score(const float *theta_dev, const float *feats_dev, int64_t n, float *scores_dev,
+                           void *stream);
+
+/* Training samples from the last grng_build_rng (which needs a pivot layer):
+ * for up to max_pairs pairs spread evenly over the pairs the exhaustive scan
+ * handled, one sample per candidate domain of the pair's first point that
+ * Proposition 3 does not rule out, labelled by an exact scan of the domain's
+ * members.  Writes min(count, capacity) rows of feats_dev (float32 [.][8]) and
+ * labels_dev (uint8); *count = samples produced.  GRNG_ECAPACITY when count >
+ * capacity (call again with capacity >= *count); GRNG_ESTATE when no guided
+ * build is current (after grng_insert_batch, until the next build). */
+grng_status grng_log_witness_cells(grng_index *idx, int64_t max_pairs, float *feats_dev, uint8_t *labels_dev,
+                                   int64_t capacity, int64_t *count);
+
+/* Install scorer weights (copied and rounded to bf16) for indexes created with
+ * witness_order = GRNG_ORDER_LEARNED; grng_build_rng on such an index returns
+ * GRNG_ESTATE until a scorer is set.  Queries and insertions use it too. */
+grng_status grng_set_scorer(grng_index *idx, const float *theta_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,10 @@ ORDER_DISTANCE, ORDER_LEARNED = 0, 1
 
 # Entry points declared in include/grng.h (checked by the CPU tests).
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
-                 "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy")
+                 "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy",
+                 "grng_mlp_params", "grng_mlp_grad", "grng_mlp_train", "grng_mlp_score", "grng_log_witness_cells",
+                 "grng_set_scorer")
+MLP_FEATURES, MLP_HIDDEN = 8, 64
 
 
 class GrngError(RuntimeError):
@@ -75,6 +78,12 @@ def lib():
             "grng_get_edges": (i32, [vp, i32, vp, i64, C.POINTER(i64)]),
             "grng_get_stats": (i32, [vp, C.POINTER(Stats)]),
             "grng_destroy": (None, [vp]),
+            "grng_mlp_params": (i32, []),
+            "grng_mlp_grad": (i32, [vp, vp, vp, i64, vp, C.POINTER(C.c_float), vp]),
+            "grng_mlp_train": (i32, [vp, vp, vp, i64, i32, C.c_float, C.POINTER(C.c_float), vp]),
+            "grng_mlp_score": (i32, [vp, vp, i64, vp, vp]),
+            "grng_log_witness_cells": (i32, [vp, i64, vp, vp, i64, C.POINTER(i64)]),
+            "grng_set_scorer": (i32, [vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -110,6 +119,50 @@ def _stream_handle(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def mlp_params() -> int:
+    return int(lib().grng_mlp_params())
+
+
+def _mlp_inputs(theta, feats, labels=None):
+    if theta.numel() != mlp_params():
+        raise ValueError("theta must hold %d parameters" % mlp_params())
+    if feats.dim() != 2 or feats.shape[1] != MLP_FEATURES:
+        raise ValueError("feats must be [n, %d]" % MLP_FEATURES)
+    if labels is not None and labels.numel() != feats.shape[0]:
+        raise ValueError("one label per feature row")
+
+
+def mlp_grad(theta, feats, labels, stream=None):
+    """(gradient float32 [P] device tensor, loss) of the witness-domain scorer."""
+    import torch
+    _mlp_inputs(theta, feats, labels)
+    g = torch.empty_like(theta)
+    loss = C.c_float(0.0)
+    check(lib().grng_mlp_grad(_dev_ptr(theta, "float32"), _dev_ptr(feats, "float32"), _dev_ptr(labels, "uint8"),
+                              feats.shape[0], _dev_ptr(g, "float32"), C.byref(loss), _stream_handle(stream)))
+    return g, float(loss.value)
+
+
+def mlp_train(theta, feats, labels, steps: int, lr: float, stream=None) -> float:
+    """Adam steps on theta in place; returns the final loss."""
+    _mlp_inputs(theta, feats, labels)
+    loss = C.c_float(0.0)
+    check(lib().grng_mlp_train(_dev_ptr(theta, "float32"), _dev_ptr(feats, "float32"), _dev_ptr(labels, "uint8"),
+                               feats.shape[0], steps, lr, C.byref(loss), _stream_handle(stream)))
+    return float(loss.value)
+
+
+def mlp_score(theta, feats, stream=None):
+    """Scores (bf16 weights, float32 accumulation) as a float32 device tensor."""
+    import torch
+    _mlp_inputs(theta, feats)
+    out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+    n = feats.shape[0]
+    check(lib().grng_mlp_score(_dev_ptr(theta, "float32"), _dev_ptr(feats, "float32") if n else None, n,
+                               _dev_ptr(out, "float32") if n else None, _stream_handle(stream)))
+    return out
 
 
 class Index:
@@ -173,6 +226,26 @@ class Index:
         n2 = C.c_int64(0)
         check(lib().grng_get_edges(self._h, layer, _dev_ptr(out, "int32") if ne else None, ne, C.byref(n2)))
         return out
+
+    def log_witness_cells(self, max_pairs: int):
+        """Training samples (feats float32 [n, 8], labels uint8 [n]) from the last build."""
+        import torch
+        cnt = C.c_int64(0)
+        st = lib().grng_log_witness_cells(self._h, max_pairs, None, None, 0, C.byref(cnt))
+        if st not in (GRNG_OK, -5):
+            check(st)
+        n = int(cnt.value)
+        feats = torch.empty((n, MLP_FEATURES), dtype=torch.float32, device="cuda")
+        labels = torch.empty(n, dtype=torch.uint8, device="cuda")
+        if n:
+            check(lib().grng_log_witness_cells(self._h, max_pairs, _dev_ptr(feats, "float32"),
+                                               _dev_ptr(labels, "uint8"), n, C.byref(cnt)))
+        return feats, labels
+
+    def set_scorer(self, theta) -> None:
+        if theta.numel() != mlp_params():
+            raise ValueError("theta must hold %d parameters" % mlp_params())
+        check(lib().grng_set_scorer(self._h, _dev_ptr(theta, "float32")))
 
     def stats(self) -> dict:
         st = Stats()

@@ -128,6 +128,64 @@ enum Counter {
     C_NUM = C_WORK_END
 };
 
+// Learned witness-cell ranking (scan order only).
+constexpr int kMlpFeatures = 8;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpFeatures * kMlpHidden + 2 * kMlpHidden + 1;
+
+// Scale-free features of candidate cell c for the pair (x, y): distances of
+// x and y to the cell's pivot, cell radius, domain radius, the Proposition 3
+// lower bound, log cell size, the pivot's position relative to the lune, all
+// divided by d(x, y) (or its square).
+__device__ inline void mlp_features(double dx, double dy, double dcell, double rdom, int32_t size, double dxy,
+                                    float *f) {
+    const double inv = 1.0 / dxy;
+    const double v[kMlpFeatures] = {dx * inv,
+                                    dy * inv,
+                                    dcell * inv,
+                                    rdom * inv,
+                                    (fmax(dx, dy) - dcell) * inv,
+                                    log2(1.0 + (double)size) * 0.1,
+                                    (dx * dx + dy * dy) * inv * inv - 1.0,
+                                    fmin(dx, dy) * inv};
+    for (int k = 0; k < kMlpFeatures; ++k) f[k] = (float)fmin(64.0, fmax(-64.0, v[k]));
+}
+
+__device__ inline float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Score with bf16 weights [W1, b1, w2, b2] and float32 accumulation.
+__device__ inline float mlp_score_bf16(const uint16_t *wb, const float *f) {
+    const uint16_t *W1 = wb, *b1 = wb + kMlpFeatures * kMlpHidden, *w2 = b1 + kMlpHidden;
+    float s = bf16_bits_to_f32(wb[kMlpParams - 1]);
+    for (int j = 0; j < kMlpHidden; ++j) {
+        float a = bf16_bits_to_f32(b1[j]);
+        for (int k = 0; k < kMlpFeatures; ++k) a = fmaf(f[k], bf16_bits_to_f32(W1[k * kMlpHidden + j]), a);
+        s = fmaf(a > 0.f ? a : 0.f, bf16_bits_to_f32(w2[j]), s);
+    }
+    return s;
+}
+
+// k_mlp.hip
+void launch_mlp_grad(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels, int64_t n,
+                     float *grad, float *loss, DevBuf &scratch);
+void launch_adam(hipStream_t s, float *theta, const float *g, float *m, float *v, int t, float lr);
+void launch_pack_bf16(hipStream_t s, const float *theta, uint16_t *out);
+void launch_mlp_score(hipStream_t s, const uint16_t *wb, const float *feats, int64_t n, float *scores);
+// Returns the number of samples; writes them only when it fits in capacity.
+int64_t launch_log_cells(hipStream_t s, int64_t nsamp, int64_t npairs, const int32_t *px, const int32_t *py,
+                         const double *pd2, int dp, const double *Xh, const double *nrmh, const int32_t *grp_off,
+                         const double *dvor, const double *rad, const double *Xp, const double *nrmp,
+                         const int64_t *rel_off, const int32_t *rel_grp, const double *rel_d2x, float *feats,
+                         uint8_t *labels, int64_t capacity);
+
+// State of the last build's exhaustive scan, kept for logging training samples.
+struct ExhaustiveState {
+    bool valid = false;            // set by a guided build_rng
+    int64_t np = 0;
+    DevBuf x, y, d2;               // pairs sorted by row point
+    DevBuf rel_off, rel_grp, rel_d2x;
+};
+
 }  // namespace grng
 
 struct grng_index {
@@ -145,6 +203,8 @@ struct grng_index {
     grng::DevBuf edges;        // int32 [2E] canonical exemplar RNG edges
     int64_t nedges = 0;
     grng::DevBuf counters;     // uint64 [C_NUM]
+    grng::ExhaustiveState ex;  // last guided build's exhaustive pairs (for training samples)
+    grng::DevBuf scorer;       // uint16 [kMlpParams] bf16 scorer weights (learned order)
     grng_stats stats{};
 };
 
@@ -238,7 +298,8 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
                         const double *dhome, const int32_t *zstart, const int32_t *grp_off, const double *dvor,
                         const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
-                        const double *rel_d2x, uint8_t *alive, uint64_t *work, uint64_t *counters);
+                        const double *rel_d2x, const double *rad, const uint16_t *scorer, uint8_t *alive,
+                        uint64_t *work, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
                      int64_t z_from, uint8_t *alive, uint64_t *counters);

@@ -72,6 +72,8 @@ void check_opts(const grng_options *o) {
     require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_BF16, GRNG_EINVAL, "unknown precision");
     require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED, GRNG_EINVAL,
             "unknown witness order");
+    require(o->use_graph == 0 || o->use_graph == 1, GRNG_EINVAL, "use_graph must be 0 or 1");
+    require(o->autotune == 0 || o->autotune == 1, GRNG_EINVAL, "autotune must be 0 or 1");
     require(o->stage4_pivots >= 0 && o->stage4_pivots <= kPivWitness, GRNG_EINVAL, "stage4_pivots must be in [0, 16]");
     require(o->reserved_i[0] == 0 && o->reserved_i[1] == 0, GRNG_EINVAL, "reserved option fields must be 0");
     for (int t = 0; t < 4; ++t) require(o->reserved[t] == 0, GRNG_EINVAL, "reserved option fields must be 0");
@@ -282,6 +284,7 @@ void do_build_layer(grng_index *idx, int32_t layer, const int32_t *pid_dev, cons
     idx->layers.push_back(std::move(L));
     idx->rng_built = false;
     idx->ps = PointState();
+    idx->ex = ExhaustiveState();
     idx->edges.release();
     idx->nedges = 0;
     idx->stats.n_layers = (int64_t)idx->layers.size();
@@ -512,7 +515,7 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
 //   zstart: first witness position per cell (Stage VII: the inserted points), or null.
 void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const PointState &X, const PointState &S,
                     Pairs &P, int64_t np, const DevBuf &dmax, const int32_t *cell_filter, const int32_t *zstart,
-                    DevBuf &alive, BuildTimes &bt) {
+                    DevBuf &alive, BuildTimes &bt, ExhaustiveState *keep = nullptr) {
     hipStream_t s = idx->stream;
     const int64_t n = X.n, m = L.m;
     uint64_t *ctr = idx->counters.as<uint64_t>();
@@ -548,12 +551,24 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
                        X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.dhome.as<double>(), zstart,
                        S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),
-                       rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), alive.as<uint8_t>(),
-                       ctr + C_WORK0, ctr);
+                       rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
+                       idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,
+                       alive.as<uint8_t>(), ctr + C_WORK0, ctr);
     bt.lune += lt.stop();
+    if (keep) {
+        keep->valid = true;
+        keep->np = np;
+        keep->x = std::move(P.x);
+        keep->y = std::move(P.y);
+        keep->d2 = std::move(P.d2);
+        keep->rel_off = std::move(rel_off);
+        keep->rel_grp = std::move(rel_grp);
+        keep->rel_d2x = std::move(rel_d2x);
+    }
 }
 
-void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &edges, int64_t &ne, BuildTimes &bt) {
+void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &edges, int64_t &ne, BuildTimes &bt,
+                      ExhaustiveState &ex) {
     const Layer &L = idx->layers.back();
     prepare_aux(idx, L, aux);
     prepare_points(idx, L, aux, idx->X.as<double>(), idx->nrm.as<double>(), idx->n, nullptr, nullptr, ps, bt);
@@ -561,8 +576,9 @@ void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &ed
     DevBuf dmax, alive;
     int64_t np = 0;
     run_pairs(idx, L, aux, ps, ps, PM_SELF, P, dmax, np, bt);
-    run_exhaustive(idx, L, aux, ps, ps, P, np, dmax, ps.gcount.as<int32_t>(), nullptr, alive, bt);
-    pairs_to_edges(idx->stream, idx->n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(),
+    // The scan is read twice: for the edges now, and later for training samples.
+    run_exhaustive(idx, L, aux, ps, ps, P, np, dmax, ps.gcount.as<int32_t>(), nullptr, alive, bt, &ex);
+    pairs_to_edges(idx->stream, idx->n, np, ex.x.as<int32_t>(), ex.y.as<int32_t>(), alive.as<uint8_t>(),
                    ps.perm.as<int32_t>(), edges, ne);
     ps.dxp.release();   // only needed while building
 }
@@ -589,6 +605,8 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
 
 void do_build_rng(grng_index *idx) {
     require(idx != nullptr, GRNG_EINVAL, "index is NULL");
+    require(idx->opt.witness_order != GRNG_ORDER_LEARNED || idx->scorer.p != nullptr, GRNG_ESTATE,
+            "the learned witness order needs grng_set_scorer first");
     hipStream_t s = idx->stream;
     EventTimer timer(s);
     reset_counters(idx);
@@ -597,12 +615,14 @@ void do_build_rng(grng_index *idx) {
     BuildTimes bt;
     PointState ps;
     LayerAux aux;
+    ExhaustiveState ex;
     if (idx->layers.empty()) {
         require(idx->n <= 65535, GRNG_EINVAL, "without a pivot layer build_rng is limited to 65535 points");
         build_rng_brute(idx, edges, ne, bt.lune);
     } else {
-        build_rng_guided(idx, ps, aux, edges, ne, bt);
+        build_rng_guided(idx, ps, aux, edges, ne, bt, ex);
     }
+    idx->ex = std::move(ex);
     const double ms = timer.stop();
     idx->edges = std::move(edges);
     idx->nedges = ne;
@@ -788,6 +808,7 @@ void do_insert(grng_index *idx, const float *pts, int64_t nb) {
                        ps.perm.as<int32_t>(), edges, ne);
         ps.dxp.release();
         idx->ps = std::move(ps);
+        idx->ex = ExhaustiveState();   // training samples come from full builds only
         std::swap(idx->X, X1);
         std::swap(idx->nrm, nrm1);
         idx->n = n1;
@@ -825,6 +846,84 @@ void do_get_edges(const grng_index *idx, int32_t layer, int32_t *uv, int64_t cap
     require(uv != nullptr, GRNG_EINVAL, "uv pointer is NULL");
     GRNG_HIP(hipMemcpyAsync(uv, src->p, sizeof(int32_t) * 2 * (size_t)ne, hipMemcpyDeviceToDevice, idx->stream));
     GRNG_HIP(hipStreamSynchronize(idx->stream));
+}
+
+// ---------------------------------------------------------------------------
+// Learned witness-cell ranking.
+
+void do_mlp_grad(const float *theta, const float *feats, const uint8_t *labels, int64_t n, float *grad,
+                 float *loss_host, void *stream) {
+    require(theta && feats && labels && grad && loss_host, GRNG_EINVAL, "NULL argument");
+    require(n >= 1, GRNG_EINVAL, "n must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf scratch, lbuf;
+    lbuf.alloc(8);
+    launch_mlp_grad(s, theta, feats, labels, n, grad, lbuf.as<float>(), scratch);
+    std::vector<float> h;
+    d2h(h, lbuf.p, 1, s);
+    *loss_host = h[0];
+}
+
+void do_mlp_train(float *theta, const float *feats, const uint8_t *labels, int64_t n, int32_t steps, float lr,
+                  float *loss_host, void *stream) {
+    require(theta && feats && labels && loss_host, GRNG_EINVAL, "NULL argument");
+    require(n >= 1 && steps >= 1 && lr > 0.f, GRNG_EINVAL, "n, steps and lr must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf scratch, g, m, v, lbuf;
+    g.alloc(4 * kMlpParams);
+    m.alloc(4 * kMlpParams);
+    v.alloc(4 * kMlpParams);
+    lbuf.alloc(8);
+    zero(m, s);
+    zero(v, s);
+    for (int32_t t = 1; t <= steps; ++t) {
+        launch_mlp_grad(s, theta, feats, labels, n, g.as<float>(), lbuf.as<float>(), scratch);
+        launch_adam(s, theta, g.as<float>(), m.as<float>(), v.as<float>(), t, lr);
+    }
+    launch_mlp_grad(s, theta, feats, labels, n, g.as<float>(), lbuf.as<float>(), scratch);
+    std::vector<float> h;
+    d2h(h, lbuf.p, 1, s);
+    *loss_host = h[0];
+}
+
+void do_mlp_score(const float *theta, const float *feats, int64_t n, float *scores, void *stream) {
+    require(theta != nullptr, GRNG_EINVAL, "NULL argument");
+    require(n >= 0, GRNG_EINVAL, "n must be >= 0");
+    require(n == 0 || (feats && scores), GRNG_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf wb;
+    wb.alloc(2 * kMlpParams);
+    launch_pack_bf16(s, theta, wb.as<uint16_t>());
+    launch_mlp_score(s, wb.as<uint16_t>(), feats, n, scores);
+    GRNG_HIP(hipStreamSynchronize(s));
+}
+
+void do_log_cells(grng_index *idx, int64_t max_pairs, float *feats, uint8_t *labels, int64_t capacity,
+                  int64_t *count) {
+    require(idx && count, GRNG_EINVAL, "NULL argument");
+    require(max_pairs >= 0 && capacity >= 0, GRNG_EINVAL, "sizes must be >= 0");
+    require(idx->rng_built && !idx->layers.empty() && idx->ex.valid, GRNG_ESTATE,
+            "needs a build_rng with a pivot layer");
+    hipStream_t s = idx->stream;
+    const ExhaustiveState &ex = idx->ex;
+    const PointState &ps = idx->ps;
+    const int64_t nsamp = std::min(max_pairs, ex.np);
+    if (capacity > 0) require(feats && labels, GRNG_EINVAL, "NULL sample buffers");
+    *count = launch_log_cells(s, nsamp, ex.np, ex.x.as<int32_t>(), ex.y.as<int32_t>(), ex.d2.as<double>(), idx->dp,
+                              ps.Xh.as<double>(), ps.nrmh.as<double>(), ps.grp_off.as<int32_t>(),
+                              ps.dvor.as<double>(), idx->layers.back().rad.as<double>(), idx->aux.Xp.as<double>(),
+                              idx->aux.nrmp.as<double>(), ex.rel_off.as<int64_t>(), ex.rel_grp.as<int32_t>(),
+                              ex.rel_d2x.as<double>(), feats, labels, capacity);
+    if (*count > capacity) throw Error(GRNG_ECAPACITY, "sample buffer too small");
+}
+
+void do_set_scorer(grng_index *idx, const float *theta) {
+    require(idx && theta, GRNG_EINVAL, "NULL argument");
+    DevBuf wb;
+    wb.alloc(2 * kMlpParams);
+    launch_pack_bf16(idx->stream, theta, wb.as<uint16_t>());
+    GRNG_HIP(hipStreamSynchronize(idx->stream));
+    idx->scorer = std::move(wb);
 }
 
 template <class F>
@@ -900,6 +999,32 @@ grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t 
 grng_status grng_query_neighbors(grng_index *idx, const float *q_dev, int64_t nq, int64_t *offsets_dev,
                                  int32_t *nbrs_dev, int64_t capacity, int64_t *needed) {
     return guarded([&] { do_query(idx, q_dev, nq, offsets_dev, nbrs_dev, capacity, needed); });
+}
+
+int32_t grng_mlp_params(void) { return kMlpParams; }
+
+grng_status grng_mlp_grad(const float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
+                          float *grad_dev, float *loss, void *stream) {
+    return guarded([&] { do_mlp_grad(theta_dev, feats_dev, labels_dev, n, grad_dev, loss, stream); });
+}
+
+grng_status grng_mlp_train(float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
+                           int32_t steps, float lr, float *loss, void *stream) {
+    return guarded([&] { do_mlp_train(theta_dev, feats_dev, labels_dev, n, steps, lr, loss, stream); });
+}
+
+grng_status grng_mlp_score(const float *theta_dev, const float *feats_dev, int64_t n, float *scores_dev,
+                           void *stream) {
+    return guarded([&] { do_mlp_score(theta_dev, feats_dev, n, scores_dev, stream); });
+}
+
+grng_status grng_log_witness_cells(grng_index *idx, int64_t max_pairs, float *feats_dev, uint8_t *labels_dev,
+                                   int64_t capacity, int64_t *count) {
+    return guarded([&] { do_log_cells(idx, max_pairs, feats_dev, labels_dev, capacity, count); });
+}
+
+grng_status grng_set_scorer(grng_index *idx, const float *theta_dev) {
+    return guarded([&] { do_set_scorer(idx, theta_dev); });
 }
 
 grng_status grng_get_edges(const grng_index *idx, int32_t layer, int32_t *uv_dev, int64_t capacity,

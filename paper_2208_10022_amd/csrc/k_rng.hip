@@ -488,7 +488,8 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const double *__restrict__ nrmh, const double *__restrict__ dhome, const int32_t *__restrict__ zstart,
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
     const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
-    const double *__restrict__ rel_d2x, uint8_t *__restrict__ alive, unsigned long long *work,
+    const double *__restrict__ rel_d2x, const double *__restrict__ rad, const uint16_t *__restrict__ scorer,
+    uint8_t *__restrict__ alive, unsigned long long *work,
     unsigned long long *counters) {
     // Dynamic, XCD-aware scheduling: workgroups are dealt round-robin to the
     // 8 XCDs, so a wave on XCD c takes pairs one at a time from the c-th
@@ -525,6 +526,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             bool scan = false;
             double dxl = 0.0, dyl = 0.0;
             int32_t g = 0;
+            float key = -INFINITY;
             if (c < r1) {
                 g = rel_grp[c];
                 const double d2x = rel_d2x[c];
@@ -538,12 +540,43 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 dyl = sqrt_lo(d2y);
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
                 scan = !surely_ge(fmax(dxl, dyl), dvor[g], dxy_hi);
+                if (scan && scorer) {
+                    float f[kMlpFeatures];
+                    mlp_features(sqrt(d2x), sqrt(d2y), dvor[g], rad[g], grp_off[g + 1] - grp_off[g], sqrt(d2), f);
+                    key = mlp_score_bf16(scorer, f);
+                    if (!(key == key)) key = -INFINITY;   // keep (key, lane) a strict total order
+                }
             }
             if (__ballot(dead)) { dead = true; break; }
             uint64_t cells = __ballot(scan);
-            while (cells && !dead) {
-                const int src = __ffsll((long long)cells) - 1;
-                cells &= cells - 1;
+            // Visit order: chunk order (cells sorted by distance to x), or by
+            // descending learned score (wave bitonic sort of (score, lane)).
+            int order = lane;
+            if (scorer && cells) {
+                float k = scan ? key : -INFINITY;
+                for (int sz = 2; sz <= 64; sz <<= 1)
+                    for (int j = sz >> 1; j > 0; j >>= 1) {
+                        const float ok = __shfl_xor(k, j, kWave);
+                        const int oi = __shfl_xor(order, j, kWave);
+                        const bool desc = (lane & sz) == 0;
+                        const bool lower = (lane & j) == 0;
+                        const bool other_first = ok > k || (ok == k && oi < order);
+                        if (lower == desc ? other_first : !other_first) {
+                            k = ok;
+                            order = oi;
+                        }
+                    }
+            }
+            for (int t = 0; cells && !dead; ++t) {
+                int src;
+                if (scorer && t < 64) {
+                    src = __shfl(order, t, kWave);
+                    if (!((cells >> src) & 1ull)) continue;
+                    cells &= ~(1ull << src);
+                } else {
+                    src = __ffsll((long long)cells) - 1;
+                    cells &= cells - 1;
+                }
                 const int32_t gg = __shfl(g, src, kWave);
                 const double gx = __shfl(dxl, src, kWave), gy = __shfl(dyl, src, kWave);
                 const double gmax = fmax(gx, gy);
@@ -714,14 +747,14 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
                         const double *dhome, const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
-                        const int32_t *rel_grp, const double *rel_d2x, uint8_t *alive, uint64_t *work,
-                        uint64_t *counters) {
+                        const int32_t *rel_grp, const double *rel_d2x, const double *rad, const uint16_t *scorer,
+                        uint8_t *alive, uint64_t *work, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     launch_fill_u64(s, work, kXcds, 0ull);
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 8));
     k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, zstart, grp_off, dvor,
-                                                              Xp, nrmp, rel_off, rel_grp, rel_d2x, alive,
+                                                              Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, alive,
                                                               (unsigned long long *)work,
                                                               (unsigned long long *)counters);
     GRNG_LAUNCHED();
