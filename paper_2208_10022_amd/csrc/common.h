@@ -123,10 +123,13 @@ enum Counter {
     C_RECHECK,        // exact re-decisions
     C_SURV,           // pairs left for the exhaustive scan (after Stage V)
     C_LUNE,           // witness predicates evaluated by the exhaustive scan
-    C_WORK0,          // 8 work counters for dynamic scheduling (one per XCD)
-    C_WORK_END = C_WORK0 + 8,
+    // 8 work counters for dynamic scheduling (one per XCD), each on its own
+    // 128-byte line: atomics on one shared line serialize across the chip.
+    C_WORK0 = 16,
+    C_WORK_END = C_WORK0 + 8 * 16,
     C_NUM = C_WORK_END
 };
+constexpr int kWorkStride = 16;   // uint64 slots between two XCDs' work counters
 
 // Learned witness-cell ranking (scan order only).
 constexpr int kMlpFeatures = 8;

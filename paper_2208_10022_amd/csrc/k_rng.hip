@@ -71,6 +71,28 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
+constexpr int kXcds = 8;       // XCDs of an MI355X; workgroups are dealt to them round-robin
+
+// Dynamic, XCD-aware scheduling over n items split into 8 contiguous ranges:
+// a caller on XCD c claims chunks of its own range first, then helps the
+// other ranges (xr counts the ranges it has exhausted).  Returns false when
+// every range is used up; otherwise [*b, *e) is the claimed chunk.
+__device__ inline bool claim_chunk(int64_t n, int64_t chunk, int xcd0, int &xr, unsigned long long *work,
+                                   int64_t *b, int64_t *e) {
+    while (xr < kXcds) {
+        const int c = (xcd0 + xr) % kXcds;
+        const int64_t lo = n * c / kXcds, hi = n * (c + 1) / kXcds;
+        const int64_t s = lo + (int64_t)atomicAdd(&work[c * kWorkStride], 1ull) * chunk;
+        if (s < hi) {
+            *b = s;
+            *e = s + chunk < hi ? s + chunk : hi;
+            return true;
+        }
+        ++xr;
+    }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // Candidate pairs guided by the pivot layer (Stages I-V), tiled.
 //
@@ -83,12 +105,20 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
 //     from the transposed virtual-pivot bitsets, and the cell bits of both;
 //   * Stage IV: the pivots nearest to the two cells as witnesses, with exact
 //     d^2 to the pivots from two more MFMA tiles;
-//   * Stage V: each survivor is tested against the 128 points of T and U,
-//     already in LDS (one lane per witness, wave ballot for the verdict).
+//   * Stage V: the 128 points of T and U as witnesses.  The in-tile distance
+//     matrices D(T,U), D(T,T), D(U,U) are exact f64 MFMA results rounded
+//     down to float32 and kept in LDS.  z is taken as a witness only when
+//     rd(d^2(x,z)) < rd(d^2(x,y)) and rd(d^2(y,z)) < rd(d^2(x,y)), which
+//     implies the exact strict inequalities (rd(a) < rd(b) <= b and
+//     a < next(rd(a)) <= rd(b)).  A pair whose only witnesses are too close
+//     to call survives to the exact scan, so no edge depends on rounding.
 // Survivors go to the global pair list for the exhaustive scan.
 constexpr int kTile = 64;
-constexpr int kXcds = 8;       // XCDs of an MI355X; workgroups are dealt to them round-robin
 constexpr int kPiv = 16;        // pivot witnesses per tile pair (one MFMA column block)
+constexpr int kDl = kTile + 1;  // row stride (floats) of the in-tile distance matrices
+constexpr int kXs = kPiv + 4;   // row stride (floats) of the pivot distances: 16-byte aligned rows
+constexpr int kPairChunk = 8;   // tile pairs claimed per atomic
+constexpr int kLuneChunk = 4;   // pairs claimed per atomic by one wave of the exhaustive scan
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -101,42 +131,117 @@ __device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) 
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_pairs_tiled(int64_t ntp, const int32_t *__restrict__ tpT,
-                                                    const int32_t *__restrict__ tpU, PointsView A, PointsView B,
-                                                    int mode, int dp, int32_t words, const int32_t *__restrict__ pknn,
-                                                    int32_t K, const double *__restrict__ Xp,
-                                                    const double *__restrict__ nrmp, PairList out,
-                                                    unsigned long long *dmax_bits, unsigned long long *work,
-                                                    unsigned long long *counters) {
-    // LDS: rows of T, U and the pivot witnesses (ld = dp + 1 doubles per row),
-    // norms, d^2 to the pivots (float, rounded up), candidate masks and the
-    // 64 x 64 bit mask of Stage IV survivors.
+// LDS bytes of k_pairs_tiled for padded dimension dp.  After Stage IV the
+// pivot rows and pivot distances are dead, and D(T,T), D(U,U) reuse them.
+__host__ __device__ inline size_t pairs_lds_bytes(int dp) {
+    const size_t ld = (size_t)dp + 1;
+    const size_t fixed = 8 * (2 * kTile * ld + 2 * kTile + kPiv + 3 * kTile) + 4 * (size_t)kTile * kDl;
+    const size_t phase_a = 8 * (size_t)kPiv * ld + 4 * 2 * (size_t)kTile * kXs;
+    const size_t phase_b = 4 * 2 * (size_t)kTile * kDl;
+    return fixed + (phase_a > phase_b ? phase_a : phase_b);
+}
+
+// Rows [0, rows) of a tile into LDS (row stride ld doubles), zero rows past
+// len; spread over nthr threads (t = this thread's index among them), four
+// threads per row, 16-byte loads.
+__device__ inline void load_rows(double *dst, const double *__restrict__ src, int len, int rows, int dp, int ld,
+                                 int t, int nthr) {
+    for (int r = t >> 2; r < rows; r += nthr >> 2) {
+        for (int c = 2 * (t & 3); c < dp; c += 8) {
+            double2 v = {0.0, 0.0};
+            if (r < len) v = *reinterpret_cast<const double2 *>(src + (int64_t)r * dp + c);
+            dst[r * ld + c] = v.x;
+            dst[r * ld + c + 1] = v.y;
+        }
+    }
+}
+
+// Up to 64 survivors of one wave, one per lane, appended to the pair list
+// with a single atomic.
+struct WaveOut {
+    int cnt = 0;   // uniform
+    int32_t x = 0, y = 0;
+    double d2 = 0.0;
+    __device__ void flush(PairList out) {
+        if (cnt == 0) return;
+        const int lane = threadIdx.x & 63;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long *)out.count, (unsigned long long)cnt);
+        base = __shfl(base, 0, kWave);
+        if (lane < cnt && (int64_t)(base + lane) < out.cap) {
+            out.x[base + lane] = x;
+            out.y[base + lane] = y;
+            out.d2[base + lane] = d2;
+        }
+        cnt = 0;
+    }
+};
+
+constexpr int kPairThreads = 512;   // 8 waves per tile pair
+constexpr int kPairWaves = kPairThreads / 64;
+
+// One wave, nb independent 16x16 blocks of rd/ru |a_i - b_j|^2 at once (the
+// MFMA chains interleave, so the matrix unit is not idle on dependences).
+template <int NB>
+__device__ inline void dist_blocks(const double *const sa[NB], const double *const na[NB], const double *const sb[NB],
+                                   const double *const nb[NB], const int r0[NB], const int c0[NB], int dp, int ld,
+                                   float *const D[NB], const int dld[NB], const bool up[NB]) {
+    const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
+    v4d acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < dp; kk += 4) {
+        double av[NB], bv[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            av[q] = sa[q][(r0[q] + il) * ld + kk + kl];
+            bv[q] = sb[q][(c0[q] + il) * ld + kk + kl];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        for (int r = 0; r < 4; ++r) {
+            const int i = r0[q] + 4 * r + kl, j = c0[q] + il;
+            const double v = na[q][i] + nb[q][j] - 2.0 * acc[q][r];
+            D[q][i * dld[q] + j] = up[q] ? __double2float_ru(v) : __double2float_rd(v);
+        }
+}
+
+__global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_tiled(
+    int64_t ntp, const int32_t *__restrict__ tpT, const int32_t *__restrict__ tpU, PointsView A, PointsView B, int mode,
+    int dp, int32_t words, const int32_t *__restrict__ pknn, int32_t K, const double *__restrict__ Xp,
+    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *work,
+    unsigned long long *counters) {
+    // LDS: rows of T and U (ld = dp + 1 doubles per row), norms, candidate
+    // masks, the 64 x 64 bit mask of Stage IV survivors, rd D(T,U); then
+    // either the pivot rows and rounded-up pivot distances (Stages I-IV) or
+    // rd D(T,T) and rd D(U,U) (Stage V) in the same bytes.
     extern __shared__ double lds[];
     const int ld = dp + 1;
-    double *sX = lds, *sY = sX + kTile * ld, *sP = sY + kTile * ld;
-    double *nX = sP + kPiv * ld, *nY = nX + kTile, *nP = nY + kTile;
+    double *sX = lds, *sY = sX + kTile * ld;
+    double *nX = sY + kTile * ld, *nY = nX + kTile, *nP = nY + kTile;
     uint64_t *mX = (uint64_t *)(nP + kPiv), *mY = mX + kTile, *surv = mY + kTile;
-    float *XP = (float *)(surv + kTile), *YP = XP + kTile * (kPiv + 1);
+    float *DTU = (float *)(surv + kTile);
+    float *region = DTU + kTile * kDl;
+    double *sP = (double *)region;
+    float *XP = (float *)(sP + kPiv * ld), *YP = XP + kTile * kXs;
+    float *DTT = region, *DUU = region + kTile * kDl;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int il = lane & 15, kl = lane >> 4;
     const bool self = (mode & PM_SELF) != 0;
-    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntests = 0;
+    uint32_t ncand = 0, ns4 = 0, nsurv = 0;
+    WaveOut wo;
     __shared__ int64_t s_tp;
+    __shared__ int s_any;
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
+    int64_t cur = 0, cend = 0;   // tid 0's claimed chunk
     for (;;) {
-        // Dynamic, XCD-aware scheduling (tile pairs are sorted by T: the
-        // c-th eighth goes to XCD c first, then the XCDs help each other).
         if (tid == 0) {
-            int64_t got = -1;
-            while (xr < kXcds) {
-                const int c = (xcd0 + xr) % kXcds;
-                const int64_t lo = ntp * c / kXcds, hi = ntp * (c + 1) / kXcds;
-                const int64_t t = (int64_t)atomicAdd(&work[c], 1ull);
-                if (lo + t < hi) { got = lo + t; break; }
-                ++xr;
-            }
-            s_tp = got;
+            if (cur >= cend && !claim_chunk(ntp, kPairChunk, xcd0, xr, work, &cur, &cend)) cur = cend = -1;
+            s_tp = cur < cend ? cur++ : -1;
+            s_any = 0;
         }
         __syncthreads();
         const int64_t tp = s_tp;
@@ -145,26 +250,11 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(int64_t ntp, const int32_t 
         const int32_t T = tpT[tp], U = tpU[tp];
         const int32_t sT = A.tiles[3 * T], lT = A.tiles[3 * T + 1], a = A.tiles[3 * T + 2];
         const int32_t sU = B.tiles[3 * U], lU = B.tiles[3 * U + 1], b = B.tiles[3 * U + 2];
-        // 1. rows, norms, pivot witnesses, candidate masks -> LDS
-        for (int e = tid; e < kTile * dp; e += 256) {
-            const int r = e / dp, c = e % dp;
-            sX[r * ld + c] = r < lT ? A.Xh[(int64_t)(sT + r) * dp + c] : 0.0;
-            sY[r * ld + c] = r < lU ? B.Xh[(int64_t)(sU + r) * dp + c] : 0.0;
-        }
-        const int ka = (a == b) ? K : (K + 1) / 2;
-        for (int e = tid; e < kPiv * dp; e += 256) {
-            const int t = e / dp, c = e % dp;
-            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
-            sP[t * ld + c] = Xp[(int64_t)pv * dp + c];
-        }
-        if (tid < kPiv) {
-            const int t = tid;
-            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
-            nP[t] = nrmp[pv];
-        }
-        if (tid < kTile) {
-            // wave 0: rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
-            const int r = tid;
+        // 1. candidate masks (waves 6, 7: the longest dependent load chains
+        // start first), rows of T (threads 0-255) and U (256-511), pivot rows.
+        if (w == 6) {
+            // rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
+            const int r = lane;
             uint64_t newU = ~0ull;
             if (mode & PM_NEW_ONLY) newU = __ballot(r < lU && B.is_new[sU + r]);
             uint64_t mk = 0;
@@ -182,8 +272,8 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(int64_t ntp, const int32_t 
             nX[r] = nv;
             mX[r] = mk;
             surv[r] = 0;
-        } else if (tid < 2 * kTile) {
-            const int r = tid - kTile;
+        } else if (w == 7) {
+            const int r = lane;
             uint64_t mk = 0;
             double nv = 0.0;
             if (r < lU) {
@@ -197,110 +287,160 @@ __global__ __launch_bounds__(256) void k_pairs_tiled(int64_t ntp, const int32_t 
             }
             nY[r] = nv;
             mY[r] = mk;
+        } else if (w == 5) {
+            const int ka = (a == b) ? K : (K + 1) / 2;
+            const int t = lane >> 2;
+            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
+            for (int c = 2 * (lane & 3); c < dp; c += 8) {
+                const double2 v = *reinterpret_cast<const double2 *>(Xp + (int64_t)pv * dp + c);
+                sP[t * ld + c] = v.x;
+                sP[t * ld + c + 1] = v.y;
+            }
+            if ((lane & 3) == 0) nP[t] = nrmp[pv];
         }
+        if (tid < 256)
+            load_rows(sX, A.Xh + (int64_t)sT * dp, lT, kTile, dp, ld, tid, 256);
+        else
+            load_rows(sY, B.Xh + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
         __syncthreads();
-        // 2a. d^2 from the 64 rows of T and U to the 16 pivot witnesses (MFMA f64).
+        // 2a. Per wave: one 16-row block of d^2 to the pivot witnesses (rows
+        // of T for waves 0-3, of U for 4-7; rounded up, +inf past K) and two
+        // 16x16 blocks of rd D(T,U); three interleaved MFMA f64 chains.
         {
-            v4d axp = {0.0, 0.0, 0.0, 0.0}, ayp = {0.0, 0.0, 0.0, 0.0};
-            for (int kk = 0; kk < dp; kk += 4) {
-                const double pv = sP[il * ld + kk + kl];
-                axp = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(w * 16 + il) * ld + kk + kl], pv, axp, 0, 0, 0);
-                ayp = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[(w * 16 + il) * ld + kk + kl], pv, ayp, 0, 0, 0);
-            }
-            for (int r = 0; r < 4; ++r) {
-                const int row = w * 16 + 4 * r + kl;
-                XP[row * (kPiv + 1) + il] = __double2float_ru(nX[row] + nP[il] - 2.0 * axp[r]);
-                YP[row * (kPiv + 1) + il] = __double2float_ru(nY[row] + nP[il] - 2.0 * ayp[r]);
+            const bool ys = w >= 4;
+            const int pr = (w & 3) * 16;
+            const int id0 = 2 * w, id1 = 2 * w + 1;
+            const double *sa[3] = {ys ? sY : sX, sX, sX};
+            const double *na[3] = {ys ? nY : nX, nX, nX};
+            const double *sb[3] = {sP, sY, sY};
+            const double *nb[3] = {nP, nY, nY};
+            const int r0[3] = {pr, (id0 >> 2) * 16, (id1 >> 2) * 16};
+            const int c0[3] = {0, (id0 & 3) * 16, (id1 & 3) * 16};
+            float *D[3] = {ys ? YP : XP, DTU, DTU};
+            const int dld[3] = {kXs, kDl, kDl};
+            const bool up[3] = {true, false, false};
+            dist_blocks<3>(sa, na, sb, nb, r0, c0, dp, ld, D, dld, up);
+            if ((lane & 15) >= K) {   // unused pivot slots never witness
+                float *Pd = ys ? YP : XP;
+                for (int r = 0; r < 4; ++r) Pd[(pr + 4 * r + (lane >> 4)) * kXs + (lane & 15)] = INFINITY;
             }
         }
         __syncthreads();
-        // 2b. Each wave: its 4 16x16 blocks of D_XY, one at a time; Stages I-IV.
-        for (int blk = 0; blk < 4; ++blk) {
-            const int rb = (w >> 1) * 32 + (blk >> 1) * 16, cb = (w & 1) * 32 + (blk & 1) * 16;
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-            for (int kk = 0; kk < dp; kk += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(rb + il) * ld + kk + kl], sY[(cb + il) * ld + kk + kl],
-                                                           acc, 0, 0, 0);
-            const int j = cb + il;
-            double d2[4];
-            uint32_t live = 0;
-            const uint64_t myj = mY[j];
-            for (int r = 0; r < 4; ++r) {
-                const int i = rb + 4 * r + kl;
-                d2[r] = nX[i] + nY[j] - 2.0 * acc[r];
-                if (((mX[i] >> j) & 1ull) && ((myj >> i) & 1ull)) live |= 1u << r;
-            }
-            ncand += __popc(live);
-            // Stage IV: min over pivots of max(d^2(x,p), d^2(y,p)) from values
-            // rounded up; below d^2(x,y) proves a witness.
-            float cmin[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-            for (int t0 = 0; t0 < K; t0 += 4) {
-                if (!__ballot(live != 0)) break;
-                ntests += __popc(live) * (uint32_t)min(4, K - t0);
-                for (int t = t0; t < t0 + 4 && t < K; ++t) {
-                    const float yv = YP[j * (kPiv + 1) + t];
-                    for (int r = 0; r < 4; ++r)
-                        cmin[r] = fminf(cmin[r], fmaxf(XP[(rb + 4 * r + kl) * (kPiv + 1) + t], yv));
-                }
+        // 2b. Stages I-IV for all 64 x 64 pairs: thread = rows ty + 16k
+        // (k < 4) x columns tx, tx + 32.  C = min over pivots of max(d^2(x,p),
+        // d^2(y,p)) (rounded up) as a (min,max) product over LDS rows; a
+        // candidate dies when C < rd d^2(x,y), which proves a pivot witness.
+        {
+            const int tx = tid & 31, ty = tid >> 5;
+            float c[4][2];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[r][0] = c[r][1] = INFINITY;
+#pragma unroll
+            for (int t0 = 0; t0 < kPiv; t0 += 4) {
+                if (t0 >= K) break;
+                float4 xv[4], yv[2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xv[r] = *reinterpret_cast<const float4 *>(XP + (ty + 16 * r) * kXs + t0);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) yv[q] = *reinterpret_cast<const float4 *>(YP + (tx + 32 * q) * kXs + t0);
+#pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if ((double)cmin[r] < d2[r]) live &= ~(1u << r);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        float m = fminf(fmaxf(xv[r].x, yv[q].x), fmaxf(xv[r].y, yv[q].y));
+                        m = fminf(m, fminf(fmaxf(xv[r].z, yv[q].z), fmaxf(xv[r].w, yv[q].w)));
+                        c[r][q] = fminf(c[r][q], m);
+                    }
             }
-            ns4 += __popc(live);
-            for (int r = 0; r < 4; ++r)
-                if (live & (1u << r)) atomicOr((unsigned long long *)&surv[rb + 4 * r + kl], 1ull << j);
+            const uint64_t my0 = mY[tx], my1 = mY[tx + 32];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = ty + 16 * r;
+                const uint64_t mxi = mX[i];
+                uint64_t bits = 0;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int j = tx + 32 * q;
+                    const bool cand = ((mxi >> j) & 1ull) && (((q ? my1 : my0) >> i) & 1ull);
+                    ncand += cand;
+                    if (cand && !(c[r][q] < DTU[i * kDl + j])) bits |= 1ull << j;
+                }
+                if (bits) {
+                    ns4 += __popcll(bits);
+                    atomicOr((unsigned long long *)&surv[i], (unsigned long long)bits);
+                    s_any = 1;
+                }
+            }
         }
         __syncthreads();
-        // 3. Stage V: each wave walks rows w, w+4, ...; every Stage IV survivor
-        // of the row is tested against the points of T and U (one lane per witness).
-        for (int i = w; i < lT; i += 4) {
+        if (!s_any) continue;   // uniform: no Stage IV survivor in this tile pair
+        // 2c. rd D(T,T) (only when T's points may witness) and rd D(U,U),
+        // written over the pivot data, which is dead now: waves 0-3 take
+        // D(T,T), waves 4-7 D(U,U), four interleaved blocks each.
+        if (self || w >= 4) {
+            const bool us = w >= 4;
+            const double *sa[2], *na[2];
+            int r0[2], c0[2], dld[2] = {kDl, kDl};
+            float *D[2];
+            bool up[2] = {false, false};
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int id = 4 * (w & 3) + 2 * h + q;
+                    sa[q] = us ? sY : sX;
+                    na[q] = us ? nY : nX;
+                    r0[q] = (id >> 2) * 16;
+                    c0[q] = (id & 3) * 16;
+                    D[q] = us ? DUU : DTT;
+                }
+                dist_blocks<2>(sa, na, sa, na, r0, c0, dp, ld, D, dld, up);
+            }
+        }
+        __syncthreads();
+        // 3. Stage V: each wave walks rows w, w+8, ...; every Stage IV survivor
+        // (i, j) is tested against the points of T and U, one lane per witness
+        // z: max(rd d^2(x,z), rd d^2(y,z)) < rd d^2(x,y).
+        for (int i = w; i < lT; i += kPairWaves) {
             uint64_t row = surv[i];
-            const double *xr = sX + i * ld;
+            double rmax = -1.0;
             while (row) {
                 const int j = __ffsll((long long)row) - 1;
                 row &= row - 1;
-                const double *yr = sY + j * ld;
-                double sxy = 0.0;
-                for (int c = 0; c < dp; ++c) sxy = fma(xr[c], yr[c], sxy);
-                const double dd = nX[i] + nY[j] - 2.0 * sxy;   // exact
-                bool wit = false;
-                for (int half = self ? 0 : 1; half < 2 && !wit; ++half) {
-                    bool wz = false;
-                    if (lane < (half == 0 ? lT : lU)) {
-                        const double *zr = (half == 0 ? sX : sY) + lane * ld;
-                        const double nz = half == 0 ? nX[lane] : nY[lane];
-                        double sx = 0.0, sy = 0.0;
-                        for (int c = 0; c < dp; ++c) {
-                            const double zc = zr[c];
-                            sx = fma(xr[c], zc, sx);
-                            sy = fma(yr[c], zc, sy);
-                        }
-                        wz = (nX[i] + nz - 2.0 * sx) < dd && (nY[j] + nz - 2.0 * sy) < dd;
-                        ++ntests;
-                    }
-                    wit = __ballot(wz) != 0;
+                const float t = DTU[i * kDl + j];
+                bool wz = false;
+                if (self && lane < lT) wz = fmaxf(DTT[i * kDl + lane], DTU[lane * kDl + j]) < t;
+                if (lane < lU) wz = wz || fmaxf(DTU[i * kDl + lane], DUU[j * kDl + lane]) < t;
+                if (__ballot(wz)) continue;
+                // survivor: exact d^2 by the lane that will hold it
+                double dd = 0.0;
+                if (lane == wo.cnt) {
+                    const double *xr = sX + i * ld, *yr = sY + j * ld;
+                    double sxy = 0.0;
+                    for (int c = 0; c < dp; ++c) sxy = fma(xr[c], yr[c], sxy);
+                    dd = nX[i] + nY[j] - 2.0 * sxy;   // exact
+                    wo.x = sT + i;
+                    wo.y = sU + j;
+                    wo.d2 = dd;
                 }
-                if (!wit && lane == 0) {
-                    const unsigned long long s0 = atomicAdd((unsigned long long *)out.count, 1ull);
-                    if ((int64_t)s0 < out.cap) {
-                        out.x[s0] = sT + i;
-                        out.y[s0] = sU + j;
-                        out.d2[s0] = dd;
-                    }
-                    atomicMax(&dmax_bits[sT + i], (unsigned long long)__double_as_longlong(dd));
-                    ++nsurv;
-                }
+                rmax = fmax(rmax, __shfl(dd, wo.cnt, kWave));
+                ++nsurv;
+                if (++wo.cnt == 64) wo.flush(out);
             }
+            if (rmax >= 0.0 && lane == 0)
+                atomicMax(&dmax_bits[sT + i], (unsigned long long)__double_as_longlong(rmax));
         }
         __syncthreads();
     }
+    wo.flush(out);
     ncand = wave_sum(ncand);
     ns4 = wave_sum(ns4);
-    ntests = wave_sum(ntests);
-    nsurv = wave_sum(nsurv);
     if (lane == 0) {
+        // witness tests: K pivot tests per candidate (Stage IV), 64 or 128
+        // in-tile tests per Stage IV survivor (Stage V)
+        const uint64_t tests = (uint64_t)ncand * (uint64_t)K + (uint64_t)ns4 * (self ? 128u : 64u);
         atomicAdd(&counters[C_CAND], (unsigned long long)ncand);
         atomicAdd(&counters[C_S4], (unsigned long long)ns4);
-        atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_WTEST], (unsigned long long)tests);
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
     }
 }
@@ -500,18 +640,17 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
     uint32_t ntests = 0, ndist = 0;
+    int64_t cur = 0, cend = 0;   // the wave's claimed chunk (uniform)
     for (;;) {
-        int64_t p = -1;
-        while (xr < kXcds) {
-            const int c = (xcd0 + xr) % kXcds;
-            const int64_t lo = npairs * c / kXcds, hi = npairs * (c + 1) / kXcds;
-            unsigned long long t = 0;
-            if (lane == 0) t = atomicAdd(&work[c], 1ull);
-            t = __shfl(t, 0, kWave);
-            if (lo + (int64_t)t < hi) { p = lo + (int64_t)t; break; }
-            ++xr;
+        if (cur >= cend) {
+            int64_t b = -1, e = -1;
+            if (lane == 0 && !claim_chunk(npairs, kLuneChunk, xcd0, xr, work, &b, &e)) b = e = -1;
+            cur = __shfl(b, 0, kWave);
+            cend = __shfl(e, 0, kWave);
+            xr = __shfl(xr, 0, kWave);
+            if (cur < 0) break;
         }
-        if (p < 0) break;
+        const int64_t p = cur++;
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
         const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
         const double d2 = pd2[p];
@@ -691,15 +830,14 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const in
     if (ntp == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the pair kernel");
     require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
-    launch_fill_u64(s, work, kXcds, 0ull);
-    const int ld = dp + 1;
-    const size_t lds = sizeof(double) * (size_t)(2 * kTile * ld + kPiv * ld + 2 * kTile + kPiv + 3 * kTile) +
-                       sizeof(float) * (size_t)(2 * kTile * (kPiv + 1));
+    launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
+    const size_t lds = pairs_lds_bytes(dp);
+    require(lds <= 160 * 1024, GRNG_EINVAL, "dimension too large for the pair kernel's LDS tiles");
     if (lds > 64 * 1024)
         GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
-    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(ntp, 256 * 8));
-    k_pairs_tiled<<<(unsigned)grid, 256, lds, s>>>(ntp, tpT, tpU, A, B, mode, dp, words, pknn, K, Xp, nrmp, out,
+    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(ntp, kPairChunk), 256 * 4));
+    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, tpT, tpU, A, B, mode, dp, words, pknn, K, Xp, nrmp, out,
                                                    (unsigned long long *)dmax_bits, (unsigned long long *)work,
                                                    (unsigned long long *)counters);
     GRNG_LAUNCHED();
@@ -751,7 +889,7 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         uint8_t *alive, uint64_t *work, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
-    launch_fill_u64(s, work, kXcds, 0ull);
+    launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 8));
     k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, zstart, grp_off, dvor,
                                                               Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, alive,

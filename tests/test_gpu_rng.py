@@ -82,10 +82,12 @@ def test_clustered_3000_d16_matches_golden(G):
 
 @pytest.mark.parametrize("n,d,m,clusters,seed", [
     (1037, 2, 30, 4, 0), (2111, 3, 70, 6, 1), (1500, 5, 16, 3, 2), (777, 16, 100, 5, 3),
-    (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7)])
+    (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7),
+    (900, 96, 24, 3, 8), (500, 100, 10, 2, 9)])
 def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed):
     say("ragged", n, d, m, clusters, seed)
-    W = synth.clustered(n=n, d=d, clusters=clusters, m=m, knn=min(30, n - 1), sub=seed)
+    # 2^-18 grid above 64 dimensions keeps d * kmax^2 below 2^51
+    W = synth.clustered(n=n, d=d, clusters=clusters, m=m, knn=min(30, n - 1), q=18 if d > 64 else 19, sub=seed)
     L = W.layers[0]
     want = native.rng_edges(W.X, W.q)
     E, lay, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
