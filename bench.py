@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--precision", type=int, default=1, help="0 = float64 everywhere, 1 = float32 screens + "
+                    "float64 re-decision (the plain float32 form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -125,7 +127,7 @@ def main():
         idx.build_grng_layer(0, pid, rad)
         idx.build_rng()
 
-    idx = P.Index(X, grid_exp=W.q)
+    idx = P.Index(X, grid_exp=W.q, precision=args.precision)
     for _ in range(args.warmup):
         step(idx)
     torch.cuda.synchronize()
@@ -159,11 +161,13 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f32",
         "data": "synthetic",
         "config": {"workload": "two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), "
                                "1,000 random pivots with 100-NN radii" % W.n,
-                   "n": W.n, "d": W.d, "pivots": int(len(L.pivot_ids)), "grid_exp": W.q},
+                   "n": W.n, "d": W.d, "pivots": int(len(L.pivot_ids)), "grid_exp": W.q,
+                   "precision": "float64 distances" if args.precision == 0 else
+                   "float32 screens, float64 re-decision of doubtful comparisons"},
         "edges": edges,
         "witness_tests": st["witness_tests"],
         "witness_tests_per_s": st["witness_tests"] / (ms / 1000.0),
@@ -172,6 +176,7 @@ def main():
         "stage4_survivors": st["stage4_survivors"],
         "exhaustive_pairs": st["exhaustive_pairs"],
         "lune_tests": st["lune_tests"],
+        "rechecks": st["rechecks"],
         "tile_pairs": st["tile_pairs"],
         "orphans": st["orphans"],
         "ms_layer": st["ms_layers"],

@@ -93,8 +93,10 @@ struct PointState {
     DevBuf perm;                   // int32 [n]
     DevBuf inv;                    // int32 [n] index -> home-order position
     DevBuf Xh, nrmh;               // double [n][dp], [n]
+    DevBuf Xf;                     // float [n][dp]: the same rows (exact, coordinates are float32 values)
     DevBuf home;                   // int32 [n] home cell (pivot position)
     DevBuf dhome;                  // double [n] upper bound of d(x, p_home)
+    DevBuf dhomef;                 // float [n] the same bound rounded up
     DevBuf grp_off;                // int32 [m+1]
     DevBuf dvor;                   // double [m] upper bound of the cell radius
     DevBuf gcount;                 // int32 [m] cell sizes
@@ -227,6 +229,7 @@ void launch_dist2(hipStream_t s, const double *A, const double *nA, int64_t na, 
 void launch_sqrt(hipStream_t s, const double *in, double *out, int64_t count);
 void launch_gather_rows(hipStream_t s, const double *src, const int32_t *idx, int64_t n, int dp, double *dst);
 void launch_gather_f64(hipStream_t s, const double *src, const int32_t *idx, int64_t n, double *dst);
+void launch_to_f32(hipStream_t s, const double *src, int64_t count, float *dst);
 void launch_iota_inverse(hipStream_t s, const int32_t *perm, int64_t n, int32_t *inv);
 void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out_excl);  // out has n+1
 void launch_scan_i32_to_i64(hipStream_t s, const int32_t *in, int64_t n, int64_t *out_excl);
@@ -299,7 +302,8 @@ void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const 
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
-                        const double *dhome, const int32_t *zstart, const int32_t *grp_off, const double *dvor,
+                        const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
+                        const int32_t *zstart, const int32_t *grp_off, const double *dvor,
                         const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
                         const double *rel_d2x, const double *rad, const uint16_t *scorer, uint8_t *alive,
                         uint64_t *work, uint64_t *counters);

@@ -395,6 +395,13 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
         for (int64_t c = 0; c < m; ++c) dvor[c] = std::sqrt(h_d2vor[c]) * (1.0 + 1e-15);   // upper bound of the cell radius
         h2d(P.grp_off, P.h_off, s);
         h2d(P.dhome, dhome, s);
+        std::vector<float> dhomef((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            float f = (float)dhome[i];
+            if ((double)f < dhome[i]) f = std::nextafter(f, INFINITY);
+            dhomef[i] = f;
+        }
+        h2d(P.dhomef, dhomef, s);
         h2d(P.dvor, dvor, s);
         h2d(P.gcount, h_gcount, s);
         launch_shifted_pivot_dists(s, m, L.dpp.as<double>(), L.rad.as<double>(), P.dvor.as<double>(),
@@ -407,6 +414,8 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     P.nrmh.alloc(sizeof(double) * (size_t)n);
     launch_gather_rows(s, X, P.perm.as<int32_t>(), n, dp, P.Xh.as<double>());
     launch_gather_f64(s, nrm, P.perm.as<int32_t>(), n, P.nrmh.as<double>());
+    P.Xf.alloc(sizeof(float) * (size_t)(n * dp));
+    launch_to_f32(s, P.Xh.as<double>(), n * dp, P.Xf.as<float>());
     // Parents and virtual-pivot bitsets (Propositions 1-2) as a tiled (min, max) product.
     P.par_idx.alloc(4 * (size_t)std::max<int64_t>(par_off[n], 1));
     launch_parents(s, n, m, P.perm.as<int32_t>(), P.dxp.as<double>(), L.rad.as<double>(), P.par_off.as<int64_t>(),
@@ -548,8 +557,11 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                            rel_d2x.as<double>());
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
+    const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
-                       X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.dhome.as<double>(), zstart,
+                       X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.dhome.as<double>(),
+                       f32 ? X.Xf.as<float>() : nullptr, f32 ? S.Xf.as<float>() : nullptr,
+                       f32 ? S.dhomef.as<float>() : nullptr, zstart,
                        S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),
                        rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
                        idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,

@@ -224,6 +224,12 @@ inline unsigned grid1(int64_t work, int block) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+// float64 -> float32 (values that are float32 on input stay exact).
+__global__ void k_to_f32(const double *src, int64_t count, float *dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (float)src[i];
+}
+
 }  // namespace
 
 void launch_grid_check(hipStream_t s, const float *x, int64_t count, double scale, uint64_t *kmax_bits,
@@ -273,6 +279,12 @@ void launch_sqrt(hipStream_t s, const double *in, double *out, int64_t count) {
 void launch_gather_rows(hipStream_t s, const double *src, const int32_t *idx, int64_t n, int dp, double *dst) {
     if (n == 0) return;
     k_gather_rows<<<grid1(n * dp, 256), 256, 0, s>>>(src, idx, n, dp, dst);
+    GRNG_LAUNCHED();
+}
+
+void launch_to_f32(hipStream_t s, const double *src, int64_t count, float *dst) {
+    if (count == 0) return;
+    k_to_f32<<<grid1(count, 256), 256, 0, s>>>(src, count, dst);
     GRNG_LAUNCHED();
 }
 

@@ -622,24 +622,60 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, in
 
 // ---------------------------------------------------------------------------
 // Exhaustive lune test of surviving pairs (Stages IV-VI).  One wave per pair.
+//
+// The row point's relevant cells are taken 64 at a time (one per lane):
+// distance of y to the cell's pivot, the pivot itself as a witness, and the
+// Proposition 3 skip.  The members of the cells still to scan are then laid
+// end to end in visit order (a wave prefix sum of member counts) and
+// streamed 256 per step across cell boundaries, each lane keeping a cursor
+// into the per-wave cell table in LDS; a ballot after each step ends the
+// pair at the first witness.  Streaming across cells keeps many loads in
+// flight per step where a cell-at-a-time scan would pay the memory latency
+// once per (small) cell.
+constexpr int kLuneWaves = 4;
+
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+template <bool F32>
 __global__ __launch_bounds__(256) void k_lune_guided(
     int64_t npairs, const int32_t *__restrict__ px, const int32_t *__restrict__ py, const double *__restrict__ pd2,
     int dp, const double *__restrict__ Xx, const double *__restrict__ nrmx, const double *__restrict__ Xh,
-    const double *__restrict__ nrmh, const double *__restrict__ dhome, const int32_t *__restrict__ zstart,
+    const double *__restrict__ nrmh, const double *__restrict__ dhome, const float *__restrict__ Xxf,
+    const float *__restrict__ Xhf, const float *__restrict__ dhomef, const int32_t *__restrict__ zstart,
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
     const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
     const double *__restrict__ rel_d2x, const double *__restrict__ rad, const uint16_t *__restrict__ scorer,
-    uint8_t *__restrict__ alive, unsigned long long *work,
-    unsigned long long *counters) {
+    uint8_t *__restrict__ alive, unsigned long long *work, unsigned long long *counters) {
+    // Per-wave cell table in visit order: first member, exclusive member
+    // prefix (entry 64 = total) and max(d(x,p), d(y,p)) lower bound.
+    __shared__ int32_t t_z0[kLuneWaves][64];
+    __shared__ int32_t t_pre[kLuneWaves][65];
+    __shared__ double t_gmax[kLuneWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t *z0t = t_z0[wv], *pre = t_pre[wv];
+    double *gmt = t_gmax[wv];
     // Dynamic, XCD-aware scheduling: workgroups are dealt round-robin to the
-    // 8 XCDs, so a wave on XCD c takes pairs one at a time from the c-th
-    // contiguous eighth of the list (sorted by row point: its witness cells
-    // stay in that XCD's L2), then helps the other eighths.  Pair costs vary
-    // by orders of magnitude, so static assignment would leave long tails.
-    const int lane = threadIdx.x & 63;
+    // 8 XCDs, so a wave on XCD c claims pairs from the c-th contiguous eighth
+    // of the list (sorted by row point: its witness cells stay in that XCD's
+    // L2), then helps the other eighths.  Pair costs vary by orders of
+    // magnitude, so static assignment would leave long tails.
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
-    uint32_t ntests = 0, ndist = 0;
+    uint32_t ntests = 0, ndist = 0, nrecheck = 0;
+    // Float32 screen: the direct-form sum of dp squared float32 differences
+    // has relative error below gamma_{dp+2} = (dp+2)u / (1 - (dp+2)u),
+    // u = 2^-24 (one rounding per difference, one per fused multiply-add,
+    // all terms non-negative).  With g = (dp+8)u > gamma, a float32 value
+    // below rd(d2 (1-g)) proves d^2 < d2 and one at or above ru(d2 (1+g))
+    // proves d^2 >= d2; anything between is decided again in exact float64.
+    const double g32 = (double)(dp + 8) * 0x1p-24;
     int64_t cur = 0, cend = 0;   // the wave's claimed chunk (uniform)
     for (;;) {
         if (cur >= cend) {
@@ -658,16 +694,19 @@ __global__ __launch_bounds__(256) void k_lune_guided(
         const double *ys = Xh + y * dp;
         const double nrx = nrmx[x], nry = nrmh[y];
         const double dxy_hi = sqrt_hi(d2);
+        const float *xf = F32 ? Xxf + x * dp : nullptr;
+        const float *yf = F32 ? Xhf + y * dp : nullptr;
+        const float tlo = __double2float_rd(d2 - d2 * g32), thi = __double2float_ru(d2 + d2 * g32);
         bool dead = false;
         const int64_t r0 = rel_off[x], r1 = rel_off[x + 1];
         for (int64_t c0 = r0; c0 < r1 && !dead; c0 += 64) {
             const int64_t c = c0 + lane;
             bool scan = false;
-            double dxl = 0.0, dyl = 0.0;
-            int32_t g = 0;
+            double gmax = 0.0;
+            int32_t z0 = 0, nmem = 0;
             float key = -INFINITY;
             if (c < r1) {
-                g = rel_grp[c];
+                const int32_t g = rel_grp[c];
                 const double d2x = rel_d2x[c];
                 const double d2y = nry + nrmp[g] - 2.0 * dot_lds(ys, Xp + (int64_t)g * dp, dp);
                 ++ndist;
@@ -675,86 +714,121 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 // Stage IV: the cell's pivot itself as a witness (exact); not
                 // when only part of each cell may witness (zstart given).
                 if (!zstart && d2x < d2 && d2y < d2) dead = true;
-                dxl = sqrt_lo(d2x);
-                dyl = sqrt_lo(d2y);
+                const double dxl = sqrt_lo(d2x), dyl = sqrt_lo(d2y);
+                gmax = fmax(dxl, dyl);
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
-                scan = !surely_ge(fmax(dxl, dyl), dvor[g], dxy_hi);
-                if (scan && scorer) {
-                    float f[kMlpFeatures];
-                    mlp_features(sqrt(d2x), sqrt(d2y), dvor[g], rad[g], grp_off[g + 1] - grp_off[g], sqrt(d2), f);
-                    key = mlp_score_bf16(scorer, f);
-                    if (!(key == key)) key = -INFINITY;   // keep (key, lane) a strict total order
+                scan = !surely_ge(gmax, dvor[g], dxy_hi);
+                if (scan) {
+                    z0 = zstart ? zstart[g] : grp_off[g];
+                    nmem = grp_off[g + 1] - z0;
+                    if (scorer) {
+                        float f[kMlpFeatures];
+                        mlp_features(sqrt(d2x), sqrt(d2y), dvor[g], rad[g], grp_off[g + 1] - grp_off[g], sqrt(d2),
+                                     f);
+                        key = mlp_score_bf16(scorer, f);
+                        if (!(key == key)) key = -INFINITY;   // keep (key, lane) a strict total order
+                    }
                 }
             }
             if (__ballot(dead)) { dead = true; break; }
-            uint64_t cells = __ballot(scan);
+            if (!__ballot(scan && nmem > 0)) continue;
             // Visit order: chunk order (cells sorted by distance to x), or by
             // descending learned score (wave bitonic sort of (score, lane)).
-            int order = lane;
-            if (scorer && cells) {
+            int src = lane;
+            if (scorer) {
                 float k = scan ? key : -INFINITY;
                 for (int sz = 2; sz <= 64; sz <<= 1)
                     for (int j = sz >> 1; j > 0; j >>= 1) {
                         const float ok = __shfl_xor(k, j, kWave);
-                        const int oi = __shfl_xor(order, j, kWave);
+                        const int oi = __shfl_xor(src, j, kWave);
                         const bool desc = (lane & sz) == 0;
                         const bool lower = (lane & j) == 0;
-                        const bool other_first = ok > k || (ok == k && oi < order);
+                        const bool other_first = ok > k || (ok == k && oi < src);
                         if (lower == desc ? other_first : !other_first) {
                             k = ok;
-                            order = oi;
+                            src = oi;
                         }
                     }
             }
-            for (int t = 0; cells && !dead; ++t) {
-                int src;
-                if (scorer && t < 64) {
-                    src = __shfl(order, t, kWave);
-                    if (!((cells >> src) & 1ull)) continue;
-                    cells &= ~(1ull << src);
-                } else {
-                    src = __ffsll((long long)cells) - 1;
-                    cells &= cells - 1;
-                }
-                const int32_t gg = __shfl(g, src, kWave);
-                const double gx = __shfl(dxl, src, kWave), gy = __shfl(dyl, src, kWave);
-                const double gmax = fmax(gx, gy);
-                const int64_t z0 = zstart ? zstart[gg] : grp_off[gg], z1 = grp_off[gg + 1];
-                // Four 64-point chunks per ballot: more loads in flight per wave.
-                for (int64_t zb = z0; zb < z1; zb += 256) {
-                    bool wit = false;
+            // Cell table in visit order (position = lane after the sort).
+            const int n_at = __shfl(scan ? nmem : 0, src, kWave);
+            const int incl = wave_incl_scan(n_at);
+            z0t[lane] = __shfl(z0, src, kWave);
+            gmt[lane] = __shfl(gmax, src, kWave);
+            pre[lane] = incl - n_at;
+            if (lane == 63) pre[64] = incl;
+            const int total = __shfl(incl, 63, kWave);
+            __builtin_amdgcn_wave_barrier();
+            int kc[4] = {0, 0, 0, 0};   // per-slot cursors into the table (monotone)
+            for (int base = 0; base < total; base += 256) {
+                bool wit = false;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int64_t z = zb + 64 * u + lane;
+                for (int u = 0; u < 4; ++u) {
+                    const int sl = base + 64 * u + lane;
+                    if (sl < total) {
+                        while (pre[kc[u] + 1] <= sl) ++kc[u];
+                        const int64_t z = z0t[kc[u]] + (sl - pre[kc[u]]);
                         // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
-                        if (z < z1 && !surely_ge(gmax, dhome[z], dxy_hi)) {
-                            const double *zr = Xh + z * dp;
-                            const double nz = nrmh[z];
-                            double sx = 0.0, sy = 0.0;
-                            for (int c = 0; c < dp; c += 2) {
-                                const double2 zv = *reinterpret_cast<const double2 *>(zr + c);
-                                sx = fma(xs[c], zv.x, sx);
-                                sx = fma(xs[c + 1], zv.y, sx);
-                                sy = fma(ys[c], zv.x, sy);
-                                sy = fma(ys[c + 1], zv.y, sy);
+                        if (!surely_ge(gmt[kc[u]], F32 ? (double)dhomef[z] : dhome[z], dxy_hi)) {
+                            bool exact = !F32;
+                            if (F32) {
+                                const float *zr = Xhf + z * dp;
+                                float sx = 0.f, sy = 0.f;
+                                for (int cc = 0; cc < dp; cc += 4) {
+                                    const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
+                                    float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
+                                    float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
+                                    sx = fmaf(a0, a0, sx);
+                                    sx = fmaf(a1, a1, sx);
+                                    sx = fmaf(a2, a2, sx);
+                                    sx = fmaf(a3, a3, sx);
+                                    a0 = yf[cc] - zv.x;
+                                    a1 = yf[cc + 1] - zv.y;
+                                    a2 = yf[cc + 2] - zv.z;
+                                    a3 = yf[cc + 3] - zv.w;
+                                    sy = fmaf(a0, a0, sy);
+                                    sy = fmaf(a1, a1, sy);
+                                    sy = fmaf(a2, a2, sy);
+                                    sy = fmaf(a3, a3, sy);
+                                }
+                                if (sx < tlo && sy < tlo)
+                                    wit = true;
+                                else if (!(sx >= thi || sy >= thi))
+                                    exact = true;   // too close to call in float32
+                                nrecheck += exact;
                             }
-                            wit = wit || ((nrx + nz - 2.0 * sx) < d2 && (nry + nz - 2.0 * sy) < d2);
+                            if (exact) {
+                                const double *zr = Xh + z * dp;
+                                const double nz = nrmh[z];
+                                double sx = 0.0, sy = 0.0;
+                                for (int cc = 0; cc < dp; cc += 2) {
+                                    const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
+                                    sx = fma(xs[cc], zv.x, sx);
+                                    sx = fma(xs[cc + 1], zv.y, sx);
+                                    sy = fma(ys[cc], zv.x, sy);
+                                    sy = fma(ys[cc + 1], zv.y, sy);
+                                }
+                                wit = wit || ((nrx + nz - 2.0 * sx) < d2 && (nry + nz - 2.0 * sy) < d2);
+                            }
                             ndist += 2;
                             ++ntests;
                         }
                     }
-                    if (__ballot(wit)) { dead = true; break; }
                 }
+                if (__ballot(wit)) { dead = true; break; }
             }
+            __builtin_amdgcn_wave_barrier();   // the table is rewritten by the next chunk
         }
         if (lane == 0) alive[p] = dead ? 0 : 1;
     }
     ntests = wave_sum(ntests);
     ndist = wave_sum(ndist);
+    nrecheck = wave_sum(nrecheck);
     if (lane == 0) {
         atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
         atomicAdd(&counters[C_LUNE], (unsigned long long)ntests);
         atomicAdd(&counters[C_DIST], (unsigned long long)ndist);
+        if (nrecheck) atomicAdd(&counters[C_RECHECK], (unsigned long long)nrecheck);
     }
 }
 
@@ -883,7 +957,8 @@ void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const 
 
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
-                        const double *dhome, const int32_t *zstart, const int32_t *grp_off,
+                        const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
+                        const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
                         const int32_t *rel_grp, const double *rel_d2x, const double *rad, const uint16_t *scorer,
                         uint8_t *alive, uint64_t *work, uint64_t *counters) {
@@ -891,10 +966,15 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 8));
-    k_lune_guided<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, zstart, grp_off, dvor,
-                                                              Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, alive,
-                                                              (unsigned long long *)work,
-                                                              (unsigned long long *)counters);
+    const bool f32 = Xxf && Xhf && dhomef;
+    if (f32)
+        k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
+            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
+            rel_off, rel_grp, rel_d2x, rad, scorer, alive, (unsigned long long *)work, (unsigned long long *)counters);
+    else
+        k_lune_guided<false><<<(unsigned)grid, 256, 0, s>>>(
+            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
+            rel_off, rel_grp, rel_d2x, rad, scorer, alive, (unsigned long long *)work, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 

@@ -26,8 +26,8 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def make_index(G, X, q, layer=None):
-    idx = G.Index(to_dev(X), grid_exp=q)
+def make_index(G, X, q, layer=None, precision=0):
+    idx = G.Index(to_dev(X), grid_exp=q, precision=precision)
     if layer is not None:
         idx.build_grng_layer(0, to_dev(np.asarray(layer[0], np.int32)), to_dev(np.asarray(layer[1], np.float32)))
     idx.build_rng()
@@ -41,14 +41,14 @@ def query_lists(idx, Q):
     return [nb[off[i]:off[i + 1]] for i in range(len(Q))]
 
 
-@pytest.mark.parametrize("layered", [True, False])
-def test_query_neighbors_match_oracle(G, layered):
-    say("query", layered)
+@pytest.mark.parametrize("layered,prec", [(True, 0), (True, 1), (False, 0)])
+def test_query_neighbors_match_oracle(G, layered, prec):
+    say("query", layered, "precision", prec)
     W = synth.clustered(n=2500, d=16, clusters=6, m=60, knn=40, sub=3)
     Q = synth.queries_like(W, 150)
     # plus: a duplicate of an indexed point and a far-away point
     Q = np.vstack([Q, W.X[17:18], np.full((1, 16), 20.0, np.float32)])
-    idx = make_index(G, W.X, W.q, (W.layers[0].pivot_ids, W.layers[0].radii) if layered else None)
+    idx = make_index(G, W.X, W.q, (W.layers[0].pivot_ids, W.layers[0].radii) if layered else None, prec)
     got = query_lists(idx, Q)
     idx.close()
     for i, qpt in enumerate(Q):
@@ -74,12 +74,12 @@ def test_query_capacity_protocol(G):
     idx.close()
 
 
-@pytest.mark.parametrize("layered", [True, False])
-def test_insert_batches_match_rebuild_oracle(G, layered):
-    say("insert", layered)
+@pytest.mark.parametrize("layered,prec", [(True, 0), (True, 1), (False, 0)])
+def test_insert_batches_match_rebuild_oracle(G, layered, prec):
+    say("insert", layered, "precision", prec)
     W = synth.clustered(n=2000, d=8, clusters=5, m=50, knn=30, sub=4)
     batches = synth.insert_batches(W, n_batches=3, lo=100, hi=900, sub=1)
-    idx = make_index(G, W.X, W.q, (W.layers[0].pivot_ids, W.layers[0].radii) if layered else None)
+    idx = make_index(G, W.X, W.q, (W.layers[0].pivot_ids, W.layers[0].radii) if layered else None, prec)
     allX = W.X
     for bi, B in enumerate(batches):
         idx.insert_batch(to_dev(B))
@@ -98,7 +98,7 @@ def test_insert_order_invariance_and_duplicates(G):
     b = synth.insert_batches(W, n_batches=2, lo=200, hi=400, sub=2)
     dup = W.X[:50].copy()            # exact duplicates of indexed points
     lay = (W.layers[0].pivot_ids, W.layers[0].radii)
-    i1 = make_index(G, W.X, W.q, lay)
+    i1 = make_index(G, W.X, W.q, lay, precision=1)
     for B in (b[0], b[1], dup):
         i1.insert_batch(to_dev(B))
     e1 = i1.edges().cpu().numpy().astype(np.int64)

@@ -28,6 +28,11 @@ def G():
     return P
 
 
+# Both distance precisions must give identical edges: float64 everywhere
+# (0), and float32 screens with exact float64 re-decision (1).
+PRECISIONS = [0, 1]
+
+
 def golden_edges(name):
     rows = [ln.split() for ln in open(os.path.join(HERE, "golden", name)) if ln.strip() and not ln.startswith("#")]
     return np.array(rows, dtype=np.int64).reshape(-1, 2)
@@ -70,11 +75,12 @@ def test_uniform2d_1000_guided_matches_golden(G):
     assert np.array_equal(lay[0], native.grng_edges(W.X[pid], rad, W.q))
 
 
-def test_clustered_3000_d16_matches_golden(G):
-    say("clustered n=3000 d=16 m=60")
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_clustered_3000_d16_matches_golden(G, prec):
+    say("clustered n=3000 d=16 m=60 precision", prec)
     W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
     L = W.layers[0]
-    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec)
     assert np.array_equal(E, golden_edges("clustered_n3000_d16_rng_edges.txt"))
     assert np.array_equal(lay[0], golden_edges("clustered_n3000_d16_m60_grng_edges.txt"))
     assert st["candidate_pairs"] > 0
@@ -84,16 +90,17 @@ def test_clustered_3000_d16_matches_golden(G):
     (1037, 2, 30, 4, 0), (2111, 3, 70, 6, 1), (1500, 5, 16, 3, 2), (777, 16, 100, 5, 3),
     (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7),
     (900, 96, 24, 3, 8), (500, 100, 10, 2, 9)])
-def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed):
-    say("ragged", n, d, m, clusters, seed)
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed, prec):
+    say("ragged", n, d, m, clusters, seed, "precision", prec)
     # 2^-18 grid above 64 dimensions keeps d * kmax^2 below 2^51
     W = synth.clustered(n=n, d=d, clusters=clusters, m=m, knn=min(30, n - 1), q=18 if d > 64 else 19, sub=seed)
     L = W.layers[0]
     want = native.rng_edges(W.X, W.q)
-    E, lay, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    E, lay, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec)
     assert np.array_equal(E, want)
     assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
-    Eb, _, _ = gpu_edges(G, W.X, W.q)
+    Eb, _, _ = gpu_edges(G, W.X, W.q, precision=prec)
     assert np.array_equal(Eb, want)
 
 
@@ -107,8 +114,9 @@ def test_stage4_pivot_count_does_not_change_edges(G):
         assert np.array_equal(E, want), k
 
 
-def test_degenerate_inputs(G):
-    say("degenerate inputs")
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_degenerate_inputs(G, prec):
+    say("degenerate inputs precision", prec)
     # one point, two points, all identical, 1-D path, boundary tie, collinear.
     cases = [np.zeros((1, 3), np.float32), np.array([[0, 0], [1, 2]], np.float32),
              np.zeros((7, 4), np.float32),
@@ -118,20 +126,21 @@ def test_degenerate_inputs(G):
              np.array([[0], [0], [1]], np.float32)]
     for X in cases:
         want = rng.rng_edges(exact.to_grid(X, 0))
-        E, _, _ = gpu_edges(G, X, 0)
+        E, _, _ = gpu_edges(G, X, 0, precision=prec)
         assert np.array_equal(E, want), X
         if len(X) >= 3:   # same with every point a zero-radius pivot (GRNG = RNG, Section 2)
             pid = np.arange(len(X), dtype=np.int32)
-            E2, lay, _ = gpu_edges(G, X, 0, [(pid, np.zeros(len(X), np.float32))])
+            E2, lay, _ = gpu_edges(G, X, 0, [(pid, np.zeros(len(X), np.float32))], precision=prec)
             assert np.array_equal(E2, want)
             assert np.array_equal(lay[0], want)
 
 
-def test_grid_lattice_with_pivots(G):
-    say("lattice 20x20 with pivots")
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_grid_lattice_with_pivots(G, prec):
+    say("lattice 20x20 with pivots precision", prec)
     K = np.array([(i, j) for i in range(20) for j in range(20)], np.float32)
     pid = np.arange(0, 400, 7, dtype=np.int32)
-    E, lay, _ = gpu_edges(G, K, 0, [(pid, np.full(len(pid), 2.0, np.float32))])
+    E, lay, _ = gpu_edges(G, K, 0, [(pid, np.full(len(pid), 2.0, np.float32))], precision=prec)
     assert len(E) == 2 * 20 * 19
     assert np.array_equal(E, rng.rng_edges(exact.to_grid(K, 0)))
 
@@ -166,11 +175,17 @@ def test_error_statuses(G):
 
 def test_clustered_full_size_sampled_rows(G):
     """The 100k x 16-D, 32-cluster, 1,000-pivot workload in the bench's launch
-    configuration; sampled rows compared with the oracle one by one."""
+    configuration, in both precisions: sampled rows compared with the oracle
+    one by one, and the two edge sets compared in full."""
     say("clustered full size n=100000 d=16 m=1000")
     W = synth.clustered()
     L = W.layers[0]
-    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)])
+    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=0)
+    say("stats fp64", st)
+    E32, lay32, st32 = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=1)
+    say("stats fp32", st32)
+    assert np.array_equal(E32, E)
+    assert np.array_equal(lay32[0], lay[0])
     assert np.all(E[:, 0] < E[:, 1])
     assert np.all(np.diff(E[:, 0]) >= 0)
     g = np.random.default_rng(99)
@@ -181,7 +196,28 @@ def test_clustered_full_size_sampled_rows(G):
         assert np.array_equal(got, row), x
     # GRNG of the full 1,000-pivot layer in full.
     assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
-    say("stats", st)
+
+
+def test_float32_screen_redecides_exact_ties(G):
+    """3-4-5 triangles A=(0,0), B=(5,0), C=(3,4) far apart: for the pair
+    (A, B) the point C sits exactly on the lune boundary (d(A,C) = d(A,B) = 5),
+    so the edge is kept (strict lune) and the float32 screen cannot decide C:
+    those comparisons must be re-decided in float64."""
+    say("float32 screen on exact ties")
+    g = np.random.default_rng(5)
+    offs = np.unique(g.integers(0, 60, size=(80, 2)), axis=0)[:50] * 100
+    tri = np.array([[0, 0], [5, 0], [3, 4]])
+    P = (offs[:, None, :] + tri[None, :, :]).reshape(-1, 2).astype(np.float32)
+    pid = np.arange(2, len(P), 3, dtype=np.int32)      # each C is a pivot of radius 5
+    rad = np.full(len(pid), 5.0, np.float32)
+    want = rng.rng_edges(exact.to_grid(P, 0))
+    for prec in PRECISIONS:
+        E, _, st = gpu_edges(G, P, 0, [(pid, rad)], precision=prec)
+        assert np.array_equal(E, want), prec
+        if prec == 1:
+            assert st["rechecks"] > 0
+        else:
+            assert st["rechecks"] == 0
 
 
 def test_grng_layer_exact_ties_use_the_integer_predicate(G):
@@ -206,14 +242,15 @@ def test_grng_layer_exact_ties_use_the_integer_predicate(G):
             assert st["rechecks"] > 0
 
 
-@pytest.mark.parametrize("n,d,mf,mc,seed", [(6000, 32, 240, 12, 0), (3000, 8, 150, 20, 1)])
-def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed):
+@pytest.mark.parametrize("n,d,mf,mc,seed,prec", [(6000, 32, 240, 12, 0, 0), (6000, 32, 240, 12, 0, 1),
+                                                 (3000, 8, 150, 20, 1, 1)])
+def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed, prec):
     """Coarse layer -> guided fine layer (Theorem 2) -> RNG, on the
     8-dimensional-subspace workload family at reduced size."""
-    say("three layers", n, d, mf, mc, seed)
+    say("three layers", n, d, mf, mc, seed, "precision", prec)
     W = synth.subspace3(n=n, d=d, m_fine=mf, m_coarse=mc, sub=seed)
     (Lc, Lf) = W.layers
-    E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)])
+    E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)], precision=prec)
     assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
     assert np.array_equal(lay[1], native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q))
     assert np.array_equal(E, native.rng_edges(W.X, W.q))
