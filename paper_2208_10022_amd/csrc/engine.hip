@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -314,6 +315,17 @@ void build_rng_brute(grng_index *idx, DevBuf &edges, int64_t &ne, double &ms_lun
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), nullptr, edges, ne);
 }
 
+// Stage trace on stderr when the environment sets GRNG_TRACE (diagnostics of
+// long builds: each line is printed when its stage has finished on the device).
+bool trace_on() {
+    static const bool on = std::getenv("GRNG_TRACE") != nullptr;
+    return on;
+}
+
+void trace(const char *stage, double ms, int64_t count) {
+    if (trace_on()) std::fprintf(stderr, "[grng] %s done: %.1f ms (%lld)\n", stage, ms, (long long)count);
+}
+
 struct BuildTimes {
     double vgrng = 0, pairs = 0, lune = 0;
     int64_t tile_pairs = 0;
@@ -361,6 +373,7 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     std::vector<int32_t> h_home, h_npar, h_gcount((size_t)m, 0);
     std::vector<double> h_d2home, h_d2vor((size_t)m, 0.0);
     d2h(h_home, home.p, (size_t)n, s);
+    trace("pivot distances and home cells", 0.0, n * m);
     d2h(h_npar, npar.p, (size_t)n, s);
     if (indexed) d2h(h_d2home, d2home.p, (size_t)n, s);
     // Home order: stable counting sort by home cell (host, O(n)).
@@ -428,7 +441,9 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
                      L.rad.as<double>(), C.dvor.as<double>(), C.gcount.as<int32_t>(), P.par_off.as<int64_t>(),
                      P.par_idx.as<int32_t>(), L.bits.as<uint64_t>(), words, P.g_rows.as<uint64_t>(),
                      P.v_rows.as<uint64_t>(), ctr);
-        bt.vgrng += vt.stop();
+        const double ms = vt.stop();
+        bt.vgrng += ms;
+        trace("virtual-pivot bitsets", ms, n);
     }
     P.nw = div_up(n, 64);
     P.g_cols.alloc(8 * (size_t)(m * P.nw));
@@ -492,7 +507,16 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
                       B.tv.as<uint64_t>(), nb, words, mode, toff.as<int64_t>(), tcnt.as<int32_t>(), tpT.as<int32_t>(),
                       tpU.as<int32_t>());
     dmax.alloc(8 * (size_t)std::max<int64_t>(A.n, 1));
+    // Survivor capacity: 64 per point.  A pass that overflows is run again
+    // with the exact size; at a million points a pass takes tens of seconds
+    // where pruning is weak, so there the first capacity is 256 per point
+    // when a quarter of the free device memory holds it.
     int64_t cap = std::max<int64_t>(1 << 22, 64 * A.n);
+    if (A.n >= 500000) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+            cap = std::max<int64_t>(cap, std::min<int64_t>(256 * A.n, (int64_t)(fr / 4 / 17)));
+    }
     std::vector<uint64_t> snapshot;
     d2h(snapshot, idx->counters.p, C_NUM, s);
     const PointsView va = view_of(A, with_new), vb = view_of(B, with_new);
@@ -504,7 +528,9 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
         launch_pairs_tiled(s, ntp, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, idx->dp, words,
                            aux.pknn.as<int32_t>(), K, aux.Xp.as<double>(), aux.nrmp.as<double>(), P.view(),
                            dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
-        bt.pairs += pt.stop();
+        const double ms = pt.stop();
+        bt.pairs += ms;
+        trace("tile pairs (Stages I-V)", ms, ntp);
         std::vector<uint64_t> h;
         d2h(h, P.count.p, 1, s);
         np = (int64_t)h[0];
@@ -566,7 +592,9 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                        rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
                        idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,
                        alive.as<uint8_t>(), ctr + C_WORK0, ctr);
-    bt.lune += lt.stop();
+    const double lms = lt.stop();
+    bt.lune += lms;
+    trace("exhaustive lune scan", lms, np);
     if (keep) {
         keep->valid = true;
         keep->np = np;

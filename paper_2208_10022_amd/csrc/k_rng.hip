@@ -562,43 +562,75 @@ __global__ void k_pairs_all(int64_t nA, const double *__restrict__ XA, const dou
 // pair (x, y) of x only if d(x, p_c) - radius(c) < max_y d(x, y)
 // (Proposition 3 with the x-side distance alone).  pass 0 counts, pass 1
 // fills the cells sorted by d(x, p_c) ascending with their exact d^2(x, p_c).
-__global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, int32_t mpow2, const int32_t *perm,
+constexpr int kRelSortMax = 4096;   // kept cells sorted in LDS per row (12 bytes each)
+
+__global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, const int32_t *perm,
                                                         const double *dxp, const double *dvor, const int32_t *gcount,
                                                         const uint64_t *dmax_bits, const int64_t *rel_off,
                                                         int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
                                                         int pass) {
+    // Pass 0 counts the cells of row point i that may hold a witness of any
+    // of its pairs (Proposition 3 with the row's largest pair distance);
+    // pass 1 writes them, nearest pivot first (a bitonic sort in LDS), or in
+    // pivot order when there are more than kRelSortMax of them (the order
+    // only steers the scan, it never changes a verdict).
     extern __shared__ unsigned char smem[];
     double *key = (double *)smem;
-    int32_t *kid = (int32_t *)(key + mpow2);
+    int32_t *kid = (int32_t *)(key + kRelSortMax);
     const int lane = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= n) return;
     const double dmax2 = __longlong_as_double((long long)dmax_bits[i]);
+    if (!(dmax2 > 0.0)) {
+        if (pass == 0 && lane == 0) rel_cnt[i] = 0;
+        return;
+    }
+    int64_t o = 0, cnt = 0;
+    if (pass == 1) {
+        o = rel_off[i];
+        cnt = rel_off[i + 1] - o;
+        if (cnt == 0) return;
+    }
+    const bool sorted = cnt <= kRelSortMax;
     const double dmax_hi = sqrt_hi(dmax2);
     const double *row = dxp + (int64_t)perm[i] * m;
-    int cnt = 0;
-    for (int64_t k0 = 0; k0 < mpow2; k0 += 64) {
+    int64_t pos = 0;
+    for (int64_t k0 = 0; k0 < m; k0 += 64) {
         const int64_t k = k0 + lane;
         bool keep = false;
         double d2 = INFINITY;
-        if (k < m && dmax2 > 0.0 && gcount[k] > 0) {
+        if (k < m && gcount[k] > 0) {
             d2 = row[k];
             keep = !surely_ge(sqrt_lo(d2), dvor[k], dmax_hi);
         }
-        cnt += __popcll(__ballot(keep));
-        if (pass == 1 && k < mpow2) {
-            key[k] = keep ? d2 : INFINITY;
-            kid[k] = (int32_t)k;
+        const uint64_t bal = __ballot(keep);
+        if (pass == 1 && keep) {
+            const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
+            if (sorted) {
+                key[t] = d2;
+                kid[t] = (int32_t)k;
+            } else {
+                rel_grp[o + t] = (int32_t)k;
+                rel_d2x[o + t] = d2;
+            }
         }
+        pos += __popcll(bal);
     }
     if (pass == 0) {
-        if (lane == 0) rel_cnt[i] = cnt;
+        if (lane == 0) rel_cnt[i] = (int32_t)pos;
         return;
     }
+    if (!sorted) return;
+    int32_t P = 64;
+    while (P < cnt) P <<= 1;
+    for (int64_t t = cnt + lane; t < P; t += 64) {
+        key[t] = INFINITY;
+        kid[t] = INT32_MAX;
+    }
     __syncthreads();
-    for (int32_t size = 2; size <= mpow2; size <<= 1) {
+    for (int32_t size = 2; size <= P; size <<= 1) {
         for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t t = lane; t < (mpow2 >> 1); t += 64) {
+            for (int32_t t = lane; t < (P >> 1); t += 64) {
                 const int32_t lo = 2 * t - (t & (stride - 1));
                 const int32_t hi = lo + stride;
                 const bool up = (lo & size) == 0;
@@ -613,8 +645,7 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, in
             __syncthreads();
         }
     }
-    const int64_t o = rel_off[i];
-    for (int t = lane; t < cnt; t += 64) {
+    for (int64_t t = lane; t < cnt; t += 64) {
         rel_grp[o + t] = kid[t];
         rel_d2x[o + t] = key[t];
     }
@@ -676,6 +707,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     // below rd(d2 (1-g)) proves d^2 < d2 and one at or above ru(d2 (1+g))
     // proves d^2 >= d2; anything between is decided again in exact float64.
     const double g32 = (double)(dp + 8) * 0x1p-24;
+    const bool xself = Xx == Xh;   // x is a point of the scanned set (not a query)
     int64_t cur = 0, cend = 0;   // the wave's claimed chunk (uniform)
     for (;;) {
         if (cur >= cend) {
@@ -768,6 +800,8 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                     if (sl < total) {
                         while (pre[kc[u] + 1] <= sl) ++kc[u];
                         const int64_t z = z0t[kc[u]] + (sl - pre[kc[u]]);
+                        // The pair's own points are never witnesses (max = d(x,y)).
+                        if (z == y || (xself && z == x)) continue;
                         // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
                         if (!surely_ge(gmt[kc[u]], F32 ? (double)dhomef[z] : dhome[z], dxy_hi)) {
                             bool exact = !F32;
@@ -930,15 +964,13 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x) {
     if (n == 0) return;
-    int32_t mp = 64;
-    while (mp < m) mp <<= 1;
-    const size_t lds = (size_t)mp * (sizeof(double) + sizeof(int32_t));
-    require(lds <= 160 * 1024, GRNG_EINVAL, "pivot layer too large for the witness-cell pass");
+    require(n <= 0x7fffffffLL, GRNG_EINVAL, "too many points for the witness-cell pass");
+    const size_t lds = (size_t)kRelSortMax * (sizeof(double) + sizeof(int32_t));
     if (rel_off == nullptr) {
-        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, mp, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
+        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
                                                        nullptr, nullptr, 0);
     } else {
-        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, mp, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt,
+        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt,
                                                        rel_grp, rel_d2x, 1);
     }
     GRNG_LAUNCHED();

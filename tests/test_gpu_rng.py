@@ -254,3 +254,24 @@ def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed, prec):
     assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
     assert np.array_equal(lay[1], native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q))
     assert np.array_equal(E, native.rng_edges(W.X, W.q))
+
+
+def test_subspace3_full_size_sampled_rows(G):
+    """The three-layer workload at full size: 1,000,000 points in 32-D near an
+    8-D subspace, 100 coarse and 3,000 fine pivots.  Both GRNG layers are
+    checked (coarse in full, fine on sampled rows) and RNG rows of sampled
+    points are compared with the oracle one by one."""
+    say("subspace3 full size n=1000000 d=32 m=100/3000")
+    W = synth.subspace3()
+    (Lc, Lf) = W.layers
+    E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)], precision=1)
+    say("stats", st)
+    assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
+    want_f = native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)
+    assert np.array_equal(lay[1], want_f)
+    g = np.random.default_rng(7)
+    xs = g.choice(W.n, 12, replace=False)
+    rows = native.rng_rows(W.X, W.q, xs)
+    for x, row in zip(xs, rows):
+        got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
+        assert np.array_equal(got, row), x
