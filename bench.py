@@ -28,30 +28,77 @@ MI355X_FP64_TFLOPS = 78.6
 MI355X_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def roofline(st: dict) -> dict:
-    """Roofline entry for the main kernel that took the longest in the last build.
+KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "common.h"], "k_lune_guided": ["k_rng.hip", "common.h"],
+                  "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
 
-    virtual-pivot (min,max) kernel: ALU-bound, 2 VALU ops (one max, one min)
-        per (point, pivot j, pivot k) triple for each of the two radius choices:
-        algorithmic ops = 2 * vgrng_ops.
-    tiled pair kernel: MFMA f64 tiles, algorithmic flops = pairs_flops.
-    exhaustive lune kernel: witness rows streamed, algorithmic bytes =
-        (8 dp + 16) per witness test = lune_bytes.
+
+def source_hash(kernel: str) -> str:
+    """sha256 of the sources a kernel is built from (to tell whether measured counters still apply)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2208_10022_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and this workload; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != source_hash(kernel) or rec.get("workload") != workload:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def kernel_rooflines(st: dict) -> dict:
+    """Per main kernel of the last build: time and achieved fraction of its roof.
+
+    k_vgrng_tiles  (min,max) product, VALU: 2 ops per (point, pivot j, pivot k)
+                   for each of two radius choices = 2 * vgrng_ops.
+    k_pairs_tiled  MFMA f64 distance tiles (pairs_flops) and the Stage IV
+                   (min,max) product on the VALU (stage4_ops); the roof is the
+                   one with the longer time at peak.
+    k_lune_guided  witness rows streamed: lune_bytes (row + cell bound per
+                   witness test) against HBM bandwidth.
     """
-    kernels = {"vgrng": st["ms_vgrng"], "pairs": st["ms_pairs"], "lune": st["ms_lune"]}
-    k = max(kernels, key=kernels.get)
-    ms = kernels[k]
-    if k == "vgrng":
-        ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12
-        return {"kernel": "k_vgrng_tiles", "bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS,
-                "unit": "Tops/s (fp32 min/max)", "frac": ach / MI355X_VALU_TOPS, "traffic": None, "ms": ms}
-    if k == "pairs":
+    out = {}
+    ms = st["ms_vgrng"]
+    ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12
+    out["k_vgrng_tiles"] = {"bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS, "unit": "Tops/s",
+                            "frac": ach / MI355X_VALU_TOPS, "ms": ms}
+    ms = st["ms_pairs"]
+    t_mfma = st["pairs_flops"] / (MI355X_FP64_TFLOPS * 1e12)
+    t_valu = st["stage4_ops"] / (MI355X_VALU_TOPS * 1e12)
+    if t_mfma >= t_valu:
         ach = st["pairs_flops"] / (ms / 1e3) / 1e12
-        return {"kernel": "k_pairs_tiled", "bound": "mfma", "achieved": ach, "peak": MI355X_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / MI355X_FP64_TFLOPS, "traffic": None, "ms": ms}
+        out["k_pairs_tiled"] = {"bound": "mfma", "achieved": ach, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
+                                "frac": ach / MI355X_FP64_TFLOPS, "ms": ms,
+                                "valu_frac": t_valu / (ms / 1e3)}
+    else:
+        ach = st["stage4_ops"] / (ms / 1e3) / 1e12
+        out["k_pairs_tiled"] = {"bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS, "unit": "Tops/s",
+                                "frac": ach / MI355X_VALU_TOPS, "ms": ms, "mfma_frac": t_mfma / (ms / 1e3)}
+    ms = st["ms_lune"]
     ach = st["lune_bytes"] / (ms / 1e3) / 1e9
-    return {"kernel": "k_lune_guided", "bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-            "frac": ach / MI355X_HBM_GBS, "traffic": None, "ms": ms}
+    out["k_lune_guided"] = {"bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                            "frac": ach / MI355X_HBM_GBS, "ms": ms}
+    return out
+
+
+def roofline(st: dict, workload: str) -> dict:
+    """Roofline entry for the main kernel that took the longest in the last build."""
+    ks = kernel_rooflines(st)
+    k = max(ks, key=lambda name: ks[name]["ms"])
+    r = dict(ks[k])
+    r["kernel"] = k
+    r["traffic"] = measured_traffic(k, workload)
+    return r
 
 
 def parse():
@@ -150,6 +197,7 @@ def main():
     edges = idx.num_edges()
     idx.close()
 
+    workload = "clustered-n%d-d16-m1000-p%d" % (W.n, args.precision)
     line = {
         "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
         "value": ms / 1000.0,
@@ -184,7 +232,8 @@ def main():
         "ms_vgrng": st["ms_vgrng"],
         "ms_pairs": st["ms_pairs"],
         "ms_lune": st["ms_lune"],
-        "roofline": roofline(st),
+        "roofline": roofline(st, workload),
+        "kernels": kernel_rooflines(st),
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:

@@ -108,9 +108,14 @@ typedef struct grng_stats {
     double ms_pairs;              /* device time of the tiled candidate-pair kernel in the last build */
     double ms_lune;               /* device time of the exhaustive lune kernel in the last build */
     double vgrng_ops;             /* (min,max) pairs evaluated by the virtual-pivot kernel: 2 n m^2 */
-    double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair */
-    double lune_bytes;            /* algorithmic bytes read by the lune kernel: (8 dp + 16) per witness test */
-    double reserved[4];
+    double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair,
+                                     plus 2 dp * 2*64*64 per tile pair that reaches Stage V */
+    double lune_bytes;            /* algorithmic bytes read by the lune kernel per witness test: the
+                                     witness row and its cell bound, 4 dp + 4 with the float32 screen,
+                                     8 dp + 16 in float64 */
+    double stage4_ops;            /* (min,max) operations of Stage IV in the pair kernel: 2*64*64*K'
+                                     per tile pair, K' = pivot witnesses rounded up to a multiple of 4 */
+    double reserved[3];
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -125,6 +125,7 @@ enum Counter {
     C_RECHECK,        // exact re-decisions
     C_SURV,           // pairs left for the exhaustive scan (after Stage V)
     C_LUNE,           // witness predicates evaluated by the exhaustive scan
+    C_TPV,            // tile pairs that reached Stage V (in-tile distance matrices computed)
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,

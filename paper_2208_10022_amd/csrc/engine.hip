@@ -637,10 +637,21 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.rechecks = (double)c[C_RECHECK];
     idx->stats.exhaustive_pairs = (double)c[C_SURV];
     idx->stats.lune_tests = (double)c[C_LUNE];
-    idx->stats.lune_bytes = (double)c[C_LUNE] * (8.0 * idx->dp + 16.0);
+    // Bytes a witness test reads: the witness row and its cell-distance
+    // bound (float32 with the float32 screen; float64 row, norm and bound
+    // otherwise).
+    idx->stats.lune_bytes = (double)c[C_LUNE] * (idx->opt.precision == GRNG_PREC_FP64 ? 8.0 * idx->dp + 16.0
+                                                                                     : 4.0 * idx->dp + 4.0);
     const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
     idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * m;
-    idx->stats.pairs_flops = 2.0 * idx->dp * (64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs;
+    // MFMA flops of the pair kernel: D(T,U) and the two pivot blocks for every
+    // tile pair, D(T,T) and D(U,U) for those that reach Stage V.
+    idx->stats.pairs_flops = 2.0 * idx->dp * ((64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs +
+                                              2.0 * 64.0 * 64.0 * (double)c[C_TPV]);
+    {
+        const int K = idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK;
+        idx->stats.stage4_ops = 2.0 * 64.0 * 64.0 * (double)((K + 3) / 4 * 4) * (double)bt.tile_pairs;
+    }
 }
 
 void do_build_rng(grng_index *idx) {

@@ -106,16 +106,19 @@ __device__ inline bool claim_chunk(int64_t n, int64_t chunk, int xcd0, int &xr, 
 //   * Stage IV: the pivots nearest to the two cells as witnesses, with exact
 //     d^2 to the pivots from two more MFMA tiles;
 //   * Stage V: the 128 points of T and U as witnesses.  The in-tile distance
-//     matrices D(T,U), D(T,T), D(U,U) are exact f64 MFMA results rounded
-//     down to float32 and kept in LDS.  z is taken as a witness only when
-//     rd(d^2(x,z)) < rd(d^2(x,y)) and rd(d^2(y,z)) < rd(d^2(x,y)), which
-//     implies the exact strict inequalities (rd(a) < rd(b) <= b and
-//     a < next(rd(a)) <= rd(b)).  A pair whose only witnesses are too close
-//     to call survives to the exact scan, so no edge depends on rounding.
+//     matrices D(T,U), D(T,T), D(U,U) are exact f64 MFMA results rounded to
+//     nearest float32 and kept in LDS.  With u = 2^-24 each stored value is
+//     within a factor (1 +- u) of the exact one, and max/min of rounded
+//     values are the rounded max/min, so fl(max(d^2(x,z), d^2(y,z))) <
+//     fl(d^2(x,y)) * (1 - 2^-21) (itself rounded) proves the exact strict
+//     inequality: (1+u)^3 (1 - 8u) < 1.  The same certificate ends a pair in
+//     Stage IV.  A pair whose only witnesses are too close to call survives
+//     to the exact scan, so no edge depends on rounding.
 // Survivors go to the global pair list for the exhaustive scan.
 constexpr int kTile = 64;
 constexpr int kPiv = 16;        // pivot witnesses per tile pair (one MFMA column block)
 constexpr int kDl = kTile + 1;  // row stride (floats) of the in-tile distance matrices
+constexpr float kCertain = 1.0f - 0x1p-21f;   // threshold factor of the float32 witness certificate
 constexpr int kXs = kPiv + 4;   // row stride (floats) of the pivot distances: 16-byte aligned rows
 constexpr int kPairChunk = 8;   // tile pairs claimed per atomic
 constexpr int kLuneChunk = 4;   // pairs claimed per atomic by one wave of the exhaustive scan
@@ -180,12 +183,13 @@ struct WaveOut {
 constexpr int kPairThreads = 512;   // 8 waves per tile pair
 constexpr int kPairWaves = kPairThreads / 64;
 
-// One wave, nb independent 16x16 blocks of rd/ru |a_i - b_j|^2 at once (the
-// MFMA chains interleave, so the matrix unit is not idle on dependences).
+// One wave, NB independent 16x16 blocks of |a_i - b_j|^2 at once: exact f64
+// MFMA results rounded to nearest float32 (the MFMA chains interleave, so the
+// matrix unit is not idle on dependences).
 template <int NB>
 __device__ inline void dist_blocks(const double *const sa[NB], const double *const na[NB], const double *const sb[NB],
                                    const double *const nb[NB], const int r0[NB], const int c0[NB], int dp, int ld,
-                                   float *const D[NB], const int dld[NB], const bool up[NB]) {
+                                   float *const D[NB], const int dld[NB]) {
     const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
     v4d acc[NB];
 #pragma unroll
@@ -204,8 +208,7 @@ __device__ inline void dist_blocks(const double *const sa[NB], const double *con
     for (int q = 0; q < NB; ++q)
         for (int r = 0; r < 4; ++r) {
             const int i = r0[q] + 4 * r + kl, j = c0[q] + il;
-            const double v = na[q][i] + nb[q][j] - 2.0 * acc[q][r];
-            D[q][i * dld[q] + j] = up[q] ? __double2float_ru(v) : __double2float_rd(v);
+            D[q][i * dld[q] + j] = (float)(na[q][i] + nb[q][j] - 2.0 * acc[q][r]);
         }
 }
 
@@ -215,9 +218,9 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *work,
     unsigned long long *counters) {
     // LDS: rows of T and U (ld = dp + 1 doubles per row), norms, candidate
-    // masks, the 64 x 64 bit mask of Stage IV survivors, rd D(T,U); then
-    // either the pivot rows and rounded-up pivot distances (Stages I-IV) or
-    // rd D(T,T) and rd D(U,U) (Stage V) in the same bytes.
+    // masks, the 64 x 64 bit mask of Stage IV survivors, D(T,U); then either
+    // the pivot rows and pivot distances (Stages I-IV) or D(T,T) and D(U,U)
+    // (Stage V) in the same bytes.
     extern __shared__ double lds[];
     const int ld = dp + 1;
     double *sX = lds, *sY = sX + kTile * ld;
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     float *DTT = region, *DUU = region + kTile * kDl;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool self = (mode & PM_SELF) != 0;
-    uint32_t ncand = 0, ns4 = 0, nsurv = 0;
+    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0;
     WaveOut wo;
     __shared__ int64_t s_tp;
     __shared__ int s_any;
@@ -304,8 +307,8 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             load_rows(sY, B.Xh + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
         __syncthreads();
         // 2a. Per wave: one 16-row block of d^2 to the pivot witnesses (rows
-        // of T for waves 0-3, of U for 4-7; rounded up, +inf past K) and two
-        // 16x16 blocks of rd D(T,U); three interleaved MFMA f64 chains.
+        // of T for waves 0-3, of U for 4-7; +inf past K) and two 16x16 blocks
+        // of D(T,U); three interleaved MFMA f64 chains, float32 results.
         {
             const bool ys = w >= 4;
             const int pr = (w & 3) * 16;
@@ -318,8 +321,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             const int c0[3] = {0, (id0 & 3) * 16, (id1 & 3) * 16};
             float *D[3] = {ys ? YP : XP, DTU, DTU};
             const int dld[3] = {kXs, kDl, kDl};
-            const bool up[3] = {true, false, false};
-            dist_blocks<3>(sa, na, sb, nb, r0, c0, dp, ld, D, dld, up);
+            dist_blocks<3>(sa, na, sb, nb, r0, c0, dp, ld, D, dld);
             if ((lane & 15) >= K) {   // unused pivot slots never witness
                 float *Pd = ys ? YP : XP;
                 for (int r = 0; r < 4; ++r) Pd[(pr + 4 * r + (lane >> 4)) * kXs + (lane & 15)] = INFINITY;
@@ -328,8 +330,9 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         __syncthreads();
         // 2b. Stages I-IV for all 64 x 64 pairs: thread = rows ty + 16k
         // (k < 4) x columns tx, tx + 32.  C = min over pivots of max(d^2(x,p),
-        // d^2(y,p)) (rounded up) as a (min,max) product over LDS rows; a
-        // candidate dies when C < rd d^2(x,y), which proves a pivot witness.
+        // d^2(y,p)) as a (min,max) product over LDS rows; a candidate dies
+        // when C < d^2(x,y) * (1 - 2^-21) in float32, which proves a pivot
+        // witness.
         {
             const int tx = tid & 31, ty = tid >> 5;
             float c[4][2];
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                     const int j = tx + 32 * q;
                     const bool cand = ((mxi >> j) & 1ull) && (((q ? my1 : my0) >> i) & 1ull);
                     ncand += cand;
-                    if (cand && !(c[r][q] < DTU[i * kDl + j])) bits |= 1ull << j;
+                    if (cand && !(c[r][q] < DTU[i * kDl + j] * kCertain)) bits |= 1ull << j;
                 }
                 if (bits) {
                     ns4 += __popcll(bits);
@@ -374,7 +377,8 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         __syncthreads();
         if (!s_any) continue;   // uniform: no Stage IV survivor in this tile pair
-        // 2c. rd D(T,T) (only when T's points may witness) and rd D(U,U),
+        ntpv += tid == 0;
+        // 2c. D(T,T) (only when T's points may witness) and D(U,U),
         // written over the pivot data, which is dead now: waves 0-3 take
         // D(T,T), waves 4-7 D(U,U), four interleaved blocks each.
         if (self || w >= 4) {
@@ -382,7 +386,6 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             const double *sa[2], *na[2];
             int r0[2], c0[2], dld[2] = {kDl, kDl};
             float *D[2];
-            bool up[2] = {false, false};
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
@@ -393,20 +396,20 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                     c0[q] = (id & 3) * 16;
                     D[q] = us ? DUU : DTT;
                 }
-                dist_blocks<2>(sa, na, sa, na, r0, c0, dp, ld, D, dld, up);
+                dist_blocks<2>(sa, na, sa, na, r0, c0, dp, ld, D, dld);
             }
         }
         __syncthreads();
         // 3. Stage V: each wave walks rows w, w+8, ...; every Stage IV survivor
         // (i, j) is tested against the points of T and U, one lane per witness
-        // z: max(rd d^2(x,z), rd d^2(y,z)) < rd d^2(x,y).
+        // z, with the float32 certificate above.
         for (int i = w; i < lT; i += kPairWaves) {
             uint64_t row = surv[i];
             double rmax = -1.0;
             while (row) {
                 const int j = __ffsll((long long)row) - 1;
                 row &= row - 1;
-                const float t = DTU[i * kDl + j];
+                const float t = DTU[i * kDl + j] * kCertain;
                 bool wz = false;
                 if (self && lane < lT) wz = fmaxf(DTT[i * kDl + lane], DTU[lane * kDl + j]) < t;
                 if (lane < lU) wz = wz || fmaxf(DTU[i * kDl + lane], DUU[j * kDl + lane]) < t;
@@ -442,6 +445,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         atomicAdd(&counters[C_S4], (unsigned long long)ns4);
         atomicAdd(&counters[C_WTEST], (unsigned long long)tests);
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
+        if (ntpv) atomicAdd(&counters[C_TPV], (unsigned long long)ntpv);
     }
 }
 

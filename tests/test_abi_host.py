@@ -45,13 +45,14 @@ def test_library_exports_every_declared_symbol(L):
 def test_struct_layouts_match_header(L, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "grng.h"\nint main(void){'
-                   'printf("%zu %zu %zu %zu\\n", sizeof(grng_options), sizeof(grng_stats),'
-                   ' offsetof(grng_options, reserved), offsetof(grng_stats, lune_bytes)); return 0;}\n')
+                   'printf("%zu %zu %zu %zu %zu\\n", sizeof(grng_options), sizeof(grng_stats),'
+                   ' offsetof(grng_options, reserved), offsetof(grng_stats, lune_bytes),'
+                   ' offsetof(grng_stats, stage4_ops)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
-    a, b, c, d = map(int, subprocess.check_output([str(exe)]).split())
+    a, b, c, d, e = map(int, subprocess.check_output([str(exe)]).split())
     assert a == C.sizeof(L.Options) and b == C.sizeof(L.Stats)
-    assert c == L.Options.reserved.offset and d == L.Stats.lune_bytes.offset
+    assert c == L.Options.reserved.offset and d == L.Stats.lune_bytes.offset and e == L.Stats.stage4_ops.offset
 
 
 def test_host_validation_without_device(L):
