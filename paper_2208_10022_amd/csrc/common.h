@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "grng.h"
@@ -35,24 +36,68 @@ inline void require(bool ok, grng_status s, const std::string &msg) {
 
 // ---------------------------------------------------------------------------
 // Owning device buffer.
+// Per-index cache of device blocks.  Every kernel and copy of an index runs
+// on the index's one stream, so a block handed back while work that uses it
+// is still queued can be handed out again at once: the next user's work is
+// queued behind it.  This keeps hipMalloc / hipFree (which waits for the
+// device) out of the middle of a build.  Blocks come in size classes (powers
+// of two up to 2 MiB, then eighths of a power of two).
+class BlockPool {
+public:
+    BlockPool() = default;
+    BlockPool(const BlockPool &) = delete;
+    BlockPool &operator=(const BlockPool &) = delete;
+    ~BlockPool();
+    void *get(size_t bytes, size_t *cls);   // throws ENOMEM
+    void put(void *p, size_t cls);
+    void trim(size_t keep);                  // free cached blocks, largest first, down to keep bytes
+    size_t cached() const { return cached_; }
+private:
+    std::multimap<size_t, void *> free_;
+    size_t cached_ = 0;
+};
+
+// Pool of the index the current C-ABI call works on (null: plain hipMalloc).
+extern thread_local BlockPool *g_pool;
+
+// Owning device buffer.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    BlockPool *pool = nullptr;            // where the block goes back to (null: hipFree)
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), pool(o.pool) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.pool = nullptr;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            pool = o.pool;
+            o.p = nullptr;
+            o.bytes = 0;
+            o.pool = nullptr;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool)
+                pool->put(p, bytes);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        pool = nullptr;
     }
-    void alloc(size_t nbytes);            // throws ENOMEM; contents undefined
+    void alloc(size_t nbytes);            // throws ENOMEM; contents undefined; bytes >= nbytes
     void ensure(size_t nbytes);           // grow (discarding contents) if smaller
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
@@ -195,6 +240,7 @@ struct ExhaustiveState {
 }  // namespace grng
 
 struct grng_index {
+    grng::BlockPool pool;      // first member: destroyed after every buffer below
     hipStream_t stream = nullptr;
     grng_options opt{};
     int32_t d = 0, dp = 0, q = 0;

@@ -977,6 +977,21 @@ void do_set_scorer(grng_index *idx, const float *theta) {
     idx->scorer = std::move(wb);
 }
 
+// Device blocks an index keeps cached between calls.
+constexpr size_t kPoolKeep = size_t(8) << 30;
+
+// Makes the index's block pool the current one for the duration of a call
+// and trims its cache when the call ends.
+struct PoolScope {
+    grng_index *idx;
+    BlockPool *saved;
+    explicit PoolScope(grng_index *i) : idx(i), saved(g_pool) { g_pool = i ? &i->pool : nullptr; }
+    ~PoolScope() {
+        if (idx) idx->pool.trim(kPoolKeep);
+        g_pool = saved;
+    }
+};
+
 template <class F>
 grng_status guarded(F &&f) {
     try {
@@ -999,6 +1014,64 @@ grng_status guarded(F &&f) {
 
 }  // namespace
 
+thread_local BlockPool *g_pool = nullptr;
+
+namespace {
+
+size_t size_class(size_t n) {
+    size_t c = n < 256 ? 256 : n;
+    size_t pw = 256;
+    while (pw < c) pw <<= 1;
+    if (pw <= (size_t(2) << 20)) return pw;
+    const size_t g = pw >> 3;   // eighths of the power of two: at most 12.5% slack
+    return (c + g - 1) / g * g;
+}
+
+void *device_malloc(size_t bytes) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+}  // namespace
+
+BlockPool::~BlockPool() { trim(0); }
+
+void *BlockPool::get(size_t bytes, size_t *cls) {
+    *cls = size_class(bytes);
+    auto it = free_.find(*cls);
+    if (it != free_.end()) {
+        void *p = it->second;
+        free_.erase(it);
+        cached_ -= *cls;
+        return p;
+    }
+    void *p = device_malloc(*cls);
+    if (!p && cached_) {   // give the cache back and try once more
+        trim(0);
+        p = device_malloc(*cls);
+    }
+    if (!p) throw Error(GRNG_ENOMEM, "device allocation of " + std::to_string(*cls) + " bytes failed");
+    return p;
+}
+
+void BlockPool::put(void *p, size_t cls) {
+    free_.emplace(cls, p);
+    cached_ += cls;
+}
+
+void BlockPool::trim(size_t keep) {
+    while (cached_ > keep && !free_.empty()) {
+        auto it = std::prev(free_.end());
+        (void)hipFree(it->second);
+        cached_ -= it->first;
+        free_.erase(it);
+    }
+}
+
 void DevBuf::alloc(size_t nbytes) {
     release();
     nbytes = (nbytes + 7) & ~size_t(7);
@@ -1006,12 +1079,15 @@ void DevBuf::alloc(size_t nbytes) {
     ++g_alloc_calls;
     if (fail_at() >= 0 && g_alloc_calls == fail_at())
         throw Error(GRNG_ENOMEM, "device allocation failed (injected by GRNG_FAIL_ALLOC_AT)");
-    hipError_t e = hipMalloc(&p, nbytes);
-    if (e != hipSuccess) {
-        p = nullptr;
-        (void)hipGetLastError();
-        throw Error(GRNG_ENOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+    if (g_pool) {
+        size_t cls = 0;
+        p = g_pool->get(nbytes, &cls);
+        bytes = cls;
+        pool = g_pool;
+        return;
     }
+    p = device_malloc(nbytes);
+    if (!p) throw Error(GRNG_ENOMEM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
     bytes = nbytes;
 }
 
@@ -1036,20 +1112,32 @@ grng_status grng_create(grng_index **out, const float *points_dev, int64_t n, in
 
 grng_status grng_build_grng_layer(grng_index *idx, int32_t layer, const int32_t *pivot_ids_dev,
                                   const float *radii_dev, int64_t m) {
-    return guarded([&] { do_build_layer(idx, layer, pivot_ids_dev, radii_dev, m); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_build_layer(idx, layer, pivot_ids_dev, radii_dev, m);
+    });
 }
 
 grng_status grng_build_rng(grng_index *idx) {
-    return guarded([&] { do_build_rng(idx); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_build_rng(idx);
+    });
 }
 
 grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t nb) {
-    return guarded([&] { do_insert(idx, points_dev, nb); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_insert(idx, points_dev, nb);
+    });
 }
 
 grng_status grng_query_neighbors(grng_index *idx, const float *q_dev, int64_t nq, int64_t *offsets_dev,
                                  int32_t *nbrs_dev, int64_t capacity, int64_t *needed) {
-    return guarded([&] { do_query(idx, q_dev, nq, offsets_dev, nbrs_dev, capacity, needed); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_query(idx, q_dev, nq, offsets_dev, nbrs_dev, capacity, needed);
+    });
 }
 
 int32_t grng_mlp_params(void) { return kMlpParams; }
@@ -1071,11 +1159,17 @@ grng_status grng_mlp_score(const float *theta_dev, const float *feats_dev, int64
 
 grng_status grng_log_witness_cells(grng_index *idx, int64_t max_pairs, float *feats_dev, uint8_t *labels_dev,
                                    int64_t capacity, int64_t *count) {
-    return guarded([&] { do_log_cells(idx, max_pairs, feats_dev, labels_dev, capacity, count); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_log_cells(idx, max_pairs, feats_dev, labels_dev, capacity, count);
+    });
 }
 
 grng_status grng_set_scorer(grng_index *idx, const float *theta_dev) {
-    return guarded([&] { do_set_scorer(idx, theta_dev); });
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_set_scorer(idx, theta_dev);
+    });
 }
 
 grng_status grng_get_edges(const grng_index *idx, int32_t layer, int32_t *uv_dev, int64_t capacity,

@@ -572,15 +572,16 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
                                                         const double *dxp, const double *dvor, const int32_t *gcount,
                                                         const uint64_t *dmax_bits, const int64_t *rel_off,
                                                         int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
-                                                        int pass) {
+                                                        int32_t cap, int pass) {
     // Pass 0 counts the cells of row point i that may hold a witness of any
     // of its pairs (Proposition 3 with the row's largest pair distance);
-    // pass 1 writes them, nearest pivot first (a bitonic sort in LDS), or in
-    // pivot order when there are more than kRelSortMax of them (the order
-    // only steers the scan, it never changes a verdict).
+    // pass 1 writes them, nearest pivot first (a bitonic sort in LDS of
+    // cap entries, a power of two), or in pivot order when there are more
+    // than cap of them (the order only steers the scan, it never changes a
+    // verdict).
     extern __shared__ unsigned char smem[];
     double *key = (double *)smem;
-    int32_t *kid = (int32_t *)(key + kRelSortMax);
+    int32_t *kid = (int32_t *)(key + cap);
     const int lane = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= n) return;
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
         cnt = rel_off[i + 1] - o;
         if (cnt == 0) return;
     }
-    const bool sorted = cnt <= kRelSortMax;
+    const bool sorted = cnt <= cap;
     const double dmax_hi = sqrt_hi(dmax2);
     const double *row = dxp + (int64_t)perm[i] * m;
     int64_t pos = 0;
@@ -969,13 +970,15 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x) {
     if (n == 0) return;
     require(n <= 0x7fffffffLL, GRNG_EINVAL, "too many points for the witness-cell pass");
-    const size_t lds = (size_t)kRelSortMax * (sizeof(double) + sizeof(int32_t));
+    int32_t cap = 64;   // sort capacity: the layer size rounded up to a power of two, at most kRelSortMax
+    while (cap < m && cap < kRelSortMax) cap <<= 1;
+    const size_t lds = (size_t)cap * (sizeof(double) + sizeof(int32_t));
     if (rel_off == nullptr) {
-        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
-                                                       nullptr, nullptr, 0);
+        k_relevant_groups<<<(unsigned)n, 64, 0, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
+                                                     nullptr, nullptr, cap, 0);
     } else {
         k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt,
-                                                       rel_grp, rel_d2x, 1);
+                                                       rel_grp, rel_d2x, cap, 1);
     }
     GRNG_LAUNCHED();
 }
