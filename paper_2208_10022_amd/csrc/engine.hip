@@ -448,25 +448,33 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     P.nw = div_up(n, 64);
     P.g_cols.alloc(8 * (size_t)(m * P.nw));
     launch_bits_transpose(s, P.g_rows.as<uint64_t>(), n, words, m, P.g_cols.as<uint64_t>());
-    // Tiles: chunks of <= 64 home-order points of one home cell.
+    // Tiles: chunks of <= 64 home-order points of one home cell.  When new
+    // points are being inserted they follow the old ones inside each cell
+    // (stable order), and tiles are cut at that boundary too, so a tile is
+    // either all old or all new and only tile pairs with a new tile are
+    // scanned.
     std::vector<int32_t> tiles;
     std::vector<uint8_t> tnew, newh;
-    if (is_new) newh.resize((size_t)n);
-    for (int64_t c = 0; c < m; ++c)
-        for (int32_t st = P.h_off[c]; st < P.h_off[c + 1]; st += 64) {
-            const int32_t len = std::min<int32_t>(64, P.h_off[c + 1] - st);
+    if (is_new) {
+        newh.resize((size_t)n);
+        for (int64_t r = 0; r < n; ++r) newh[r] = (*is_new)[P.h_perm[r]];
+    }
+    auto add_tiles = [&](int32_t b, int32_t e, int64_t c, uint8_t fresh) {
+        for (int32_t st = b; st < e; st += 64) {
             tiles.push_back(st);
-            tiles.push_back(len);
+            tiles.push_back(std::min<int32_t>(64, e - st));
             tiles.push_back((int32_t)c);
-            if (is_new) {
-                uint8_t any = 0;
-                for (int32_t r = st; r < st + len; ++r) {
-                    newh[r] = (*is_new)[P.h_perm[r]];
-                    any |= newh[r];
-                }
-                tnew.push_back(any);
-            }
+            if (is_new) tnew.push_back(fresh);
         }
+    };
+    for (int64_t c = 0; c < m; ++c) {
+        int32_t split = P.h_off[c + 1];
+        if (is_new)
+            for (int32_t r = P.h_off[c]; r < P.h_off[c + 1]; ++r)
+                if (newh[r]) { split = r; break; }
+        add_tiles(P.h_off[c], split, c, 0);
+        add_tiles(split, P.h_off[c + 1], c, 1);
+    }
     P.ntiles = (int64_t)tiles.size() / 3;
     h2d(P.tiles, tiles, s);
     P.tv.alloc(8 * (size_t)std::max<int64_t>(P.ntiles * words, 1));

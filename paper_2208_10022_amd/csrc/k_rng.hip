@@ -405,15 +405,18 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         // z, with the float32 certificate above.
         for (int i = w; i < lT; i += kPairWaves) {
             uint64_t row = surv[i];
+            if (!row) continue;
+            // the x side of every test of this row, once per row
+            const float ax = (self && lane < lT) ? DTT[i * kDl + lane] : INFINITY;
+            const float au = lane < lU ? DTU[i * kDl + lane] : INFINITY;
             double rmax = -1.0;
             while (row) {
                 const int j = __ffsll((long long)row) - 1;
                 row &= row - 1;
                 const float t = DTU[i * kDl + j] * kCertain;
-                bool wz = false;
-                if (self && lane < lT) wz = fmaxf(DTT[i * kDl + lane], DTU[lane * kDl + j]) < t;
-                if (lane < lU) wz = wz || fmaxf(DTU[i * kDl + lane], DUU[j * kDl + lane]) < t;
-                if (__ballot(wz)) continue;
+                const float by = (self && lane < lT) ? DTU[lane * kDl + j] : INFINITY;
+                const float bu = lane < lU ? DUU[j * kDl + lane] : INFINITY;
+                if (__ballot(fmaxf(ax, by) < t || fmaxf(au, bu) < t)) continue;
                 // survivor: exact d^2 by the lane that will hold it
                 double dd = 0.0;
                 if (lane == wo.cnt) {
