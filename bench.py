@@ -110,6 +110,10 @@ def parse():
     ap.add_argument("--precision", type=int, default=1, help="0 = float64 everywhere, 1 = float32 screens + "
                     "float64 re-decision (the plain float32 form)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, help="1: the index autotunes its witness-pivot counts on "
+                    "the first (warmup) build")
+    ap.add_argument("--vgrng-pivots", type=int, default=0, help="Proposition 1 witness pivots per block (autotune 0)")
+    ap.add_argument("--stage4-pivots", type=int, default=0, help="Stage IV pivot witnesses (autotune 0)")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
@@ -174,7 +178,11 @@ def main():
         idx.build_grng_layer(0, pid, rad)
         idx.build_rng()
 
-    idx = P.Index(X, grid_exp=W.q, precision=args.precision)
+    idx = P.Index(X, grid_exp=W.q, precision=args.precision, autotune=args.autotune,
+                  vgrng_pivots=args.vgrng_pivots, stage4_pivots=args.stage4_pivots)
+    if args.autotune and args.warmup < 1:
+        print("--autotune needs at least one warmup step (the tuning runs there)", file=sys.stderr)
+        sys.exit(2)
     for _ in range(args.warmup):
         step(idx)
     torch.cuda.synchronize()
@@ -226,6 +234,9 @@ def main():
         "lune_tests": st["lune_tests"],
         "rechecks": st["rechecks"],
         "tile_pairs": st["tile_pairs"],
+        "vgrng_pivots": st["vgrng_pivots"],
+        "stage4_pivots": st["stage4_pivots"],
+        "ms_autotune_once": st["ms_autotune"],
         "orphans": st["orphans"],
         "ms_layer": st["ms_layers"],
         "ms_rng": st["ms_rng"],

@@ -79,10 +79,18 @@ typedef struct grng_options {
     int32_t grid_exp;      /* q: every coordinate and radius is an integer multiple of 2^-q; 0..60 */
     int32_t precision;     /* GRNG_PREC_* */
     int32_t witness_order; /* GRNG_ORDER_* */
-    int32_t use_graph;     /* 1: insert_batch replays captured HIP graphs per size bucket */
-    int32_t autotune;      /* 1: pick tile shapes by timing candidates on first use */
+    int32_t use_graph;     /* 0 or 1; no effect in this version (every call sizes its buffers on the host
+                              between launches, and launch overhead is below 1% of a call) */
+    int32_t autotune;      /* 1: the first grng_build_rng with a pivot layer times complete builds over a
+                              small set of witness-pivot counts (vgrng_pivots, then stage4_pivots) and
+                              keeps the fastest for later builds, insertions and queries of this index;
+                              0: use the two fields below */
     int32_t stage4_pivots; /* pivot witnesses tested per pair before the exhaustive scan: 0 = default (16), 1..16 */
-    int32_t reserved_i[2]; /* must be 0 */
+    int32_t vgrng_pivots;  /* Proposition 1 witnesses per 64-point block: the pivots nearest the block's home
+                              cell, 0 = default (128), values >= the layer size use every pivot.  Any subset
+                              of pivots is a valid witness set (fewer only prunes less), so edges never
+                              depend on it. */
+    int32_t reserved_i[1]; /* must be 0 */
     uint64_t reserved[4];  /* must be 0 */
 } grng_options;
 
@@ -92,7 +100,9 @@ typedef struct grng_stats {
     int64_t n_layers;             /* pivot layers built */
     int64_t orphans;              /* points in no pivot domain of the finest layer */
     int64_t tile_pairs;           /* 64-point tile pairs scanned for candidate pairs */
-    int64_t reserved_i[3];
+    int64_t vgrng_pivots;         /* Proposition 1 witness pivots per block used by the last build */
+    int64_t stage4_pivots;        /* Stage IV pivot witnesses used by the last build */
+    int64_t reserved_i[1];
     double distance_computations; /* squared distances produced (the paper's cost unit, Section 1) */
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
@@ -107,7 +117,8 @@ typedef struct grng_stats {
     double ms_vgrng;              /* device time of the virtual-pivot (min,max) kernel in the last build */
     double ms_pairs;              /* device time of the tiled candidate-pair kernel in the last build */
     double ms_lune;               /* device time of the exhaustive lune kernel in the last build */
-    double vgrng_ops;             /* (min,max) pairs evaluated by the virtual-pivot kernel: 2 n m^2 */
+    double vgrng_ops;             /* (min,max) pairs evaluated by the virtual-pivot kernel: 2 n m kw, kw the
+                                     Proposition 1 witness pivots per block (vgrng_pivots) */
     double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair,
                                      plus 2 dp * 2*64*64 per tile pair that reaches Stage V */
     double lune_bytes;            /* algorithmic bytes read by the lune kernel per witness test: the
@@ -115,7 +126,8 @@ typedef struct grng_stats {
                                      8 dp + 16 in float64 */
     double stage4_ops;            /* (min,max) operations of Stage IV in the pair kernel: 2*64*64*K'
                                      per tile pair, K' = pivot witnesses rounded up to a multiple of 4 */
-    double reserved[3];
+    double ms_autotune;           /* device time of the autotuner's trial builds (0 when it has not run) */
+    double reserved[2];
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -37,19 +37,21 @@ class GrngError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("grid_exp", C.c_int32), ("precision", C.c_int32), ("witness_order", C.c_int32),
                 ("use_graph", C.c_int32), ("autotune", C.c_int32), ("stage4_pivots", C.c_int32),
-                ("reserved_i", C.c_int32 * 2), ("reserved", C.c_uint64 * 4)]
+                ("vgrng_pivots", C.c_int32), ("reserved_i", C.c_int32 * 1), ("reserved", C.c_uint64 * 4)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_edges", C.c_int64), ("n_layers", C.c_int64), ("orphans", C.c_int64),
-                ("tile_pairs", C.c_int64), ("reserved_i", C.c_int64 * 3),
+                ("tile_pairs", C.c_int64), ("vgrng_pivots", C.c_int64), ("stage4_pivots", C.c_int64),
+                ("reserved_i", C.c_int64 * 1),
                 ("distance_computations", C.c_double), ("witness_tests", C.c_double),
                 ("candidate_pairs", C.c_double), ("stage4_survivors", C.c_double),
                 ("exhaustive_pairs", C.c_double), ("lune_tests", C.c_double), ("rechecks", C.c_double),
                 ("ms_layers", C.c_double), ("ms_rng", C.c_double), ("ms_insert", C.c_double),
                 ("ms_query", C.c_double), ("ms_vgrng", C.c_double), ("ms_pairs", C.c_double),
                 ("ms_lune", C.c_double), ("vgrng_ops", C.c_double), ("pairs_flops", C.c_double),
-                ("lune_bytes", C.c_double), ("stage4_ops", C.c_double), ("reserved", C.c_double * 3)]
+                ("lune_bytes", C.c_double), ("stage4_ops", C.c_double), ("ms_autotune", C.c_double),
+                ("reserved", C.c_double * 2)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
@@ -169,11 +171,12 @@ class Index:
     """An exact RNG / GRNG index over device-resident points (see include/grng.h)."""
 
     def __init__(self, points, grid_exp: int, precision: int = PREC_FP64, witness_order: int = ORDER_DISTANCE,
-                 use_graph: int = 0, autotune: int = 0, stage4_pivots: int = 0, stream=None):
+                 use_graph: int = 0, autotune: int = 0, stage4_pivots: int = 0, vgrng_pivots: int = 0,
+                 stream=None):
         self._h = C.c_void_p()
         self._stream = stream
         opt = Options(grid_exp=grid_exp, precision=precision, witness_order=witness_order, use_graph=use_graph,
-                      autotune=autotune, stage4_pivots=stage4_pivots)
+                      autotune=autotune, stage4_pivots=stage4_pivots, vgrng_pivots=vgrng_pivots)
         n, d = points.shape
         check(lib().grng_create(C.byref(self._h), _dev_ptr(points, "float32", 2), n, d,
                                 _stream_handle(stream), C.byref(opt)))

@@ -158,6 +158,8 @@ struct PointState {
 struct LayerAux {
     DevBuf Xp, nrmp;               // pivot coordinates and norms
     DevBuf pknn;                   // int32 [m][16] nearest pivots of each pivot
+    DevBuf wknn;                   // int32 [m][kw] nearest pivots of each pivot (Proposition 1 witnesses)
+    int32_t kw = 0;
     DevBuf bd, bv;                 // float [m][m] shifted pivot distances (virtual-pivot test)
 };
 
@@ -257,6 +259,9 @@ struct grng_index {
     grng::DevBuf counters;     // uint64 [C_NUM]
     grng::ExhaustiveState ex;  // last guided build's exhaustive pairs (for training samples)
     grng::DevBuf scorer;       // uint16 [kMlpParams] bf16 scorer weights (learned order)
+    int32_t tuned_kw = 0;      // Proposition 1 witness pivots chosen by the autotuner (0: not tuned)
+    int32_t tuned_k4 = 0;      // Stage IV pivot witnesses chosen by the autotuner (0: not tuned)
+    double ms_tune = 0;        // device time the autotuner spent
     grng_stats stats{};
 };
 
@@ -303,8 +308,8 @@ void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, con
                                 float *bd, float *bv);
 void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
                   const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
-                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, uint64_t *g_rows, uint64_t *v_rows,
-                  uint64_t *counters);
+                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, const int32_t *home,
+                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
 
 // k_rng.hip
 struct PairList {
@@ -330,7 +335,7 @@ struct PointsView {
 enum PairMode { PM_SELF = 1, PM_NEW_ONLY = 2 };
 
 constexpr int kPivWitness = 16;   // pivot witnesses per tile pair in the tiled pair kernel
-void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t *pknn);   // pknn [m][16]
+void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t K, int32_t *pknn);   // pknn [m][16]
 void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
                        uint64_t *tv);
 void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const uint64_t *tvA, const uint8_t *newA,

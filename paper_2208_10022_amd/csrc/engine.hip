@@ -29,6 +29,19 @@ int64_t fail_at() {
 }
 
 constexpr int kDefaultK = kPivWitness;
+constexpr int kDefaultVgrngPivots = 256;
+
+// Witness-pivot counts in effect: the autotuner's choice, else the option,
+// else the default.
+int32_t vgrng_pivots(const grng_index *idx, int64_t m) {
+    const int32_t k = idx->tuned_kw > 0 ? idx->tuned_kw
+                                        : (idx->opt.vgrng_pivots > 0 ? idx->opt.vgrng_pivots : kDefaultVgrngPivots);
+    return (int32_t)std::min<int64_t>(m, k);
+}
+
+int32_t stage4_pivots(const grng_index *idx) {
+    return idx->tuned_k4 > 0 ? idx->tuned_k4 : (idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK);
+}
 
 struct EventTimer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -76,7 +89,8 @@ void check_opts(const grng_options *o) {
     require(o->use_graph == 0 || o->use_graph == 1, GRNG_EINVAL, "use_graph must be 0 or 1");
     require(o->autotune == 0 || o->autotune == 1, GRNG_EINVAL, "autotune must be 0 or 1");
     require(o->stage4_pivots >= 0 && o->stage4_pivots <= kPivWitness, GRNG_EINVAL, "stage4_pivots must be in [0, 16]");
-    require(o->reserved_i[0] == 0 && o->reserved_i[1] == 0, GRNG_EINVAL, "reserved option fields must be 0");
+    require(o->vgrng_pivots >= 0, GRNG_EINVAL, "vgrng_pivots must be >= 0");
+    require(o->reserved_i[0] == 0, GRNG_EINVAL, "reserved option fields must be 0");
     for (int t = 0; t < 4; ++t) require(o->reserved[t] == 0, GRNG_EINVAL, "reserved option fields must be 0");
 }
 
@@ -341,7 +355,15 @@ void prepare_aux(grng_index *idx, const Layer &L, LayerAux &aux) {
     launch_gather_rows(s, idx->X.as<double>(), L.pid.as<int32_t>(), m, dp, aux.Xp.as<double>());
     launch_gather_f64(s, idx->nrm.as<double>(), L.pid.as<int32_t>(), m, aux.nrmp.as<double>());
     aux.pknn.alloc(4 * (size_t)(m * kPivWitness));
-    launch_pivot_knn(s, m, L.dpp2.as<double>(), aux.pknn.as<int32_t>());
+    launch_pivot_knn(s, m, L.dpp2.as<double>(), kPivWitness, aux.pknn.as<int32_t>());
+    // Proposition 1 witnesses per point block: the pivots nearest its home cell.
+    aux.kw = vgrng_pivots(idx, m);
+    if (aux.kw < m) {
+        aux.wknn.alloc(4 * (size_t)(m * aux.kw));
+        launch_pivot_knn(s, m, L.dpp2.as<double>(), aux.kw, aux.wknn.as<int32_t>());
+    } else {
+        aux.wknn.release();
+    }
     aux.bd.alloc(4 * (size_t)(m * m));
     aux.bv.alloc(4 * (size_t)(m * m));
 }
@@ -439,7 +461,8 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
         EventTimer vt(s);
         launch_vgrng(s, n, m, P.perm.as<int32_t>(), P.dxp.as<double>(), aux.bd.as<float>(), aux.bv.as<float>(),
                      L.rad.as<double>(), C.dvor.as<double>(), C.gcount.as<int32_t>(), P.par_off.as<int64_t>(),
-                     P.par_idx.as<int32_t>(), L.bits.as<uint64_t>(), words, P.g_rows.as<uint64_t>(),
+                     P.par_idx.as<int32_t>(), L.bits.as<uint64_t>(), words, P.home.as<int32_t>(),
+                     aux.wknn.as<int32_t>(), aux.kw, P.g_rows.as<uint64_t>(),
                      P.v_rows.as<uint64_t>(), ctr);
         const double ms = vt.stop();
         bt.vgrng += ms;
@@ -496,7 +519,7 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
                int mode, Pairs &P, DevBuf &dmax, int64_t &np, BuildTimes &bt) {
     hipStream_t s = idx->stream;
     const int32_t words = L.words;
-    const int32_t K = idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK;
+    const int32_t K = stage4_pivots(idx);
     uint64_t *ctr = idx->counters.as<uint64_t>();
     const bool with_new = (mode & PM_NEW_ONLY) != 0;
     DevBuf tcnt, toff, tpT, tpU;
@@ -638,6 +661,9 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.ms_pairs = bt.pairs;
     idx->stats.ms_lune = bt.lune;
     idx->stats.tile_pairs = bt.tile_pairs;
+    idx->stats.vgrng_pivots = idx->layers.empty() ? 0 : vgrng_pivots(idx, idx->layers.back().m);
+    idx->stats.stage4_pivots = idx->layers.empty() ? 0 : stage4_pivots(idx);
+    idx->stats.ms_autotune = idx->ms_tune;
     idx->stats.distance_computations = (double)c[C_DIST];
     idx->stats.witness_tests = (double)c[C_WTEST];
     idx->stats.candidate_pairs = (double)c[C_CAND];
@@ -651,21 +677,65 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.lune_bytes = (double)c[C_LUNE] * (idx->opt.precision == GRNG_PREC_FP64 ? 8.0 * idx->dp + 16.0
                                                                                      : 4.0 * idx->dp + 4.0);
     const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
-    idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * m;
+    idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * (double)idx->aux.kw;
     // MFMA flops of the pair kernel: D(T,U) and the two pivot blocks for every
     // tile pair, D(T,T) and D(U,U) for those that reach Stage V.
     idx->stats.pairs_flops = 2.0 * idx->dp * ((64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs +
                                               2.0 * 64.0 * 64.0 * (double)c[C_TPV]);
     {
-        const int K = idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK;
+        const int K = stage4_pivots(idx);
         idx->stats.stage4_ops = 2.0 * 64.0 * 64.0 * (double)((K + 3) / 4 * 4) * (double)bt.tile_pairs;
     }
+}
+
+// Autotuner: complete guided builds (results discarded) over candidate
+// witness-pivot counts, coordinate-wise: Proposition 1 witnesses per block
+// first, then Stage IV pivots; the fastest device time wins.  Every
+// candidate gives the same edges, so only speed is compared.
+void autotune(grng_index *idx) {
+    const int64_t m = idx->layers.back().m;
+    auto trial = [&]() {
+        EventTimer t(idx->stream);
+        PointState ps;
+        LayerAux aux;
+        ExhaustiveState ex;
+        DevBuf edges;
+        int64_t ne = 0;
+        BuildTimes bt;
+        build_rng_guided(idx, ps, aux, edges, ne, bt, ex);
+        return t.stop();
+    };
+    std::vector<int32_t> kws;
+    for (int64_t k = 64; k < m && k <= 1024; k *= 2) kws.push_back((int32_t)k);
+    if (m <= 2048) kws.push_back((int32_t)m);
+    double best = INFINITY, spent = 0;
+    int32_t best_kw = vgrng_pivots(idx, m);
+    idx->tuned_k4 = stage4_pivots(idx);
+    for (int32_t kw : kws) {
+        idx->tuned_kw = kw;
+        const double ms = trial();
+        spent += ms;
+        trace("autotune vgrng_pivots", ms, kw);
+        if (ms < best) { best = ms; best_kw = kw; }
+    }
+    idx->tuned_kw = best_kw;
+    int32_t best_k4 = idx->tuned_k4;
+    for (int32_t k4 : {8, 12}) {
+        idx->tuned_k4 = k4;
+        const double ms = trial();
+        spent += ms;
+        trace("autotune stage4_pivots", ms, k4);
+        if (ms < best) { best = ms; best_k4 = k4; }
+    }
+    idx->tuned_k4 = best_k4;
+    idx->ms_tune = spent;
 }
 
 void do_build_rng(grng_index *idx) {
     require(idx != nullptr, GRNG_EINVAL, "index is NULL");
     require(idx->opt.witness_order != GRNG_ORDER_LEARNED || idx->scorer.p != nullptr, GRNG_ESTATE,
             "the learned witness order needs grng_set_scorer first");
+    if (idx->opt.autotune && idx->tuned_kw == 0 && !idx->layers.empty()) autotune(idx);
     hipStream_t s = idx->stream;
     EventTimer timer(s);
     reset_counters(idx);

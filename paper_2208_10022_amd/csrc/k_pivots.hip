@@ -258,10 +258,12 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     const float *__restrict__ bd, const float *__restrict__ bv, const double *__restrict__ rad,
     const double *__restrict__ dvor, const int32_t *__restrict__ gcount, const int64_t *__restrict__ par_off,
     const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ layer_bits, int32_t words,
-    uint64_t *__restrict__ g_rows, uint64_t *__restrict__ v_rows, unsigned long long *counters) {
+    const int32_t *__restrict__ home, const int32_t *__restrict__ wknn, int32_t kw, uint64_t *__restrict__ g_rows,
+    uint64_t *__restrict__ v_rows, unsigned long long *counters) {
     __shared__ float sA[kVT_X][kVT_K + 1];
     __shared__ float sD[kVT_K][kVT_J];
     __shared__ float sV[kVT_K][kVT_J];
+    __shared__ int32_t sK[kVT_K];
     __shared__ uint64_t sCand[kVT_X];
     __shared__ unsigned long long sG[kVT_X], sVb[kVT_X];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -288,21 +290,29 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     float cD[4][4], cV[4][4];
     for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c) cD[r][c] = cV[r][c] = INFINITY;
-    for (int64_t k0 = 0; k0 < m; k0 += kVT_K) {
+    // Witness pivots: the kw pivots nearest to the home cell of the block's
+    // first point (in that order), or all of them when kw == m.  Any subset
+    // of pivots gives a valid witness set: fewer witnesses only prune less.
+    const int32_t *wk = kw < m ? wknn + (int64_t)home[x0] * kw : nullptr;
+    for (int64_t k0 = 0; k0 < kw; k0 += kVT_K) {
+        __syncthreads();
+        if (tid < kVT_K) sK[tid] = k0 + tid < kw ? (wk ? wk[k0 + tid] : (int32_t)(k0 + tid)) : -1;
         __syncthreads();
         for (int e = tid; e < kVT_X * kVT_K; e += 256) {
             const int r = e / kVT_K, kk = e % kVT_K;
-            const int64_t i = x0 + r, k = k0 + kk;
+            const int64_t i = x0 + r;
+            const int32_t k = sK[kk];
             float v = INFINITY;
-            if (i < n && k < m) v = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + k]) * (1.0 + 1e-15));
+            if (i < n && k >= 0) v = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + k]) * (1.0 + 1e-15));
             sA[r][kk] = v;
         }
         for (int e = tid; e < kVT_K * kVT_J; e += 256) {
             const int kk = e / kVT_J, jj = e % kVT_J;
-            const int64_t k = k0 + kk, j = j0 + jj;
-            const bool ok = k < m && j < m;
-            sD[kk][jj] = ok ? bd[k * m + j] : INFINITY;
-            sV[kk][jj] = ok ? bv[k * m + j] : INFINITY;
+            const int32_t k = sK[kk];
+            const int64_t j = j0 + jj;
+            const bool ok = k >= 0 && j < m;
+            sD[kk][jj] = ok ? bd[(int64_t)k * m + j] : INFINITY;
+            sV[kk][jj] = ok ? bv[(int64_t)k * m + j] : INFINITY;
         }
         __syncthreads();
 #pragma unroll 4
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     if (tid == 0) {
         const int64_t rows = (n - x0) < kVT_X ? (n - x0) : kVT_X;
         const int64_t cols = (m - j0) < kVT_J ? (m - j0) : kVT_J;
-        atomicAdd(&counters[C_WTEST], (unsigned long long)(2 * rows * cols * m));
+        atomicAdd(&counters[C_WTEST], (unsigned long long)(2 * rows * cols * kw));
     }
 }
 
@@ -419,13 +429,14 @@ void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, con
 
 void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
                   const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
-                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, uint64_t *g_rows, uint64_t *v_rows,
-                  uint64_t *counters) {
+                  const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, const int32_t *home,
+                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
     if (n == 0) return;
+    require(kw >= 1 && kw <= m, GRNG_EINVAL, "witness pivot count out of range");
     dim3 g((unsigned)div_up(n, kVT_X), (unsigned)div_up(m, kVT_J));
     require(g.y <= 65535u, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
     k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits, words,
-                                    g_rows, v_rows, (unsigned long long *)counters);
+                                    home, wknn, kw, g_rows, v_rows, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 

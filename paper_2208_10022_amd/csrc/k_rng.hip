@@ -518,12 +518,14 @@ __global__ __launch_bounds__(64) void k_tile_pairs(int64_t ntA, const int32_t *t
     if (!off && lane == 0) cnt[T] = c;
 }
 
-__global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2, int32_t *pknn) {
+// The K nearest pivots of each pivot (itself first), ties by index; K > m
+// repeats the pivot itself past the m-th.
+__global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2, int32_t K, int32_t *pknn) {
     const int lane = threadIdx.x;
     const int64_t a = blockIdx.x;
     double last = -1.0;
     int64_t lastk = -1;
-    for (int t = 0; t < kPiv; ++t) {
+    for (int t = 0; t < K; ++t) {
         double best = INFINITY;
         int64_t bk = m;
         for (int64_t k = lane; k < m; k += 64) {
@@ -536,9 +538,9 @@ __global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2,
             const int64_t ok = __shfl_xor(bk, o, kWave);
             if (ob < best || (ob == best && ok < bk)) { best = ob; bk = ok; }
         }
-        if (bk >= m) bk = a;    // fewer than kPiv pivots: repeat the pivot itself
+        if (bk >= m) bk = a;    // fewer than K pivots: repeat the pivot itself
         else { last = best; lastk = bk; }
-        if (lane == 0) pknn[a * kPiv + t] = (int32_t)bk;
+        if (lane == 0) pknn[a * K + t] = (int32_t)bk;
     }
 }
 
@@ -917,9 +919,9 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
 
 }  // namespace
 
-void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t *pknn) {
+void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t K, int32_t *pknn) {
     if (m == 0) return;
-    k_pivot_knn<<<(unsigned)m, 64, 0, s>>>(m, dpp2, pknn);
+    k_pivot_knn<<<(unsigned)m, 64, 0, s>>>(m, dpp2, K, pknn);
     GRNG_LAUNCHED();
 }
 

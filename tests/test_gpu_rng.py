@@ -104,14 +104,39 @@ def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed, p
     assert np.array_equal(Eb, want)
 
 
-def test_stage4_pivot_count_does_not_change_edges(G):
-    say("stage4 pivot count sweep")
+def test_witness_pivot_counts_do_not_change_edges(G):
+    """Stage IV pivot witnesses (1..16) and Proposition 1 witness pivots per
+    block (1 .. all) only change how much is pruned, never the edges."""
+    say("witness pivot count sweep")
     W = synth.clustered(n=2500, d=8, clusters=6, m=80, knn=30, sub=11)
     L = W.layers[0]
     want = native.rng_edges(W.X, W.q)
     for k in (1, 4, 9, 16):
         E, _, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], stage4_pivots=k)
         assert np.array_equal(E, want), k
+    cands = []
+    for kw in (1, 5, 33, 80, 500):
+        E, _, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], vgrng_pivots=kw)
+        assert np.array_equal(E, want), kw
+        cands.append(st["candidate_pairs"])
+    # more witnesses prune at least as much (all pivots at 80 and beyond)
+    assert cands[0] >= cands[2] >= cands[3] == cands[4]
+
+
+def test_autotune_keeps_edges_and_tunes_once(G):
+    say("autotune, clustered n=3000 m=60")
+    W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
+    L = W.layers[0]
+    idx = G.Index(to_dev(W.X), grid_exp=W.q, autotune=1)
+    idx.build_grng_layer(0, to_dev(L.pivot_ids), to_dev(L.radii))
+    idx.build_rng()
+    st = idx.stats()
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), golden_edges("clustered_n3000_d16_rng_edges.txt"))
+    assert st["ms_autotune"] > 0 and st["vgrng_pivots"] in (60,) and st["stage4_pivots"] in (8, 12, 16)
+    idx.build_rng()   # tuned once per index
+    st2 = idx.stats()
+    assert st2["ms_autotune"] == st["ms_autotune"] and st2["vgrng_pivots"] == st["vgrng_pivots"]
+    idx.close()
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
