@@ -115,9 +115,12 @@ def _golden(name):
     return np.array(rows, dtype=np.int64).reshape(-1, 2)
 
 
-def _build(G, W, theta=None, **kw):
+def _build(G, W, theta=None, precision=0, **kw):
+    # precision 0: both orders run the per-pair exhaustive scan, so their
+    # witness-test counts compare like with like
     L = W.layers[0]
-    idx = G.Index(to_dev(W.X), grid_exp=W.q, witness_order=G.ORDER_LEARNED if theta is not None else 0, **kw)
+    idx = G.Index(to_dev(W.X), grid_exp=W.q, witness_order=G.ORDER_LEARNED if theta is not None else 0,
+                  precision=precision, **kw)
     idx.build_grng_layer(0, to_dev(L.pivot_ids), to_dev(L.radii))
     if theta is not None:
         idx.set_scorer(theta)
