@@ -150,7 +150,8 @@ struct PointState {
     DevBuf g_cols;                 // uint64 [m][nw] transposed g_rows
     DevBuf tiles;                  // int32 [ntiles][3]
     DevBuf tv;                     // uint64 [ntiles][words] OR of v_rows over the tile
-    DevBuf is_new, tnew;           // uint8 [n], [ntiles] (insertion only)
+    DevBuf gid;                    // int32 [n] global point ids (a batch being inserted), else empty
+    DevBuf is_new, tnew;           // uint8 [n], [ntiles]: batch points and tiles (dense insertion only)
     DevBuf dxp;                    // double [n][m] exact d^2 to the pivots, input order
 };
 
@@ -330,9 +331,18 @@ struct PointsView {
     const uint64_t *g_cols;  // [m][nw] transposed domain bits of the virtual-pivot test
     int64_t nw;
     const int32_t *tiles;    // [ntiles][3]: start, length (<= 64), home cell
-    const uint8_t *is_new;   // [n] inserted in this batch (insertion only), else null
+    const int32_t *gid;      // [n] global point id (PM_INSERT), else null
+    int32_t new_from;        // ids >= new_from belong to the batch being inserted
+    const uint8_t *is_new;   // [n] 1 for points of the batch being inserted (PM_NEW_ONLY), else null
 };
-enum PairMode { PM_SELF = 1, PM_NEW_ONLY = 2 };
+// PM_SELF: both sides are the indexed set (pairs y > x).
+// PM_NEW_ONLY (with PM_SELF): only pairs with at least one point of the batch
+//   being inserted (dense batches: the batch points keep their cells' tiles).
+// PM_INSERT: the row side is the batch being inserted (sparse batches, tiles
+//   packed across cells) and the other side the whole set with the batch in
+//   it; a pair of two batch points is kept once (larger id on the indexed
+//   side) and a point is not paired with its own copy.
+enum PairMode { PM_SELF = 1, PM_INSERT = 2, PM_NEW_ONLY = 4 };
 
 constexpr int kPivWitness = 16;   // pivot witnesses per tile pair in the tiled pair kernel
 void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t K, int32_t *pknn);   // pknn [m][16]
@@ -367,6 +377,7 @@ void launch_pair_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t 
 void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,
                       const int32_t *qperm, const int32_t *perm, int64_t nq, int32_t *deg, const int64_t *off,
                       int32_t *fill, int32_t *nbr, int pass);
+void launch_pairs_to_ids(hipStream_t s, int64_t np, int32_t *px, int32_t *py, const int32_t *mx, const int32_t *my);
 void launch_sort_segments(hipStream_t s, int64_t nseg, const int64_t *off, int32_t *vals);
 void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py);
 

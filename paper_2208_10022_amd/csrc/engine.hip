@@ -471,32 +471,67 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     P.nw = div_up(n, 64);
     P.g_cols.alloc(8 * (size_t)(m * P.nw));
     launch_bits_transpose(s, P.g_rows.as<uint64_t>(), n, words, m, P.g_cols.as<uint64_t>());
-    // Tiles: chunks of <= 64 home-order points of one home cell.  When new
-    // points are being inserted they follow the old ones inside each cell
-    // (stable order), and tiles are cut at that boundary too, so a tile is
-    // either all old or all new and only tile pairs with a new tile are
-    // scanned.
+    // Tiles.  Indexed points: chunks of <= 64 home-order points of one home
+    // cell (the cell ball of a tile is then its cell's).  Queries and batches
+    // being inserted: cells with few of them share packed tiles of up to 64
+    // consecutive home-order points; the tile's cell (its first point's) only
+    // chooses the Stage IV pivot witnesses there, which any pivots may be.
     std::vector<int32_t> tiles;
     std::vector<uint8_t> tnew, newh;
-    if (is_new) {
-        newh.resize((size_t)n);
-        for (int64_t r = 0; r < n; ++r) newh[r] = (*is_new)[P.h_perm[r]];
-    }
-    auto add_tiles = [&](int32_t b, int32_t e, int64_t c, uint8_t fresh) {
-        for (int32_t st = b; st < e; st += 64) {
-            tiles.push_back(st);
-            tiles.push_back(std::min<int32_t>(64, e - st));
-            tiles.push_back((int32_t)c);
-            if (is_new) tnew.push_back(fresh);
+    if (indexed) {
+        // With a dense batch being inserted (is_new), the batch points follow
+        // the old ones inside each cell (stable order) and tiles are cut at
+        // that boundary too: a tile is all old or all new.
+        if (is_new) {
+            newh.resize((size_t)n);
+            for (int64_t r = 0; r < n; ++r) newh[r] = (*is_new)[P.h_perm[r]];
         }
-    };
-    for (int64_t c = 0; c < m; ++c) {
-        int32_t split = P.h_off[c + 1];
-        if (is_new)
-            for (int32_t r = P.h_off[c]; r < P.h_off[c + 1]; ++r)
-                if (newh[r]) { split = r; break; }
-        add_tiles(P.h_off[c], split, c, 0);
-        add_tiles(split, P.h_off[c + 1], c, 1);
+        auto add_tiles = [&](int32_t b, int32_t e, int64_t c, uint8_t fresh) {
+            for (int32_t st = b; st < e; st += 64) {
+                tiles.push_back(st);
+                tiles.push_back(std::min<int32_t>(64, e - st));
+                tiles.push_back((int32_t)c);
+                if (is_new) tnew.push_back(fresh);
+            }
+        };
+        for (int64_t c = 0; c < m; ++c) {
+            int32_t split = P.h_off[c + 1];
+            if (is_new)
+                for (int32_t r = P.h_off[c]; r < P.h_off[c + 1]; ++r)
+                    if (newh[r]) { split = r; break; }
+            add_tiles(P.h_off[c], split, c, 0);
+            add_tiles(split, P.h_off[c + 1], c, 1);
+        }
+    } else {
+        // A cell with at least kOwnTile points keeps tiles of its own (their
+        // pivot witnesses and tile-pair filter stay specific); runs of
+        // consecutive smaller cells share packed tiles.
+        constexpr int32_t kOwnTile = 16;
+        int32_t open = -1;   // start of the packed tile being filled
+        auto close_packed = [&](int32_t end) {
+            if (open >= 0 && end > open) {
+                tiles.push_back(open);
+                tiles.push_back(end - open);
+                tiles.push_back(home_h[open]);
+            }
+            open = -1;
+        };
+        for (int64_t c = 0; c < m; ++c) {
+            const int32_t b = P.h_off[c], e = P.h_off[c + 1];
+            if (e == b) continue;
+            if (e - b >= kOwnTile) {
+                close_packed(b);
+                for (int32_t st = b; st < e; st += 64) {
+                    tiles.push_back(st);
+                    tiles.push_back(std::min<int32_t>(64, e - st));
+                    tiles.push_back((int32_t)c);
+                }
+                continue;
+            }
+            if (open >= 0 && e - open > 64) close_packed(b);
+            if (open < 0) open = b;
+        }
+        close_packed((int32_t)n);
     }
     P.ntiles = (int64_t)tiles.size() / 3;
     h2d(P.tiles, tiles, s);
@@ -508,10 +543,13 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     }
 }
 
-PointsView view_of(const PointState &P, bool with_new) {
-    return PointsView{P.Xh.as<double>(),   P.nrmh.as<double>(),  P.par_off.as<int64_t>(),
+// gid: global point ids of the set (PM_INSERT), or null; new_from: first id
+// of the batch being inserted; with_new: pass the batch flags (PM_NEW_ONLY).
+PointsView view_of(const PointState &P, const int32_t *gid, int32_t new_from, bool with_new) {
+    return PointsView{P.Xh.as<double>(),      P.nrmh.as<double>(),     P.par_off.as<int64_t>(),
                       P.par_idx.as<int32_t>(), P.v_rows.as<uint64_t>(), P.g_cols.as<uint64_t>(),
-                      P.nw,                 P.tiles.as<int32_t>(), with_new ? P.is_new.as<uint8_t>() : nullptr};
+                      P.nw,                    P.tiles.as<int32_t>(),   gid,
+                      new_from,                with_new ? P.is_new.as<uint8_t>() : nullptr};
 }
 
 // Stages I-V over candidate tile pairs of A (row side) x B (indexed side).
@@ -521,10 +559,10 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     const int32_t words = L.words;
     const int32_t K = stage4_pivots(idx);
     uint64_t *ctr = idx->counters.as<uint64_t>();
-    const bool with_new = (mode & PM_NEW_ONLY) != 0;
     DevBuf tcnt, toff, tpT, tpU;
     tcnt.alloc(4 * (size_t)std::max<int64_t>(A.ntiles, 1));
     toff.alloc(8 * (size_t)(A.ntiles + 1));
+    const bool with_new = (mode & PM_NEW_ONLY) != 0;
     const uint8_t *na = with_new ? A.tnew.as<uint8_t>() : nullptr, *nb = with_new ? B.tnew.as<uint8_t>() : nullptr;
     launch_tile_pairs(s, A.ntiles, A.tiles.as<int32_t>(), A.tv.as<uint64_t>(), na, B.ntiles, B.tiles.as<int32_t>(),
                       B.tv.as<uint64_t>(), nb, words, mode, nullptr, tcnt.as<int32_t>(), nullptr, nullptr);
@@ -550,7 +588,9 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     }
     std::vector<uint64_t> snapshot;
     d2h(snapshot, idx->counters.p, C_NUM, s);
-    const PointsView va = view_of(A, with_new), vb = view_of(B, with_new);
+    const bool ins = (mode & PM_INSERT) != 0;
+    const PointsView va = view_of(A, ins ? A.gid.as<int32_t>() : nullptr, 0, with_new),
+                     vb = view_of(B, ins ? B.perm.as<int32_t>() : nullptr, ins ? (int32_t)(B.n - A.n) : 0, with_new);
     for (int attempt = 0; attempt < 3; ++attempt) {
         P.reserve(cap);
         zero(P.count, s);
@@ -884,15 +924,39 @@ void do_insert(grng_index *idx, const float *pts, int64_t nb) {
     } else {
         const Layer &L = idx->layers.back();
         LayerAux &aux = idx->aux;
-        std::vector<uint8_t> is_new((size_t)n1, 0);
-        for (int64_t x = n0; x < n1; ++x) is_new[x] = 1;
-        prepare_points(idx, L, aux, X1.as<double>(), nrm1.as<double>(), n1, nullptr, &is_new, ps, bt);
-        // Localization of the new points (Stages I-VI) against S u B: pairs with a new end.
+        // Localization of the new points (Stages I-VI) against S u B.  A dense
+        // batch (at least kDenseBatch points per pivot cell on average) keeps
+        // the batch points in their cells' tiles and scans the tile pairs with
+        // a batch tile; a sparse one is the row side of its own, with tiles
+        // packed across cells.
+        constexpr int64_t kDenseBatch = 8;
+        const bool dense = nb >= kDenseBatch * L.m;
+        std::vector<uint8_t> is_new;
+        if (dense) {
+            is_new.assign((size_t)n1, 0);
+            for (int64_t x = n0; x < n1; ++x) is_new[x] = 1;
+        }
+        prepare_points(idx, L, aux, X1.as<double>(), nrm1.as<double>(), n1, nullptr, dense ? &is_new : nullptr, ps,
+                       bt);
         Pairs Pn;
         DevBuf dmax_n, alive_n;
         int64_t np_n = 0;
-        run_pairs(idx, L, aux, ps, ps, PM_SELF | PM_NEW_ONLY, Pn, dmax_n, np_n, bt);
-        run_exhaustive(idx, L, aux, ps, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
+        if (dense) {
+            run_pairs(idx, L, aux, ps, ps, PM_SELF | PM_NEW_ONLY, Pn, dmax_n, np_n, bt);
+            run_exhaustive(idx, L, aux, ps, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
+            launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), ps.perm.as<int32_t>(),
+                                ps.perm.as<int32_t>());
+        } else {
+            PointState qs;
+            prepare_points(idx, L, aux, Xb.as<double>(), nrmb.as<double>(), nb, &ps, nullptr, qs, bt);
+            std::vector<int32_t> g(qs.h_perm.size());
+            for (size_t r = 0; r < g.size(); ++r) g[r] = (int32_t)(n0 + qs.h_perm[r]);
+            h2d(qs.gid, g, s);
+            run_pairs(idx, L, aux, qs, ps, PM_INSERT, Pn, dmax_n, np_n, bt);
+            run_exhaustive(idx, L, aux, qs, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
+            launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), qs.gid.as<int32_t>(),
+                                ps.perm.as<int32_t>());
+        }
         // Stage VII (Proposition 5): an existing edge survives iff no inserted
         // point lies in its lune; only the inserted points are witnesses (home
         // cells keep old points first, so they are a suffix of each cell).
@@ -930,11 +994,13 @@ void do_insert(grng_index *idx, const float *pts, int64_t nb) {
                 GRNG_HIP(hipMemcpyAsync(static_cast<char *>(dst.p) + el * (size_t)na, b.p, el * (size_t)nb2,
                                         hipMemcpyDeviceToDevice, s));
         };
+        launch_pairs_to_ids(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), ps.perm.as<int32_t>(),
+                            ps.perm.as<int32_t>());
         cat(Pm.x, Po.x, Pn.x, 4, ne0, np_n);
         cat(Pm.y, Po.y, Pn.y, 4, ne0, np_n);
         cat(alive_m, alive_o, alive_n, 1, ne0, np_n);
-        pairs_to_edges(s, n1, ne0 + np_n, Pm.x.as<int32_t>(), Pm.y.as<int32_t>(), alive_m.as<uint8_t>(),
-                       ps.perm.as<int32_t>(), edges, ne);
+        pairs_to_edges(s, n1, ne0 + np_n, Pm.x.as<int32_t>(), Pm.y.as<int32_t>(), alive_m.as<uint8_t>(), nullptr,
+                       edges, ne);
         ps.dxp.release();
         idx->ps = std::move(ps);
         idx->ex = ExhaustiveState();   // training samples come from full builds only

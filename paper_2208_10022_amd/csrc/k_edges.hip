@@ -142,6 +142,14 @@ __global__ void k_edges_to_pairs(int64_t ne, const int32_t *uv, const int32_t *i
     py[e] = inv[uv[2 * e + 1]];
 }
 
+// Pair endpoints from set positions to point ids: px[p] = mx[px[p]], py[p] = my[py[p]].
+__global__ void k_pairs_to_ids(int64_t np, int32_t *px, int32_t *py, const int32_t *mx, const int32_t *my) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    px[p] = mx[px[p]];
+    py[p] = my[py[p]];
+}
+
 inline unsigned grid1(int64_t work) { return (unsigned)(div_up(work, 256) < 1 ? 1 : div_up(work, 256)); }
 
 }  // namespace
@@ -165,6 +173,12 @@ void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const in
 void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py) {
     if (ne == 0) return;
     k_edges_to_pairs<<<grid1(ne), 256, 0, s>>>(ne, uv, inv, px, py);
+    GRNG_LAUNCHED();
+}
+
+void launch_pairs_to_ids(hipStream_t s, int64_t np, int32_t *px, int32_t *py, const int32_t *mx, const int32_t *my) {
+    if (np == 0) return;
+    k_pairs_to_ids<<<grid1(np), 256, 0, s>>>(np, px, py, mx, my);
     GRNG_LAUNCHED();
 }
 

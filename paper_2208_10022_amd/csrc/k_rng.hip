@@ -258,8 +258,20 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (w == 6) {
             // rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
             const int r = lane;
-            uint64_t newU = ~0ull;
+            // Insertion: drop y = the row point's own copy, and a batch point y
+            // paired with a batch row point of larger or equal id (that pair
+            // is produced once, from the other side).
+            uint64_t ins = 0, newU = ~0ull;
             if (mode & PM_NEW_ONLY) newU = __ballot(r < lU && B.is_new[sU + r]);
+            if (mode & PM_INSERT) {
+                const int32_t gy = r < lU ? B.gid[sU + r] : -1;
+                const int32_t gx = r < lT ? A.gid[sT + r] : -1;
+                for (int t = 0; t < 64; ++t) {
+                    const int32_t gxt = __shfl(gx, t, kWave);   // every lane takes part in the shuffle
+                    const uint64_t m = __ballot(gy >= B.new_from && gy <= gxt);
+                    if (r == t) ins = m;
+                }
+            }
             uint64_t mk = 0;
             double nv = 0.0;
             if (r < lT) {
@@ -269,7 +281,8 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                 for (int64_t q = A.par_off[x]; q < A.par_off[x + 1] && mk; ++q)
                     mk &= bits_at(B.g_cols + (int64_t)A.par_idx[q] * B.nw, sU, lU);
                 if (self && T == U) mk &= r == 63 ? 0ull : (~0ull << (r + 1));   // y > x inside one tile
-                if ((mode & PM_NEW_ONLY) && !A.is_new[x]) mk &= newU;           // a new point on one side
+                mk &= ~ins;
+                if ((mode & PM_NEW_ONLY) && !A.is_new[x]) mk &= newU;   // a batch point on one side
                 mk &= lU == 64 ? ~0ull : ((1ull << lU) - 1ull);
             }
             nX[r] = nv;

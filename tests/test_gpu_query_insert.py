@@ -74,11 +74,15 @@ def test_query_capacity_protocol(G):
     idx.close()
 
 
-@pytest.mark.parametrize("layered,prec", [(True, 0), (True, 1), (False, 0)])
-def test_insert_batches_match_rebuild_oracle(G, layered, prec):
-    say("insert", layered, "precision", prec)
+@pytest.mark.parametrize("layered,prec,lo,hi", [(True, 0, 100, 900), (True, 1, 100, 900), (False, 0, 100, 900),
+                                               (True, 1, 10, 150), (True, 0, 10, 150)])
+def test_insert_batches_match_rebuild_oracle(G, layered, prec, lo, hi):
+    """Batches of 400 or more points into 50 pivot cells take the dense path
+    (batch points in their cells' tiles); smaller ones the sparse path (the
+    batch as the row side, tiles packed across cells)."""
+    say("insert", layered, "precision", prec, "sizes", lo, hi)
     W = synth.clustered(n=2000, d=8, clusters=5, m=50, knn=30, sub=4)
-    batches = synth.insert_batches(W, n_batches=3, lo=100, hi=900, sub=1)
+    batches = synth.insert_batches(W, n_batches=3, lo=lo, hi=hi, sub=1)
     idx = make_index(G, W.X, W.q, (W.layers[0].pivot_ids, W.layers[0].radii) if layered else None, prec)
     allX = W.X
     for bi, B in enumerate(batches):
