@@ -712,9 +712,10 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     __shared__ int32_t t_z0[kLuneWaves][64];
     __shared__ int32_t t_pre[kLuneWaves][65];
     __shared__ double t_gmax[kLuneWaves][64];
+    __shared__ double t_gmin[kLuneWaves][64];   // min(d(x,p), d(y,p)) upper bound
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int32_t *z0t = t_z0[wv], *pre = t_pre[wv];
-    double *gmt = t_gmax[wv];
+    double *gmt = t_gmax[wv], *gmn = t_gmin[wv];
     // Dynamic, XCD-aware scheduling: workgroups are dealt round-robin to the
     // 8 XCDs, so a wave on XCD c claims pairs from the c-th contiguous eighth
     // of the list (sorted by row point: its witness cells stay in that XCD's
@@ -757,7 +758,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
         for (int64_t c0 = r0; c0 < r1 && !dead; c0 += 64) {
             const int64_t c = c0 + lane;
             bool scan = false;
-            double gmax = 0.0;
+            double gmax = 0.0, gmin = 0.0;
             int32_t z0 = 0, nmem = 0;
             float key = -INFINITY;
             if (c < r1) {
@@ -771,6 +772,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 if (!zstart && d2x < d2 && d2y < d2) dead = true;
                 const double dxl = sqrt_lo(d2x), dyl = sqrt_lo(d2y);
                 gmax = fmax(dxl, dyl);
+                gmin = fmin(sqrt_hi(d2x), sqrt_hi(d2y));
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
                 scan = !surely_ge(gmax, dvor[g], dxy_hi);
                 if (scan) {
@@ -810,6 +812,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             const int incl = wave_incl_scan(n_at);
             z0t[lane] = __shfl(z0, src, kWave);
             gmt[lane] = __shfl(gmax, src, kWave);
+            gmn[lane] = __shfl(gmin, src, kWave);
             pre[lane] = incl - n_at;
             if (lane == 63) pre[64] = incl;
             const int total = __shfl(incl, 63, kWave);
@@ -825,8 +828,13 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                         const int64_t z = z0t[kc[u]] + (sl - pre[kc[u]]);
                         // The pair's own points are never witnesses (max = d(x,y)).
                         if (z == y || (xself && z == x)) continue;
-                        // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y).
-                        if (!surely_ge(gmt[kc[u]], F32 ? (double)dhomef[z] : dhome[z], dxy_hi)) {
+                        // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y);
+                        // by the same triangle inequality also when d(z,p) -
+                        // min(d(x,p), d(y,p)) >= d(x,y).  The stored d(z,p) is an
+                        // upper bound; 1 - 2^-21 of it is a lower bound.
+                        const double dzh = F32 ? (double)dhomef[z] : dhome[z];
+                        if (!surely_ge(gmt[kc[u]], dzh, dxy_hi) &&
+                            !surely_ge(dzh * (1.0 - 0x1p-21), gmn[kc[u]], dxy_hi)) {
                             bool exact = !F32;
                             if (F32) {
                                 const float *zr = Xhf + z * dp;
