@@ -61,13 +61,15 @@ typedef enum grng_status {
     GRNG_ESTATE = -6     /* call out of order (e.g. layer 1 before layer 0) */
 } grng_status;
 
-/* Distance-tile precision used by the screening passes.  Every kept/eliminated
- * decision is exact in all modes; the modes differ in how much work reaches
- * the exact float64 re-decision. */
+/* Arithmetic of the exhaustive witness scan (Section 2, Stage VI), where most
+ * witness tests are spent.  Every kept/eliminated decision is exact in all
+ * modes; the pivot and in-tile certificates before the scan always compare
+ * float32 roundings of exact float64 tiles and only eliminate on a proven
+ * witness. */
 enum {
-    GRNG_PREC_FP64 = 0, /* exact float64 distance tiles (MFMA f64), no re-decision needed */
-    GRNG_PREC_FP32 = 1, /* float32 tiles + per-tile error bound, float64 re-decision of near ties */
-    GRNG_PREC_BF16 = 2  /* bf16 MFMA tiles (fp32 accumulate) + bound, float64 re-decision */
+    GRNG_PREC_FP64 = 0, /* exact float64 squared distance for every witness test */
+    GRNG_PREC_FP32 = 1, /* float32 rows with an error-bounded screen; undecided tests are recomputed in float64 */
+    GRNG_PREC_BF16 = 2  /* accepted; currently the same screen as GRNG_PREC_FP32 */
 };
 
 enum {
@@ -87,7 +89,7 @@ typedef struct grng_options {
                               0: use the two fields below */
     int32_t stage4_pivots; /* pivot witnesses tested per pair before the exhaustive scan: 0 = default (16), 1..16 */
     int32_t vgrng_pivots;  /* Proposition 1 witnesses per 64-point block: the pivots nearest the block's home
-                              cell, 0 = default (128), values >= the layer size use every pivot.  Any subset
+                              cell, 0 = default (256), values >= the layer size use every pivot.  Any subset
                               of pivots is a valid witness set (fewer only prunes less), so edges never
                               depend on it. */
     int32_t reserved_i[1]; /* must be 0 */
@@ -127,7 +129,9 @@ typedef struct grng_stats {
     double stage4_ops;            /* (min,max) operations of Stage IV in the pair kernel: 2*64*64*K'
                                      per tile pair, K' = pivot witnesses rounded up to a multiple of 4 */
     double ms_autotune;           /* device time of the autotuner's trial builds (0 when it has not run) */
-    double reserved[2];
+    double ms_pair_masks;         /* device time of the candidate-mask pass before the pair kernel (last build);
+                                     ms_pairs is the pair kernel alone */
+    double reserved[1];
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */
@@ -166,7 +170,10 @@ grng_status grng_build_grng_layer(grng_index *idx, int32_t layer, const int32_t 
  * With at least one layer built, candidate pairs and witnesses are pruned by
  * the finest layer (Section 2: Theorem 1, Propositions 1-2 for candidates,
  * Stage IV pivot witnesses, Propositions 3-4 for witness domains); without a
- * layer, every pair is tested against every point.  Errors: ENOMEM, EDEVICE. */
+ * layer, every pair is tested against every point.  The kernels keep rows in
+ * LDS: guided builds, insertions and queries need d <= 104, the brute-force
+ * build d <= 128 (EINVAL above that).  Errors: EINVAL, ESTATE, ENOMEM,
+ * EDEVICE. */
 grng_status grng_build_rng(grng_index *idx);
 
 /* Insert nb points (float32 [nb][d], device) with ids n..n+nb-1 and update

@@ -341,7 +341,7 @@ void trace(const char *stage, double ms, int64_t count) {
 }
 
 struct BuildTimes {
-    double vgrng = 0, pairs = 0, lune = 0;
+    double vgrng = 0, masks = 0, pairs = 0, lune = 0;
     int64_t tile_pairs = 0;
 };
 
@@ -591,17 +591,32 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     const bool ins = (mode & PM_INSERT) != 0;
     const PointsView va = view_of(A, ins ? A.gid.as<int32_t>() : nullptr, 0, with_new),
                      vb = view_of(B, ins ? B.perm.as<int32_t>() : nullptr, ins ? (int32_t)(B.n - A.n) : 0, with_new);
+    // Tile-pair records (bounds and candidate masks), written by the mask
+    // pass and streamed by the pair kernel, in chunks of at most 2^21 tile
+    // pairs (2.2 GB).
+    const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 21);
+    DevBuf rec;
+    rec.alloc(8 * (size_t)kPairRecordWords * (size_t)std::max<int64_t>(chunk, 1));
     for (int attempt = 0; attempt < 3; ++attempt) {
         P.reserve(cap);
         zero(P.count, s);
         zero(dmax, s);
-        EventTimer pt(s);
-        launch_pairs_tiled(s, ntp, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, idx->dp, words,
-                           aux.pknn.as<int32_t>(), K, aux.Xp.as<double>(), aux.nrmp.as<double>(), P.view(),
-                           dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
-        const double ms = pt.stop();
+        double ms_m = 0.0, ms = 0.0;
+        for (int64_t c0 = 0; c0 < ntp; c0 += chunk) {
+            const int64_t nc = std::min<int64_t>(chunk, ntp - c0);
+            EventTimer mt(s);
+            launch_pair_masks(s, c0, nc, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, words, rec.as<uint64_t>());
+            ms_m += mt.stop();
+            EventTimer pt(s);
+            launch_pairs_tiled(s, nc, rec.as<uint64_t>(), A.Xh.as<double>(), A.nrmh.as<double>(), B.Xh.as<double>(),
+                               B.nrmh.as<double>(), mode, idx->dp, aux.pknn.as<int32_t>(), K, aux.Xp.as<double>(),
+                               aux.nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
+            ms += pt.stop();
+        }
+        bt.masks += ms_m;
         bt.pairs += ms;
-        trace("tile pairs (Stages I-V)", ms, ntp);
+        trace("tile-pair masks (Stages I-III)", ms_m, ntp);
+        trace("tile pairs (Stages IV-V)", ms, ntp);
         std::vector<uint64_t> h;
         d2h(h, P.count.p, 1, s);
         np = (int64_t)h[0];
@@ -699,6 +714,7 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     read_counters(idx, c);
     idx->stats.ms_vgrng = bt.vgrng;
     idx->stats.ms_pairs = bt.pairs;
+    idx->stats.ms_pair_masks = bt.masks;
     idx->stats.ms_lune = bt.lune;
     idx->stats.tile_pairs = bt.tile_pairs;
     idx->stats.vgrng_pivots = idx->layers.empty() ? 0 : vgrng_pivots(idx, idx->layers.back().m);

@@ -121,6 +121,9 @@ constexpr int kDl = kTile + 1;  // row stride (floats) of the in-tile distance m
 constexpr float kCertain = 1.0f - 0x1p-21f;   // threshold factor of the float32 witness certificate
 constexpr int kXs = kPiv + 4;   // row stride (floats) of the pivot distances: 16-byte aligned rows
 constexpr int kPairChunk = 8;   // tile pairs claimed per atomic
+constexpr int kPairRecMeta = 4;  // record words before the masks: tiles' start, length, home cell
+constexpr int kPairRecWords = kPairRecordWords;
+static_assert(kPairRecWords == kPairRecMeta + 2 * kTile, "record layout");
 constexpr int kLuneChunk = 4;   // pairs claimed per atomic by one wave of the exhaustive scan
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -132,6 +135,26 @@ __device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) 
     uint64_t v = row[w] >> sh;
     if (sh && ((start + len - 1) >> 6) > w) v |= row[w + 1] << (64 - sh);
     return v;
+}
+
+// Proposition 2 for one point x against a 64-point range of the other set:
+// bit k is set iff every parent p of x has bit start + k set in its column
+// g_cols[p] (p in GRNG(y)).  Parents are taken four at a time, so their ids
+// and then their words are all in flight together.
+__device__ inline uint64_t parents_mask(const int64_t *__restrict__ par_off, const int32_t *__restrict__ par_idx,
+                                        const uint64_t *__restrict__ g_cols, int32_t nw, int64_t x, int64_t start,
+                                        int len) {
+    uint64_t mk = ~0ull;
+    const int64_t q1 = par_off[x + 1];
+    for (int64_t q = par_off[x]; q < q1 && mk; q += 4) {
+        int32_t p[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[k] = q + k < q1 ? par_idx[q + k] : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (p[k] >= 0) mk &= bits_at(g_cols + (int64_t)p[k] * nw, start, len);
+    }
+    return mk;
 }
 
 // LDS bytes of k_pairs_tiled for padded dimension dp.  After Stage IV the
@@ -212,11 +235,70 @@ __device__ inline void dist_blocks(const double *const sa[NB], const double *con
         }
 }
 
+// Stages I-III for the tile pairs [tp0, tp0 + n): one wave per tile pair
+// writes its record (kPairRecWords words): the tiles' start, length and home
+// cell, then the candidate masks of the rows of T (bit j: y = U[j] passes
+// Theorem 1 and Propositions 1-2 from x's side) and of the rows of U (bit i:
+// the same from y's side).  A pair (i, j) is a candidate when both bits are
+// set.  Only dependent gathers here; the pair kernel then starts each tile
+// pair from one streamed record.
+__global__ __launch_bounds__(256) void k_pair_masks(int64_t tp0, int64_t n, const int32_t *__restrict__ tpT,
+                                                    const int32_t *__restrict__ tpU, PointsView A, PointsView B,
+                                                    int mode, int32_t words, uint64_t *__restrict__ rec) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;   // the whole wave
+    const bool self = (mode & PM_SELF) != 0;
+    const int32_t T = tpT[tp0 + k], U = tpU[tp0 + k];
+    const int32_t sT = A.tiles[3 * T], lT = A.tiles[3 * T + 1], a = A.tiles[3 * T + 2];
+    const int32_t sU = B.tiles[3 * U], lU = B.tiles[3 * U + 1], b = B.tiles[3 * U + 2];
+    uint64_t *r = rec + k * kPairRecWords;
+    const int i = lane;
+    // rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
+    // Insertion: drop y = the row point's own copy, and a batch point y
+    // paired with a batch row point of larger or equal id (that pair is
+    // produced once, from the other side).
+    uint64_t ins = 0, newU = ~0ull;
+    if (mode & PM_NEW_ONLY) newU = __ballot(i < lU && B.is_new[sU + i]);
+    if (mode & PM_INSERT) {
+        const int32_t gy = i < lU ? B.gid[sU + i] : -1;
+        const int32_t gx = i < lT ? A.gid[sT + i] : -1;
+        for (int t = 0; t < 64; ++t) {
+            const int32_t gxt = __shfl(gx, t, kWave);   // every lane takes part in the shuffle
+            const uint64_t m = __ballot(gy >= B.new_from && gy <= gxt);
+            if (i == t) ins = m;
+        }
+    }
+    uint64_t mx = 0, my = 0;
+    if (i < lT) {
+        const int64_t x = sT + i;
+        mx = parents_mask(A.par_off, A.par_idx, B.g_cols, B.nw, x, sU, lU);
+        mx &= ((A.v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
+        if (self && T == U) mx &= i == 63 ? 0ull : (~0ull << (i + 1));   // y > x inside one tile
+        mx &= ~ins;
+        if ((mode & PM_NEW_ONLY) && !A.is_new[x]) mx &= newU;   // a batch point on one side
+        mx &= lU == 64 ? ~0ull : ((1ull << lU) - 1ull);
+    }
+    if (i < lU) {
+        const int64_t y = sU + i;
+        // The cell test needs the row points inside the cell ball of a:
+        // true for indexed points, not for queries.
+        my = parents_mask(B.par_off, B.par_idx, A.g_cols, A.nw, y, sT, lT);
+        if (self) my &= ((B.v_rows[y * words + (a >> 6)] >> (a & 63)) & 1ull) ? ~0ull : 0ull;
+    }
+    r[kPairRecMeta + i] = mx;
+    r[kPairRecMeta + kTile + i] = my;
+    if (lane < 3) {
+        const int32_t lo = lane == 0 ? sT : lane == 1 ? a : sU, hi = lane == 0 ? lT : lane == 1 ? lU : b;
+        r[lane] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    }
+}
+
 __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_tiled(
-    int64_t ntp, const int32_t *__restrict__ tpT, const int32_t *__restrict__ tpU, PointsView A, PointsView B, int mode,
-    int dp, int32_t words, const int32_t *__restrict__ pknn, int32_t K, const double *__restrict__ Xp,
-    const double *__restrict__ nrmp, PairList out, unsigned long long *dmax_bits, unsigned long long *work,
-    unsigned long long *counters) {
+    int64_t ntp, const uint64_t *__restrict__ rec, const double *__restrict__ XA, const double *__restrict__ nrmA,
+    const double *__restrict__ XB, const double *__restrict__ nrmB, int mode, int dp, const int32_t *__restrict__ pknn,
+    int32_t K, const double *__restrict__ Xp, const double *__restrict__ nrmp, PairList out,
+    unsigned long long *dmax_bits, unsigned long long *work, unsigned long long *counters) {
     // LDS: rows of T and U (ld = dp + 1 doubles per row), norms, candidate
     // masks, the 64 x 64 bit mask of Stage IV survivors, D(T,U); then either
     // the pivot rows and pivot distances (Stages I-IV) or D(T,T) and D(U,U)
@@ -247,62 +329,25 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             s_any = 0;
         }
         __syncthreads();
-        const int64_t tp = s_tp;
+        // wave-uniform from here on: the tile-pair record is read by scalar loads
+        const int64_t tp = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)s_tp >> 32))
+                                      << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)s_tp));
         __syncthreads();
         if (tp < 0) break;
-        const int32_t T = tpT[tp], U = tpU[tp];
-        const int32_t sT = A.tiles[3 * T], lT = A.tiles[3 * T + 1], a = A.tiles[3 * T + 2];
-        const int32_t sU = B.tiles[3 * U], lU = B.tiles[3 * U + 1], b = B.tiles[3 * U + 2];
-        // 1. candidate masks (waves 6, 7: the longest dependent load chains
-        // start first), rows of T (threads 0-255) and U (256-511), pivot rows.
+        const uint64_t *rc = rec + tp * kPairRecWords;
+        const uint64_t m0 = rc[0], m1 = rc[1], m2 = rc[2];
+        const int32_t sT = (int32_t)m0, lT = (int32_t)(m0 >> 32), a = (int32_t)m1;
+        const int32_t lU = (int32_t)(m1 >> 32), sU = (int32_t)m2, b = (int32_t)(m2 >> 32);
+        // 1. candidate masks and norms (waves 6, 7), rows of T (threads
+        // 0-255) and U (256-511), pivot rows (wave 5).
         if (w == 6) {
-            // rows of T.  Pairs need P(x) within GRNG(y) (bits of the y side).
-            const int r = lane;
-            // Insertion: drop y = the row point's own copy, and a batch point y
-            // paired with a batch row point of larger or equal id (that pair
-            // is produced once, from the other side).
-            uint64_t ins = 0, newU = ~0ull;
-            if (mode & PM_NEW_ONLY) newU = __ballot(r < lU && B.is_new[sU + r]);
-            if (mode & PM_INSERT) {
-                const int32_t gy = r < lU ? B.gid[sU + r] : -1;
-                const int32_t gx = r < lT ? A.gid[sT + r] : -1;
-                for (int t = 0; t < 64; ++t) {
-                    const int32_t gxt = __shfl(gx, t, kWave);   // every lane takes part in the shuffle
-                    const uint64_t m = __ballot(gy >= B.new_from && gy <= gxt);
-                    if (r == t) ins = m;
-                }
-            }
-            uint64_t mk = 0;
-            double nv = 0.0;
-            if (r < lT) {
-                const int64_t x = sT + r;
-                nv = A.nrmh[x];
-                mk = ((A.v_rows[x * words + (b >> 6)] >> (b & 63)) & 1ull) ? ~0ull : 0ull;
-                for (int64_t q = A.par_off[x]; q < A.par_off[x + 1] && mk; ++q)
-                    mk &= bits_at(B.g_cols + (int64_t)A.par_idx[q] * B.nw, sU, lU);
-                if (self && T == U) mk &= r == 63 ? 0ull : (~0ull << (r + 1));   // y > x inside one tile
-                mk &= ~ins;
-                if ((mode & PM_NEW_ONLY) && !A.is_new[x]) mk &= newU;   // a batch point on one side
-                mk &= lU == 64 ? ~0ull : ((1ull << lU) - 1ull);
-            }
-            nX[r] = nv;
-            mX[r] = mk;
-            surv[r] = 0;
+            nX[lane] = lane < lT ? nrmA[sT + lane] : 0.0;
+            mX[lane] = rc[kPairRecMeta + lane];
+            surv[lane] = 0;
         } else if (w == 7) {
-            const int r = lane;
-            uint64_t mk = 0;
-            double nv = 0.0;
-            if (r < lU) {
-                const int64_t y = sU + r;
-                nv = B.nrmh[y];
-                // The cell test needs the row points inside the cell ball of a:
-                // true for indexed points, not for queries.
-                mk = (!self || ((B.v_rows[y * words + (a >> 6)] >> (a & 63)) & 1ull)) ? ~0ull : 0ull;
-                for (int64_t q = B.par_off[y]; q < B.par_off[y + 1] && mk; ++q)
-                    mk &= bits_at(A.g_cols + (int64_t)B.par_idx[q] * A.nw, sT, lT);
-            }
-            nY[r] = nv;
-            mY[r] = mk;
+            nY[lane] = lane < lU ? nrmB[sU + lane] : 0.0;
+            mY[lane] = rc[kPairRecMeta + kTile + lane];
         } else if (w == 5) {
             const int ka = (a == b) ? K : (K + 1) / 2;
             const int t = lane >> 2;
@@ -315,9 +360,9 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             if ((lane & 3) == 0) nP[t] = nrmp[pv];
         }
         if (tid < 256)
-            load_rows(sX, A.Xh + (int64_t)sT * dp, lT, kTile, dp, ld, tid, 256);
+            load_rows(sX, XA + (int64_t)sT * dp, lT, kTile, dp, ld, tid, 256);
         else
-            load_rows(sY, B.Xh + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
+            load_rows(sY, XB + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
         __syncthreads();
         // 2a. Per wave: one 16-row block of d^2 to the pivot witnesses (rows
         // of T for waves 0-3, of U for 4-7; +inf past K) and two 16x16 blocks
@@ -962,8 +1007,15 @@ void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const 
     GRNG_LAUNCHED();
 }
 
-void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const int32_t *tpU, const PointsView &A,
-                        const PointsView &B, int mode, int dp, int32_t words, const int32_t *pknn, int32_t K,
+void launch_pair_masks(hipStream_t s, int64_t tp0, int64_t n, const int32_t *tpT, const int32_t *tpU,
+                       const PointsView &A, const PointsView &B, int mode, int32_t words, uint64_t *rec) {
+    if (n == 0) return;
+    k_pair_masks<<<(unsigned)div_up(n, 4), 256, 0, s>>>(tp0, n, tpT, tpU, A, B, mode, words, rec);
+    GRNG_LAUNCHED();
+}
+
+void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const double *XA, const double *nrmA,
+                        const double *XB, const double *nrmB, int mode, int dp, const int32_t *pknn, int32_t K,
                         const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
                         uint64_t *counters) {
     if (ntp == 0) return;
@@ -976,8 +1028,8 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const int32_t *tpT, const in
         GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(ntp, kPairChunk), 256 * 4));
-    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, tpT, tpU, A, B, mode, dp, words, pknn, K, Xp, nrmp, out,
-                                                   (unsigned long long *)dmax_bits, (unsigned long long *)work,
+    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, rec, XA, nrmA, XB, nrmB, mode, dp, pknn, K, Xp, nrmp,
+                                                   out, (unsigned long long *)dmax_bits, (unsigned long long *)work,
                                                    (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }

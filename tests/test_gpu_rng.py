@@ -89,7 +89,10 @@ def test_clustered_3000_d16_matches_golden(G, prec):
 @pytest.mark.parametrize("n,d,m,clusters,seed", [
     (1037, 2, 30, 4, 0), (2111, 3, 70, 6, 1), (1500, 5, 16, 3, 2), (777, 16, 100, 5, 3),
     (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7),
-    (900, 96, 24, 3, 8), (500, 100, 10, 2, 9)])
+    (900, 96, 24, 3, 8), (500, 100, 10, 2, 9),
+    # largest dimension of the tiled path (its LDS rows); two pivots leave
+    # about half of all pairs to Stage V
+    (600, 104, 2, 1, 10)])
 @pytest.mark.parametrize("prec", PRECISIONS)
 def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed, prec):
     say("ragged", n, d, m, clusters, seed, "precision", prec)
