@@ -28,8 +28,8 @@ MI355X_FP64_TFLOPS = 78.6
 MI355X_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "common.h"], "k_lune_guided": ["k_rng.hip", "common.h"],
-                  "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
+KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "common.h"], "k_pair_masks": ["k_rng.hip", "common.h"],
+                  "k_lune_guided": ["k_rng.hip", "common.h"], "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
 
 
 def source_hash(kernel: str) -> str:
@@ -241,6 +241,7 @@ def main():
         "ms_layer": st["ms_layers"],
         "ms_rng": st["ms_rng"],
         "ms_vgrng": st["ms_vgrng"],
+        "ms_pair_masks": st["ms_pair_masks"],
         "ms_pairs": st["ms_pairs"],
         "ms_lune": st["ms_lune"],
         "roofline": roofline(st, workload),

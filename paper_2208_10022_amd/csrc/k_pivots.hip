@@ -253,13 +253,34 @@ __global__ void k_shifted_pivot_dists(int64_t m, const double *dpp, const double
 // rounded up, so C is an upper bound and dropping j stays sound (a dropped
 // pivot is dropped by the exact test too).
 constexpr int kVT_X = 64, kVT_J = 64, kVT_K = 32;
+
+// d(x, p_k) for the witness pivots of x's 64-point block (the kw pivots
+// nearest to the home cell of the block's first point, or all pivots when
+// kw == m), float32 rounded up, [n][kw]: gathered once per build so that the
+// tile kernel streams contiguous rows instead of gathering scattered entries
+// of D_XP for every pivot tile.
+// Rows x0 .. x0 + rows - 1 (x0 a multiple of 64) into ax[0 .. rows * kw).
+__global__ __launch_bounds__(256) void k_witness_dists(int64_t x0, int64_t rows, int64_t m,
+                                                       const int32_t *__restrict__ perm, const double *__restrict__ dxp,
+                                                       const int32_t *__restrict__ home,
+                                                       const int32_t *__restrict__ wknn, int32_t kw,
+                                                       float *__restrict__ ax) {
+    const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+    if (e >= rows * kw) return;
+    const int64_t i = x0 + e / kw;
+    const int32_t k = (int32_t)(e % kw);
+    const int32_t p = kw < m ? wknn[(int64_t)home[i / kVT_X * kVT_X] * kw + k] : k;
+    ax[e] = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + p]) * (1.0 + 1e-15));
+}
+
 __global__ __launch_bounds__(256) void k_vgrng_tiles(
     int64_t n, int64_t m, const int32_t *__restrict__ perm, const double *__restrict__ dxp,
     const float *__restrict__ bd, const float *__restrict__ bv, const double *__restrict__ rad,
     const double *__restrict__ dvor, const int32_t *__restrict__ gcount, const int64_t *__restrict__ par_off,
     const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ layer_bits, int32_t words,
-    const int32_t *__restrict__ home, const int32_t *__restrict__ wknn, int32_t kw, uint64_t *__restrict__ g_rows,
-    uint64_t *__restrict__ v_rows, unsigned long long *counters) {
+    const int32_t *__restrict__ home, const int32_t *__restrict__ wknn, int32_t kw, int64_t xbase,
+    const float *__restrict__ ax, uint64_t *__restrict__ g_rows, uint64_t *__restrict__ v_rows,
+    unsigned long long *counters) {
     __shared__ float sA[kVT_X][kVT_K + 1];
     __shared__ float sD[kVT_K][kVT_J];
     __shared__ float sV[kVT_K][kVT_J];
@@ -267,7 +288,7 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     __shared__ uint64_t sCand[kVT_X];
     __shared__ unsigned long long sG[kVT_X], sVb[kVT_X];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int64_t x0 = blockIdx.x * (int64_t)kVT_X;
+    const int64_t x0 = xbase + blockIdx.x * (int64_t)kVT_X;   // ax holds rows from xbase on
     const int64_t j0 = blockIdx.y * (int64_t)kVT_J;
     const int32_t wj = (int32_t)(j0 >> 6);
     if (tid < kVT_X) {
@@ -301,10 +322,7 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         for (int e = tid; e < kVT_X * kVT_K; e += 256) {
             const int r = e / kVT_K, kk = e % kVT_K;
             const int64_t i = x0 + r;
-            const int32_t k = sK[kk];
-            float v = INFINITY;
-            if (i < n && k >= 0) v = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + k]) * (1.0 + 1e-15));
-            sA[r][kk] = v;
+            sA[r][kk] = (i < n && k0 + kk < kw) ? ax[(i - xbase) * kw + k0 + kk] : INFINITY;
         }
         for (int e = tid; e < kVT_K * kVT_J; e += 256) {
             const int kk = e / kVT_J, jj = e % kVT_J;
@@ -433,11 +451,23 @@ void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, cons
                   const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
     if (n == 0) return;
     require(kw >= 1 && kw <= m, GRNG_EINVAL, "witness pivot count out of range");
-    dim3 g((unsigned)div_up(n, kVT_X), (unsigned)div_up(m, kVT_J));
-    require(g.y <= 65535u, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
-    k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits, words,
-                                    home, wknn, kw, g_rows, v_rows, (unsigned long long *)counters);
-    GRNG_LAUNCHED();
+    require(div_up(m, kVT_J) <= 65535, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
+    // point rows per pass: their witness distances take at most 4 GiB
+    const int64_t chunk = std::min<int64_t>(div_up(n, kVT_X) * kVT_X,
+                                            std::max<int64_t>(kVT_X, (((int64_t)1 << 30) / kw) / kVT_X * kVT_X));
+    DevBuf ax;
+    ax.alloc(4 * (size_t)chunk * (size_t)kw);
+    for (int64_t x0 = 0; x0 < n; x0 += chunk) {
+        const int64_t rows = std::min<int64_t>(chunk, n - x0);
+        k_witness_dists<<<(unsigned)div_up(rows * kw, 256), 256, 0, s>>>(x0, rows, m, perm, dxp, home, wknn, kw,
+                                                                         ax.as<float>());
+        GRNG_LAUNCHED();
+        dim3 g((unsigned)div_up(rows, kVT_X), (unsigned)div_up(m, kVT_J));
+        k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits,
+                                        words, home, wknn, kw, x0, ax.as<float>(), g_rows, v_rows,
+                                        (unsigned long long *)counters);
+        GRNG_LAUNCHED();
+    }
 }
 
 }  // namespace grng
