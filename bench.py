@@ -56,6 +56,9 @@ def measured_traffic(kernel: str, workload: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
+PAIR_RECORD_BYTES = 8 * (4 + 2 * 64)   # tile bounds and the two candidate-mask vectors
+
+
 def kernel_rooflines(st: dict) -> dict:
     """Per main kernel of the last build: time and achieved fraction of its roof.
 
@@ -66,6 +69,7 @@ def kernel_rooflines(st: dict) -> dict:
                    one with the longer time at peak.
     k_lune_guided  witness rows streamed: lune_bytes (row + cell bound per
                    witness test) against HBM bandwidth.
+    k_pair_masks   one 1,056-byte record written per tile pair.
     """
     out = {}
     ms = st["ms_vgrng"]
@@ -87,7 +91,15 @@ def kernel_rooflines(st: dict) -> dict:
     ms = st["ms_lune"]
     ach = st["lune_bytes"] / (ms / 1e3) / 1e9
     out["k_lune_guided"] = {"bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                            "frac": ach / MI355X_HBM_GBS, "ms": ms}
+                            "frac": ach / MI355X_HBM_GBS, "ms": ms,
+                            "note": "witness rows are served from L2/MALL, so the algorithmic bytes can exceed "
+                                    "the HBM roof"}
+    ms = st["ms_pair_masks"]
+    if ms > 0:
+        ach = PAIR_RECORD_BYTES * st["tile_pairs"] / (ms / 1e3) / 1e9
+        out["k_pair_masks"] = {"bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                               "frac": ach / MI355X_HBM_GBS, "ms": ms,
+                               "note": "record bytes written; the reads are dependent gathers (latency-bound)"}
     return out
 
 
