@@ -157,14 +157,24 @@ __device__ inline uint64_t parents_mask(const int64_t *__restrict__ par_off, con
     return mk;
 }
 
-// LDS bytes of k_pairs_tiled for padded dimension dp.  After Stage IV the
-// pivot rows and pivot distances are dead, and D(T,T), D(U,U) reuse them.
-__host__ __device__ inline size_t pairs_lds_bytes(int dp) {
+// LDS of k_pairs_tiled for padded dimension dp.  After Stage IV the pivot
+// rows and pivot distances are dead, and D(U,U) reuses them.  D(T,T) has
+// bytes of its own when they fit, so that it is kept while consecutive tile
+// pairs share T (the list is sorted by T); otherwise it reuses them too.
+__host__ __device__ inline size_t pairs_lds_phase_a(int dp) {
+    return 8 * (size_t)kPiv * (dp + 1) + 4 * 2 * (size_t)kTile * kXs;
+}
+__host__ __device__ inline size_t pairs_lds_fixed(int dp) {
     const size_t ld = (size_t)dp + 1;
-    const size_t fixed = 8 * (2 * kTile * ld + 2 * kTile + kPiv + 3 * kTile) + 4 * (size_t)kTile * kDl;
-    const size_t phase_a = 8 * (size_t)kPiv * ld + 4 * 2 * (size_t)kTile * kXs;
-    const size_t phase_b = 4 * 2 * (size_t)kTile * kDl;
-    return fixed + (phase_a > phase_b ? phase_a : phase_b);
+    return 8 * (2 * kTile * ld + 2 * kTile + kPiv + 3 * kTile) + 4 * (size_t)kTile * kDl;
+}
+__host__ __device__ inline bool pairs_keep_tt(int dp) {
+    const size_t dmat = 4 * (size_t)kTile * kDl, pa = pairs_lds_phase_a(dp);
+    return pairs_lds_fixed(dp) + dmat + (pa > dmat ? pa : dmat) <= 160 * 1024 - 256;
+}
+__host__ __device__ inline size_t pairs_lds_bytes(int dp) {
+    const size_t dmat = 4 * (size_t)kTile * kDl, pa = pairs_lds_phase_a(dp);
+    return pairs_lds_fixed(dp) + (pairs_keep_tt(dp) ? dmat + (pa > dmat ? pa : dmat) : (pa > 2 * dmat ? pa : 2 * dmat));
 }
 
 // Rows [0, rows) of a tile into LDS (row stride ld doubles), zero rows past
@@ -310,9 +320,12 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     uint64_t *mX = (uint64_t *)(nP + kPiv), *mY = mX + kTile, *surv = mY + kTile;
     float *DTU = (float *)(surv + kTile);
     float *region = DTU + kTile * kDl;
-    double *sP = (double *)region;
+    const bool keep_tt = pairs_keep_tt(dp);
+    float *DTT = region, *region2 = keep_tt ? region + kTile * kDl : region;
+    double *sP = (double *)region2;
     float *XP = (float *)(sP + kPiv * ld), *YP = XP + kTile * kXs;
-    float *DTT = region, *DUU = region + kTile * kDl;
+    float *DUU = keep_tt ? region2 : region + kTile * kDl;
+    int32_t tt_start = -1, sx_start = -1;   // tiles whose D(T,T) / rows are in LDS (block-uniform)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool self = (mode & PM_SELF) != 0;
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0;
@@ -359,10 +372,13 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             }
             if ((lane & 3) == 0) nP[t] = nrmp[pv];
         }
-        if (tid < 256)
-            load_rows(sX, XA + (int64_t)sT * dp, lT, kTile, dp, ld, tid, 256);
-        else
+        const bool newT = sT != sx_start;   // T's rows stay in LDS while T repeats
+        sx_start = sT;
+        if (tid < 256) {
+            if (newT) load_rows(sX, XA + (int64_t)sT * dp, lT, kTile, dp, ld, tid, 256);
+        } else {
             load_rows(sY, XB + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
+        }
         __syncthreads();
         // 2a. Per wave: one 16-row block of d^2 to the pivot witnesses (rows
         // of T for waves 0-3, of U for 4-7; +inf past K) and two 16x16 blocks
@@ -436,18 +452,22 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         __syncthreads();
         if (!s_any) continue;   // uniform: no Stage IV survivor in this tile pair
         ntpv += tid == 0;
-        // 2c. D(T,T) (only when T's points may witness) and D(U,U),
-        // written over the pivot data, which is dead now: waves 0-3 take
-        // D(T,T), waves 4-7 D(U,U), four interleaved blocks each.
-        if (self || w >= 4) {
-            const bool us = w >= 4;
+        // 2c. D(U,U), written over the pivot data, which is dead now, and
+        // D(T,T) when T's points may witness and it is not in LDS already:
+        // then waves 0-3 take D(T,T) and waves 4-7 D(U,U), four interleaved
+        // blocks each; else all eight waves take D(U,U), two blocks each.
+        {
+            const bool need_tt = self && sT != tt_start;
+            if (need_tt && keep_tt) tt_start = sT;
+            const bool us = !need_tt || w >= 4;
+            const int nh = need_tt ? 2 : 1;
             const double *sa[2], *na[2];
             int r0[2], c0[2], dld[2] = {kDl, kDl};
             float *D[2];
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < nh; ++h) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const int id = 4 * (w & 3) + 2 * h + q;
+                    const int id = need_tt ? 4 * (w & 3) + 2 * h + q : 2 * w + q;
                     sa[q] = us ? sY : sX;
                     na[q] = us ? nY : nX;
                     r0[q] = (id >> 2) * 16;
