@@ -495,18 +495,18 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                 const float by = (self && lane < lT) ? DTU[lane * kDl + j] : INFINITY;
                 const float bu = lane < lU ? DUU[j * kDl + lane] : INFINITY;
                 if (__ballot(fmaxf(ax, by) < t || fmaxf(au, bu) < t)) continue;
-                // survivor: exact d^2 by the lane that will hold it
-                double dd = 0.0;
+                // survivor: exact d^2, the dot product spread over the lanes
+                // (every partial sum is exact, so the order does not matter)
+                double part = 0.0;
+                for (int c = lane; c < dp; c += 64) part = fma(sX[i * ld + c], sY[j * ld + c], part);
+                for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+                const double dd = nX[i] + nY[j] - 2.0 * part;
                 if (lane == wo.cnt) {
-                    const double *xr = sX + i * ld, *yr = sY + j * ld;
-                    double sxy = 0.0;
-                    for (int c = 0; c < dp; ++c) sxy = fma(xr[c], yr[c], sxy);
-                    dd = nX[i] + nY[j] - 2.0 * sxy;   // exact
                     wo.x = sT + i;
                     wo.y = sU + j;
                     wo.d2 = dd;
                 }
-                rmax = fmax(rmax, __shfl(dd, wo.cnt, kWave));
+                rmax = fmax(rmax, dd);
                 ++nsurv;
                 if (++wo.cnt == 64) wo.flush(out);
             }
