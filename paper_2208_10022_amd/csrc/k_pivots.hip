@@ -253,6 +253,11 @@ __global__ void k_shifted_pivot_dists(int64_t m, const double *dpp, const double
 // rounded up, so C is an upper bound and dropping j stays sound (a dropped
 // pivot is dropped by the exact test too).
 constexpr int kVT_X = 64, kVT_J = 64, kVT_K = 32;
+__device__ inline uint32_t vt_max(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ inline uint32_t vt_min3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t m = a < b ? a : b;
+    return m < c ? m : c;
+}
 
 // d(x, p_k) for the witness pivots of x's 64-point block (the kw pivots
 // nearest to the home cell of the block's first point, or all pivots when
@@ -308,9 +313,12 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         sG[tid] = 0;
         sVb[tid] = 0;
     }
-    float cD[4][4], cV[4][4];
+    // Operands are non-negative float32 values or +inf, whose bit patterns
+    // order as unsigned integers: integer max and three-input min, no NaN
+    // handling.
+    uint32_t cD[4][4], cV[4][4];
     for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) cD[r][c] = cV[r][c] = INFINITY;
+        for (int c = 0; c < 4; ++c) cD[r][c] = cV[r][c] = 0x7f800000u;
     // Witness pivots: the kw pivots nearest to the home cell of the block's
     // first point (in that order), or all of them when kw == m.  Any subset
     // of pivots gives a valid witness set: fewer witnesses only prune less.
@@ -333,18 +341,20 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
             sV[kk][jj] = ok ? bv[(int64_t)k * m + j] : INFINITY;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < kVT_K; ++kk) {
-            float a[4], d[4], v[4];
-            for (int r = 0; r < 4; ++r) a[r] = sA[ty + 16 * r][kk];
-            for (int c = 0; c < 4; ++c) {
-                d[c] = sD[kk][tx + 16 * c];
-                v[c] = sV[kk][tx + 16 * c];
+#pragma unroll 2
+        for (int kk = 0; kk < kVT_K; kk += 2) {
+            uint32_t a[2][4], d[2][4], v[2][4];
+            for (int h = 0; h < 2; ++h) {
+                for (int r = 0; r < 4; ++r) a[h][r] = __float_as_uint(sA[ty + 16 * r][kk + h]);
+                for (int c = 0; c < 4; ++c) {
+                    d[h][c] = __float_as_uint(sD[kk + h][tx + 16 * c]);
+                    v[h][c] = __float_as_uint(sV[kk + h][tx + 16 * c]);
+                }
             }
             for (int r = 0; r < 4; ++r)
                 for (int c = 0; c < 4; ++c) {
-                    cD[r][c] = fminf(cD[r][c], fmaxf(a[r], d[c]));
-                    cV[r][c] = fminf(cV[r][c], fmaxf(a[r], v[c]));
+                    cD[r][c] = vt_min3(cD[r][c], vt_max(a[0][r], d[0][c]), vt_max(a[1][r], d[1][c]));
+                    cV[r][c] = vt_min3(cV[r][c], vt_max(a[0][r], v[0][c]), vt_max(a[1][r], v[1][c]));
                 }
         }
     }
@@ -363,8 +373,8 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
             const double mj = 1e-6 * (dj + 3.0 * fmax(rj, vj)) + 1e-300;
             const bool candD = (sCand[xr] >> jc) & 1ull;
             const bool candV = gcount[j] > 0;
-            const bool keepD = candD && !((double)cD[r][c] + rj < dj - mj);
-            const bool keepV = candV && !((double)cV[r][c] + vj < dj - mj);
+            const bool keepD = candD && !((double)__uint_as_float(cD[r][c]) + rj < dj - mj);
+            const bool keepV = candV && !((double)__uint_as_float(cV[r][c]) + vj < dj - mj);
             if (keepD) atomicOr(&sG[xr], 1ull << jc);
             if (keepV) atomicOr(&sVb[xr], 1ull << jc);
         }

@@ -128,6 +128,13 @@ constexpr int kLuneChunk = 4;   // pairs claimed per atomic by one wave of the e
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+constexpr uint32_t kInfBits = 0x7f800000u;   // +inf as float32 bits
+__device__ inline uint32_t umax2(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ inline uint32_t umin3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t m = a < b ? a : b;
+    return m < c ? m : c;
+}
+
 __device__ inline uint64_t bits_at(const uint64_t *row, int64_t start, int len) {
     // 64 bits of a bit row starting at bit `start` (bits past len are don't-care)
     const int64_t w = start >> 6;
@@ -408,25 +415,27 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         // when C < d^2(x,y) * (1 - 2^-21) in float32, which proves a pivot
         // witness.
         {
+            // All operands are non-negative float32 values or +inf, whose bit
+            // patterns order as unsigned integers: integer min/max (three-input
+            // min) need no NaN handling.
             const int tx = tid & 31, ty = tid >> 5;
-            float c[4][2];
+            uint32_t c[4][2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) c[r][0] = c[r][1] = INFINITY;
+            for (int r = 0; r < 4; ++r) c[r][0] = c[r][1] = kInfBits;
 #pragma unroll
             for (int t0 = 0; t0 < kPiv; t0 += 4) {
                 if (t0 >= K) break;
-                float4 xv[4], yv[2];
+                uint4 xv[4], yv[2];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) xv[r] = *reinterpret_cast<const float4 *>(XP + (ty + 16 * r) * kXs + t0);
+                for (int r = 0; r < 4; ++r) xv[r] = *reinterpret_cast<const uint4 *>(XP + (ty + 16 * r) * kXs + t0);
 #pragma unroll
-                for (int q = 0; q < 2; ++q) yv[q] = *reinterpret_cast<const float4 *>(YP + (tx + 32 * q) * kXs + t0);
+                for (int q = 0; q < 2; ++q) yv[q] = *reinterpret_cast<const uint4 *>(YP + (tx + 32 * q) * kXs + t0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
-                        float m = fminf(fmaxf(xv[r].x, yv[q].x), fmaxf(xv[r].y, yv[q].y));
-                        m = fminf(m, fminf(fmaxf(xv[r].z, yv[q].z), fmaxf(xv[r].w, yv[q].w)));
-                        c[r][q] = fminf(c[r][q], m);
+                        c[r][q] = umin3(c[r][q], umax2(xv[r].x, yv[q].x), umax2(xv[r].y, yv[q].y));
+                        c[r][q] = umin3(c[r][q], umax2(xv[r].z, yv[q].z), umax2(xv[r].w, yv[q].w));
                     }
             }
             const uint64_t my0 = mY[tx], my1 = mY[tx + 32];
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                     const int j = tx + 32 * q;
                     const bool cand = ((mxi >> j) & 1ull) && (((q ? my1 : my0) >> i) & 1ull);
                     ncand += cand;
-                    if (cand && !(c[r][q] < DTU[i * kDl + j] * kCertain)) bits |= 1ull << j;
+                    if (cand && !(c[r][q] < __float_as_uint(DTU[i * kDl + j] * kCertain))) bits |= 1ull << j;
                 }
                 if (bits) {
                     ns4 += __popcll(bits);
