@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                 const float t = DTU[i * kDl + j] * kCertain;
                 const float by = (self && lane < lT) ? DTU[lane * kDl + j] : INFINITY;
                 const float bu = lane < lU ? DUU[j * kDl + lane] : INFINITY;
-                if (__ballot(fmaxf(ax, by) < t || fmaxf(au, bu) < t)) continue;
+                if (__ballot((ax < t && by < t) || (au < t && bu < t))) continue;   // max(., .) < t
                 // survivor: exact d^2, the dot product spread over the lanes
                 // (every partial sum is exact, so the order does not matter)
                 double part = 0.0;
