@@ -56,7 +56,7 @@ def measured_traffic(kernel: str, workload: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-PAIR_RECORD_BYTES = 8 * (4 + 2 * 64)   # tile bounds and the two candidate-mask vectors
+PAIR_RECORD_BYTES = 8 * (12 + 2 * 64)   # tile bounds, pivot ids and the two candidate-mask vectors
 
 
 def kernel_rooflines(st: dict) -> dict:
@@ -69,7 +69,7 @@ def kernel_rooflines(st: dict) -> dict:
                    one with the longer time at peak.
     k_lune_guided  witness rows streamed: lune_bytes (row + cell bound per
                    witness test) against HBM bandwidth.
-    k_pair_masks   one 1,056-byte record written per tile pair.
+    k_pair_masks   one 1,120-byte record written per tile pair.
     """
     out = {}
     ms = st["ms_vgrng"]

@@ -352,11 +352,12 @@ void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const 
                        int64_t ntB, const int32_t *tilesB, const uint64_t *tvB, const uint8_t *newB, int32_t words,
                        int mode, const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU);
 // Tile-pair records for the pair kernel: words per record.
-constexpr int kPairRecordWords = 4 + 2 * 64;
+constexpr int kPairRecordWords = 12 + 2 * 64;
 void launch_pair_masks(hipStream_t s, int64_t tp0, int64_t n, const int32_t *tpT, const int32_t *tpU,
-                       const PointsView &A, const PointsView &B, int mode, int32_t words, uint64_t *rec);
+                       const PointsView &A, const PointsView &B, int mode, int32_t words, const int32_t *pknn,
+                       int32_t K, uint64_t *rec);
 void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const double *XA, const double *nrmA,
-                        const double *XB, const double *nrmB, int mode, int dp, const int32_t *pknn, int32_t K,
+                        const double *XB, const double *nrmB, int mode, int dp, int32_t K,
                         const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
                         uint64_t *counters);
 void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,

@@ -591,9 +591,9 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     const bool ins = (mode & PM_INSERT) != 0;
     const PointsView va = view_of(A, ins ? A.gid.as<int32_t>() : nullptr, 0, with_new),
                      vb = view_of(B, ins ? B.perm.as<int32_t>() : nullptr, ins ? (int32_t)(B.n - A.n) : 0, with_new);
-    // Tile-pair records (bounds and candidate masks), written by the mask
-    // pass and streamed by the pair kernel, in chunks of at most 2^21 tile
-    // pairs (2.2 GB).
+    // Tile-pair records (bounds, pivot ids and candidate masks), written by
+    // the mask pass and streamed by the pair kernel, in chunks of at most
+    // 2^21 tile pairs (2.3 GB).
     const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 21);
     DevBuf rec;
     rec.alloc(8 * (size_t)kPairRecordWords * (size_t)std::max<int64_t>(chunk, 1));
@@ -605,11 +605,12 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
         for (int64_t c0 = 0; c0 < ntp; c0 += chunk) {
             const int64_t nc = std::min<int64_t>(chunk, ntp - c0);
             EventTimer mt(s);
-            launch_pair_masks(s, c0, nc, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, words, rec.as<uint64_t>());
+            launch_pair_masks(s, c0, nc, tpT.as<int32_t>(), tpU.as<int32_t>(), va, vb, mode, words,
+                              aux.pknn.as<int32_t>(), K, rec.as<uint64_t>());
             ms_m += mt.stop();
             EventTimer pt(s);
             launch_pairs_tiled(s, nc, rec.as<uint64_t>(), A.Xh.as<double>(), A.nrmh.as<double>(), B.Xh.as<double>(),
-                               B.nrmh.as<double>(), mode, idx->dp, aux.pknn.as<int32_t>(), K, aux.Xp.as<double>(),
+                               B.nrmh.as<double>(), mode, idx->dp, K, aux.Xp.as<double>(),
                                aux.nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
             ms += pt.stop();
         }

@@ -121,12 +121,18 @@ constexpr int kDl = kTile + 1;  // row stride (floats) of the in-tile distance m
 constexpr float kCertain = 1.0f - 0x1p-21f;   // threshold factor of the float32 witness certificate
 constexpr int kXs = kPiv + 4;   // row stride (floats) of the pivot distances: 16-byte aligned rows
 constexpr int kPairChunk = 8;   // tile pairs claimed per atomic
-constexpr int kPairRecMeta = 4;  // record words before the masks: tiles' start, length, home cell
+constexpr int kPairRecMeta = 12;  // record words before the masks: tiles' start, length, home cell; pivot ids
 constexpr int kPairRecWords = kPairRecordWords;
 static_assert(kPairRecWords == kPairRecMeta + 2 * kTile, "record layout");
 constexpr int kLuneChunk = 4;   // pairs claimed per atomic by one wave of the exhaustive scan
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline uint64_t uniform_u64(uint64_t v) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+__device__ inline int64_t uniform_i64(int64_t v) { return (int64_t)uniform_u64((uint64_t)v); }
 
 constexpr uint32_t kInfBits = 0x7f800000u;   // +inf as float32 bits
 __device__ inline uint32_t umax2(uint32_t a, uint32_t b) { return a > b ? a : b; }
@@ -254,14 +260,15 @@ __device__ inline void dist_blocks(const double *const sa[NB], const double *con
 
 // Stages I-III for the tile pairs [tp0, tp0 + n): one wave per tile pair
 // writes its record (kPairRecWords words): the tiles' start, length and home
-// cell, then the candidate masks of the rows of T (bit j: y = U[j] passes
-// Theorem 1 and Propositions 1-2 from x's side) and of the rows of U (bit i:
-// the same from y's side).  A pair (i, j) is a candidate when both bits are
-// set.  Only dependent gathers here; the pair kernel then starts each tile
-// pair from one streamed record.
+// cell, the Stage IV pivot witnesses, then the candidate masks of the rows
+// of T (bit j: y = U[j] passes Theorem 1 and Propositions 1-2 from x's side)
+// and of the rows of U (bit i: the same from y's side).  A pair (i, j) is a
+// candidate when both bits are set.  Only dependent gathers here; the pair
+// kernel then starts each tile pair from one streamed record.
 __global__ __launch_bounds__(256) void k_pair_masks(int64_t tp0, int64_t n, const int32_t *__restrict__ tpT,
                                                     const int32_t *__restrict__ tpU, PointsView A, PointsView B,
-                                                    int mode, int32_t words, uint64_t *__restrict__ rec) {
+                                                    int mode, int32_t words, const int32_t *__restrict__ pknn,
+                                                    int32_t K, uint64_t *__restrict__ rec) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= n) return;   // the whole wave
@@ -308,19 +315,30 @@ __global__ __launch_bounds__(256) void k_pair_masks(int64_t tp0, int64_t n, cons
     if (lane < 3) {
         const int32_t lo = lane == 0 ? sT : lane == 1 ? a : sU, hi = lane == 0 ? lT : lane == 1 ? lU : b;
         r[lane] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    } else if (lane < 3 + kPiv / 2) {
+        // Stage IV pivot witnesses: the K nearest pivots of cell a (a == b),
+        // else about half from each cell; slots past K repeat a's first
+        const int ka = (a == b) ? K : (K + 1) / 2;
+        int32_t pv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = 2 * (lane - 3) + h;
+            pv[h] = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
+        }
+        r[lane] = ((uint64_t)(uint32_t)pv[1] << 32) | (uint32_t)pv[0];
     }
 }
 
 __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_tiled(
     int64_t ntp, const uint64_t *__restrict__ rec, const double *__restrict__ XA, const double *__restrict__ nrmA,
-    const double *__restrict__ XB, const double *__restrict__ nrmB, int mode, int dp, const int32_t *__restrict__ pknn,
-    int32_t K, const double *__restrict__ Xp, const double *__restrict__ nrmp, PairList out,
+    const double *__restrict__ XB, const double *__restrict__ nrmB, int mode, int dp, int32_t K,
+    const double *__restrict__ Xp, const double *__restrict__ nrmp, PairList out,
     unsigned long long *dmax_bits, unsigned long long *work, unsigned long long *counters) {
     // LDS: rows of T and U (ld = dp + 1 doubles per row), norms, candidate
-    // masks, the 64 x 64 bit mask of Stage IV survivors, D(T,U); then either
-    // the pivot rows and pivot distances (Stages I-IV) or D(T,T) and D(U,U)
-    // (Stage V) in the same bytes.
-    extern __shared__ double lds[];
+    // masks, the 64 x 64 bit mask of Stage IV survivors, D(T,U), D(T,T); then
+    // either the pivot rows and pivot distances (Stages I-IV) or D(U,U)
+    // (Stage V) in the same bytes (for dp > 96 D(T,T) shares them too).
+    extern __shared__ __align__(16) double lds[];   // 16-byte loads of rows and distance tiles
     const int ld = dp + 1;
     double *sX = lds, *sY = sX + kTile * ld;
     double *nX = sY + kTile * ld, *nY = nX + kTile, *nP = nY + kTile;
@@ -349,12 +367,10 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             s_any = 0;
         }
         __syncthreads();
-        // wave-uniform from here on: the tile-pair record is read by scalar loads
-        const int64_t tp = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)s_tp >> 32))
-                                      << 32) |
-                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)s_tp));
+        const int64_t tp = uniform_i64(s_tp);
         __syncthreads();
         if (tp < 0) break;
+        // wave-uniform from here on: the record head is read by scalar loads
         const uint64_t *rc = rec + tp * kPairRecWords;
         const uint64_t m0 = rc[0], m1 = rc[1], m2 = rc[2];
         const int32_t sT = (int32_t)m0, lT = (int32_t)(m0 >> 32), a = (int32_t)m1;
@@ -369,9 +385,8 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             nY[lane] = lane < lU ? nrmB[sU + lane] : 0.0;
             mY[lane] = rc[kPairRecMeta + kTile + lane];
         } else if (w == 5) {
-            const int ka = (a == b) ? K : (K + 1) / 2;
             const int t = lane >> 2;
-            const int32_t pv = t < ka ? pknn[a * kPiv + t] : (t < K ? pknn[b * kPiv + (t - ka)] : pknn[a * kPiv]);
+            const int32_t pv = (int32_t)(rc[3 + (t >> 1)] >> (32 * (t & 1)));
             for (int c = 2 * (lane & 3); c < dp; c += 8) {
                 const double2 v = *reinterpret_cast<const double2 *>(Xp + (int64_t)pv * dp + c);
                 sP[t * ld + c] = v.x;
@@ -671,7 +686,7 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
     // cap entries, a power of two), or in pivot order when there are more
     // than cap of them (the order only steers the scan, it never changes a
     // verdict).
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem[];
     double *key = (double *)smem;
     int32_t *kid = (int32_t *)(key + cap);
     const int lane = threadIdx.x;
@@ -1037,14 +1052,16 @@ void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const 
 }
 
 void launch_pair_masks(hipStream_t s, int64_t tp0, int64_t n, const int32_t *tpT, const int32_t *tpU,
-                       const PointsView &A, const PointsView &B, int mode, int32_t words, uint64_t *rec) {
+                       const PointsView &A, const PointsView &B, int mode, int32_t words, const int32_t *pknn,
+                       int32_t K, uint64_t *rec) {
     if (n == 0) return;
-    k_pair_masks<<<(unsigned)div_up(n, 4), 256, 0, s>>>(tp0, n, tpT, tpU, A, B, mode, words, rec);
+    require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
+    k_pair_masks<<<(unsigned)div_up(n, 4), 256, 0, s>>>(tp0, n, tpT, tpU, A, B, mode, words, pknn, K, rec);
     GRNG_LAUNCHED();
 }
 
 void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const double *XA, const double *nrmA,
-                        const double *XB, const double *nrmB, int mode, int dp, const int32_t *pknn, int32_t K,
+                        const double *XB, const double *nrmB, int mode, int dp, int32_t K,
                         const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
                         uint64_t *counters) {
     if (ntp == 0) return;
@@ -1057,7 +1074,7 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const d
         GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(ntp, kPairChunk), 256 * 4));
-    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, rec, XA, nrmA, XB, nrmB, mode, dp, pknn, K, Xp, nrmp,
+    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, rec, XA, nrmA, XB, nrmB, mode, dp, K, Xp, nrmp,
                                                    out, (unsigned long long *)dmax_bits, (unsigned long long *)work,
                                                    (unsigned long long *)counters);
     GRNG_LAUNCHED();
