@@ -929,6 +929,12 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                                 const float *zr = Xhf + z * dp;
                                 float sx = 0.f, sy = 0.f;
                                 for (int cc = 0; cc < dp; cc += 4) {
+                                    // Early out after 8 coordinates (and every 32 more):
+                                    // adding non-negative terms never lowers a rounded
+                                    // sum, so a partial sum at or above thi proves the
+                                    // full one is too, and z is no witness.  Most
+                                    // candidates end here, reading half a 16-D row.
+                                    if ((cc == 8 || (cc > 8 && (cc & 31) == 0)) && !(sx < thi && sy < thi)) break;
                                     const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
                                     float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
                                     float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
