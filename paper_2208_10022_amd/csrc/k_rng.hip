@@ -929,12 +929,12 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                                 const float *zr = Xhf + z * dp;
                                 float sx = 0.f, sy = 0.f;
                                 for (int cc = 0; cc < dp; cc += 4) {
-                                    // Early out after 8 coordinates (and every 32 more):
-                                    // adding non-negative terms never lowers a rounded
-                                    // sum, so a partial sum at or above thi proves the
-                                    // full one is too, and z is no witness.  Most
-                                    // candidates end here, reading half a 16-D row.
-                                    if ((cc == 8 || (cc > 8 && (cc & 31) == 0)) && !(sx < thi && sy < thi)) break;
+                                    // Early out every 8 coordinates: adding non-negative
+                                    // terms never lowers a rounded sum, so a partial sum
+                                    // at or above thi proves the full one is too, and z
+                                    // is no witness.  Most candidates end at the first
+                                    // check, reading half a 16-D row.
+                                    if (cc >= 8 && (cc & 7) == 0 && !(sx < thi && sy < thi)) break;
                                     const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
                                     float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
                                     float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
@@ -958,17 +958,25 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                                 nrecheck += exact;
                             }
                             if (exact) {
+                                // Exact: on the grid every difference, square and
+                                // partial sum is an integer multiple of 2^-2q below
+                                // 2^53.  The partial sums are exact lower bounds, so
+                                // the same early out applies.
                                 const double *zr = Xh + z * dp;
-                                const double nz = nrmh[z];
                                 double sx = 0.0, sy = 0.0;
                                 for (int cc = 0; cc < dp; cc += 2) {
+                                    if (cc >= 8 && (cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
                                     const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
-                                    sx = fma(xs[cc], zv.x, sx);
-                                    sx = fma(xs[cc + 1], zv.y, sx);
-                                    sy = fma(ys[cc], zv.x, sy);
-                                    sy = fma(ys[cc + 1], zv.y, sy);
+                                    double e = xs[cc] - zv.x;
+                                    sx = fma(e, e, sx);
+                                    e = xs[cc + 1] - zv.y;
+                                    sx = fma(e, e, sx);
+                                    e = ys[cc] - zv.x;
+                                    sy = fma(e, e, sy);
+                                    e = ys[cc + 1] - zv.y;
+                                    sy = fma(e, e, sy);
                                 }
-                                wit = wit || ((nrx + nz - 2.0 * sx) < d2 && (nry + nz - 2.0 * sy) < d2);
+                                wit = wit || (sx < d2 && sy < d2);
                             }
                             ndist += 2;
                             ++ntests;
