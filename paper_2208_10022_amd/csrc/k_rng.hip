@@ -1017,16 +1017,21 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
         const double d2 = pd2[p];
         const double *xs = Xx + x * dp;
         const double *ys = X + y * dp;
-        const double nrx = nrmx[x], nry = nrm[y];
         bool dead = false;
         for (int64_t zb = z_from; zb < n; zb += 64) {
             const int64_t z = zb + lane;
             bool wit = false;
             if (z < n) {
+                // exact direct form; partial sums are exact lower bounds
                 const double *zr = X + z * dp;
-                const double d2xz = nrx + nrm[z] - 2.0 * dot_lds(xs, zr, dp);
-                const double d2yz = nry + nrm[z] - 2.0 * dot_lds(ys, zr, dp);
-                wit = d2xz < d2 && d2yz < d2;
+                double sx = 0.0, sy = 0.0;
+                for (int c = 0; c < dp; ++c) {
+                    if (c >= 8 && (c & 7) == 0 && !(sx < d2 && sy < d2)) break;
+                    const double ex = xs[c] - zr[c], ey = ys[c] - zr[c];
+                    sx = fma(ex, ex, sx);
+                    sy = fma(ey, ey, sy);
+                }
+                wit = sx < d2 && sy < d2;
                 ++ntests;
             }
             if (__ballot(wit)) { dead = true; break; }
