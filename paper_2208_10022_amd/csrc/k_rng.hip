@@ -646,6 +646,43 @@ __global__ __launch_bounds__(64) void k_pivot_knn(int64_t m, const double *dpp2,
     }
 }
 
+// The same list for layers of at most kKnnSortMax pivots: one workgroup
+// sorts pivot a's row of squared distances in LDS (bitonic, by distance,
+// then index) and keeps the first K.  Equal to the selection above.
+constexpr int kKnnSortMax = 4096;
+__global__ __launch_bounds__(256) void k_pivot_knn_sorted(int64_t m, int32_t cap, const double *dpp2, int32_t K,
+                                                          int32_t *pknn) {
+    extern __shared__ __align__(16) unsigned char knn_smem[];
+    double *key = (double *)knn_smem;
+    int32_t *kid = (int32_t *)(key + cap);
+    const int64_t a = blockIdx.x;
+    for (int e = threadIdx.x; e < cap; e += blockDim.x) {
+        key[e] = e < m ? dpp2[a * m + e] : INFINITY;
+        kid[e] = e;   // padding sorts after every pivot (index >= m)
+    }
+    __syncthreads();
+    for (int size = 2; size <= cap; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = threadIdx.x; e < cap; e += blockDim.x) {
+                const int f = e ^ stride;
+                if (f > e) {
+                    const bool up = (e & size) == 0;
+                    const bool gt = key[e] > key[f] || (key[e] == key[f] && kid[e] > kid[f]);
+                    if (gt == up) {
+                        const double tk = key[e];
+                        key[e] = key[f];
+                        key[f] = tk;
+                        const int32_t ti = kid[e];
+                        kid[e] = kid[f];
+                        kid[f] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int t = threadIdx.x; t < K; t += blockDim.x) pknn[a * K + t] = t < m ? kid[t] : (int32_t)a;
+}
+
 // All pairs (no pivot layer): i < j within one set, or every (i, j) across
 // two sets.  Thread per pair, one block row per i.
 __global__ void k_pairs_all(int64_t nA, const double *__restrict__ XA, const double *__restrict__ nrmA, int64_t nB,
@@ -1050,7 +1087,13 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
 
 void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t K, int32_t *pknn) {
     if (m == 0) return;
-    k_pivot_knn<<<(unsigned)m, 64, 0, s>>>(m, dpp2, K, pknn);
+    if (m <= kKnnSortMax && K > 16) {
+        int32_t cap = 2;
+        while (cap < m) cap <<= 1;
+        k_pivot_knn_sorted<<<(unsigned)m, 256, (size_t)cap * 12, s>>>(m, cap, dpp2, K, pknn);
+    } else {
+        k_pivot_knn<<<(unsigned)m, 64, 0, s>>>(m, dpp2, K, pknn);
+    }
     GRNG_LAUNCHED();
 }
 
