@@ -750,7 +750,11 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
         double d2 = INFINITY;
         if (k < m && gcount[k] > 0) {
             d2 = row[k];
-            keep = !surely_ge(sqrt_lo(d2), dvor[k], dmax_hi);
+            // skip when d(x, p_k) - radius_k >= the row's largest pair distance,
+            // tested on squares (d2 is exact; the margin covers the rounding of
+            // the right side)
+            const double r = dvor[k] + dmax_hi;
+            keep = !(d2 >= r * r * (1.0 + 1e-12));
         }
         const uint64_t bal = __ballot(keep);
         if (pass == 1 && keep) {
