@@ -239,6 +239,10 @@ def main():
         "edges": edges,
         "witness_tests": st["witness_tests"],
         "witness_tests_per_s": st["witness_tests"] / (ms / 1000.0),
+        "lune_tests_per_s": st["lune_tests"] / (st["ms_lune"] / 1000.0) if st["ms_lune"] > 0 else None,
+        # the work pruning avoids: every pair, and every (pair, witness) test
+        "dense_pairs": W.n * (W.n - 1) // 2,
+        "dense_tests": W.n * (W.n - 1) * (W.n - 2) // 2,
         "distance_computations": st["distance_computations"],
         "candidate_pairs": st["candidate_pairs"],
         "stage4_survivors": st["stage4_survivors"],
