@@ -127,6 +127,7 @@ def parse():
     ap.add_argument("--vgrng-pivots", type=int, default=0, help="Proposition 1 witness pivots per block (autotune 0)")
     ap.add_argument("--stage4-pivots", type=int, default=0, help="Stage IV pivot witnesses (autotune 0)")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
+    ap.add_argument("--queries", type=int, default=4096, help="queries timed against the built index (0 = none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
     return ap.parse_args()
@@ -155,6 +156,32 @@ def cpu_baseline(W, rows_hint: int):
     return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": "RNG rows of %d random points (each row scans all %d points), %.2f s measured, "
                       "scaled by N/rows to the full build" % (rows, W.n, dt)}
+
+
+def query_throughput(idx, W, nq: int) -> dict:
+    """RNG neighbours of nq fresh points of the same mixture against the built
+    index (device-resident queries; the index is unchanged)."""
+    import numpy as np
+    import torch
+
+    import synth
+    Q = torch.from_numpy(synth.queries_like(W, nq, sub=2)).cuda()
+    idx.query_neighbors(Q)   # sizes the output once
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        off, _ = idx.query_neighbors(Q)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    st = idx.stats()
+    ms = float(np.median(times))
+    return {"nq": nq, "ms": ms, "queries_per_s": nq / (ms / 1e3), "neighbours": int(off[-1].item()),
+            "distance_computations_per_query": st["distance_computations"] / nq,
+            "witness_tests_per_query": st["witness_tests"] / nq}
 
 
 def main():
@@ -215,6 +242,7 @@ def main():
     ms = float(np.median(times))
     st = stats[-1]
     edges = idx.num_edges()
+    queries = query_throughput(idx, W, args.queries) if args.queries > 0 else None
     idx.close()
 
     workload = "clustered-n%d-d16-m1000-p%d" % (W.n, args.precision)
@@ -260,6 +288,7 @@ def main():
         "ms_pair_masks": st["ms_pair_masks"],
         "ms_pairs": st["ms_pairs"],
         "ms_lune": st["ms_lune"],
+        "queries": queries,
         "roofline": roofline(st, workload),
         "kernels": kernel_rooflines(st),
         "wall_s": wall,
