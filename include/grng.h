@@ -122,7 +122,8 @@ typedef struct grng_stats {
     double vgrng_ops;             /* (min,max) pairs evaluated by the virtual-pivot kernel: 2 n m kw, kw the
                                      Proposition 1 witness pivots per block (vgrng_pivots) */
     double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair,
-                                     plus 2 dp * 2*64*64 per tile pair that reaches Stage V */
+                                     plus 2 dp * 64*64 per tile pair that reaches Stage V (D(U,U)) and per
+                                     D(T,T) computed (kept while consecutive tile pairs share T) */
     double lune_bytes;            /* algorithmic bytes read by the lune kernel per witness test: the
                                      witness row and its cell bound, 4 dp + 4 with the float32 screen,
                                      8 dp + 16 in float64 */

@@ -173,7 +173,8 @@ enum Counter {
     C_RECHECK,        // exact re-decisions
     C_SURV,           // pairs left for the exhaustive scan (after Stage V)
     C_LUNE,           // witness predicates evaluated by the exhaustive scan
-    C_TPV,            // tile pairs that reached Stage V (in-tile distance matrices computed)
+    C_TPV,            // tile pairs that reached Stage V (D(U,U) computed)
+    C_TTV,            // D(T,T) computations (not repeated while consecutive tile pairs share T)
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,

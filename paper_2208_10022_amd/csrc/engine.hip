@@ -736,9 +736,10 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
     idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * (double)idx->aux.kw;
     // MFMA flops of the pair kernel: D(T,U) and the two pivot blocks for every
-    // tile pair, D(T,T) and D(U,U) for those that reach Stage V.
+    // tile pair, D(U,U) for those that reach Stage V, D(T,T) each time it is
+    // computed (it is kept while consecutive tile pairs share T).
     idx->stats.pairs_flops = 2.0 * idx->dp * ((64.0 * 64.0 + 2.0 * 64.0 * 16.0) * (double)bt.tile_pairs +
-                                              2.0 * 64.0 * 64.0 * (double)c[C_TPV]);
+                                              64.0 * 64.0 * (double)(c[C_TPV] + c[C_TTV]));
     {
         const int K = stage4_pivots(idx);
         idx->stats.stage4_ops = 2.0 * 64.0 * 64.0 * (double)((K + 3) / 4 * 4) * (double)bt.tile_pairs;

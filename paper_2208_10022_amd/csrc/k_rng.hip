@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     int32_t tt_start = -1, sx_start = -1;   // tiles whose D(T,T) / rows are in LDS (block-uniform)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool self = (mode & PM_SELF) != 0;
-    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0;
+    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nttv = 0;
     WaveOut wo;
     __shared__ int64_t s_tp;
     __shared__ int s_any;
@@ -483,6 +483,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         {
             const bool need_tt = self && sT != tt_start;
             if (need_tt && keep_tt) tt_start = sT;
+            nttv += need_tt && tid == 0;
             const bool us = !need_tt || w >= 4;
             const int nh = need_tt ? 2 : 1;
             const double *sa[2], *na[2];
@@ -551,6 +552,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         atomicAdd(&counters[C_WTEST], (unsigned long long)tests);
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
         if (ntpv) atomicAdd(&counters[C_TPV], (unsigned long long)ntpv);
+        if (nttv) atomicAdd(&counters[C_TTV], (unsigned long long)nttv);
     }
 }
 
