@@ -462,9 +462,10 @@ void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, cons
     if (n == 0) return;
     require(kw >= 1 && kw <= m, GRNG_EINVAL, "witness pivot count out of range");
     require(div_up(m, kVT_J) <= 65535, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
-    // point rows per pass: their witness distances take at most 4 GiB
-    const int64_t chunk = std::min<int64_t>(div_up(n, kVT_X) * kVT_X,
-                                            std::max<int64_t>(kVT_X, (((int64_t)1 << 30) / kw) / kVT_X * kVT_X));
+    // point rows per pass: at most 2^19, whose witness distances take at most 4 GiB
+    const int64_t chunk = std::min<int64_t>(
+        std::min<int64_t>(div_up(n, kVT_X) * kVT_X, (int64_t)1 << 19),
+        std::max<int64_t>(kVT_X, (((int64_t)1 << 30) / kw) / kVT_X * kVT_X));
     DevBuf ax;
     ax.alloc(4 * (size_t)chunk * (size_t)kw);
     for (int64_t x0 = 0; x0 < n; x0 += chunk) {

@@ -288,7 +288,9 @@ def test_subspace3_full_size_sampled_rows(G):
     """The three-layer workload at full size: 1,000,000 points in 32-D near an
     8-D subspace, 100 coarse and 3,000 fine pivots.  Both GRNG layers are
     checked (coarse in full, fine on sampled rows) and RNG rows of sampled
-    points are compared with the oracle one by one."""
+    points are compared with the oracle one by one.  At this size the
+    Proposition 1 witness distances are gathered in two passes of points and
+    the 146M tile-pair records are written in 70 chunks."""
     say("subspace3 full size n=1000000 d=32 m=100/3000")
     W = synth.subspace3()
     (Lc, Lf) = W.layers
