@@ -124,9 +124,9 @@ typedef struct grng_stats {
     double pairs_flops;           /* MFMA flops of the pair kernel: 2 dp (64*64 + 2*64*16) per tile pair,
                                      plus 2 dp * 64*64 per tile pair that reaches Stage V (D(U,U)) and per
                                      D(T,T) computed (kept while consecutive tile pairs share T) */
-    double lune_bytes;            /* algorithmic bytes read by the lune kernel per witness test: the
+    double lune_bytes;            /* algorithmic bytes read by the lune kernel: per witness test the
                                      witness row and its cell bound, 4 dp + 4 with the float32 screen,
-                                     8 dp + 16 in float64 */
+                                     8 dp + 8 in float64 (a test ending early on a partial sum reads less) */
     double stage4_ops;            /* (min,max) operations of Stage IV in the pair kernel: 2*64*64*K'
                                      per tile pair, K' = pivot witnesses rounded up to a multiple of 4 */
     double ms_autotune;           /* device time of the autotuner's trial builds (0 when it has not run) */

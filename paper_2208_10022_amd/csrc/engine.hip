@@ -729,9 +729,9 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.exhaustive_pairs = (double)c[C_SURV];
     idx->stats.lune_tests = (double)c[C_LUNE];
     // Bytes a witness test reads: the witness row and its cell-distance
-    // bound (float32 with the float32 screen; float64 row, norm and bound
-    // otherwise).
-    idx->stats.lune_bytes = (double)c[C_LUNE] * (idx->opt.precision == GRNG_PREC_FP64 ? 8.0 * idx->dp + 16.0
+    // bound (float32 with the float32 screen, float64 otherwise); a test
+    // that ends early on a partial sum reads less.
+    idx->stats.lune_bytes = (double)c[C_LUNE] * (idx->opt.precision == GRNG_PREC_FP64 ? 8.0 * idx->dp + 8.0
                                                                                      : 4.0 * idx->dp + 4.0);
     const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
     idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * (double)idx->aux.kw;

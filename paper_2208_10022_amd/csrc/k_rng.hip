@@ -9,18 +9,23 @@
 //                 Propositions 1-2), and if the home cells of x and y survive
 //                 the same virtual-pivot test with cell radii;
 //   Stage IV      pivots as witnesses;
-//   Stages V-VI   exhaustive scan over points grouped by home cell, skipping a
+//   Stage V       the points of the pair's two tiles as witnesses;
+//   Stage VI      exhaustive scan over points grouped by home cell, skipping a
 //                 whole cell when max(d(x,p), d(y,p)) - radius(p) >= d(x,y)
 //                 (Proposition 3) and a single point z of the cell when
-//                 max(d(x,p), d(y,p)) - d(z,p) >= d(x,y) (Proposition 4).
-//                 These skips use square roots, so they are taken only with a
-//                 safety margin (pruning less only costs work).
+//                 max(d(x,p), d(y,p)) - d(z,p) >= d(x,y) or d(z,p) -
+//                 min(d(x,p), d(y,p)) >= d(x,y) (Proposition 4, both sides of
+//                 the triangle inequality).  These skips use square roots, so
+//                 they are taken only with a safety margin (pruning less only
+//                 costs work).
 //
 // Layout: points in home order (grouped by nearest pivot), coordinates as
-// zero-padded float64 rows of dp values.  One wave owns one row point x in
-// the pair enumeration and one pair in the lune scan; the 64 lanes stream
-// candidate points y (pairs) or witnesses z (lune scan) with coalesced row
-// loads, and a wave ballot ends the scan at the first witness.
+// zero-padded float64 rows of dp values and their exact float32 copies.
+// Stages I-III run in k_pair_masks (one wave per 64 x 64 tile pair, writing
+// a record); Stages IV-V in k_pairs_tiled (one workgroup per tile pair at a
+// time, tiles in LDS); Stage VI in k_lune_guided (one wave per surviving
+// pair, 64 lanes streaming witnesses, a wave ballot ends the scan at the
+// first witness).
 #include <algorithm>
 
 #include "common.h"
@@ -97,12 +102,13 @@ __device__ inline bool claim_chunk(int64_t n, int64_t chunk, int xcd0, int &xr, 
 // Candidate pairs guided by the pivot layer (Stages I-V), tiled.
 //
 // Points are split into tiles: chunks of at most 64 consecutive home-order
-// points of one home cell.  A workgroup takes a pair of tiles (T, U), T <= U,
-// whose cells survive each other's virtual-pivot test, and for the 64 x 64
-// pairs (x in T, y in U):
+// points of one home cell.  Tile pairs (T, U), T <= U, whose cells survive
+// each other's virtual-pivot test are listed; for the 64 x 64 pairs
+// (x in T, y in U):
+//   * Stages I-III as bit masks (k_pair_masks): P(x) within GRNG(y) and P(y)
+//     within GRNG(x) from the transposed virtual-pivot bitsets, and the cell
+//     bits of both;
 //   * exact d^2(x, y) from an f64 MFMA tile (16x16x4 blocks, operands in LDS);
-//   * Stages I-III as bit masks: P(x) within GRNG(y) and P(y) within GRNG(x)
-//     from the transposed virtual-pivot bitsets, and the cell bits of both;
 //   * Stage IV: the pivots nearest to the two cells as witnesses, with exact
 //     d^2 to the pivots from two more MFMA tiles;
 //   * Stage V: the 128 points of T and U as witnesses.  The in-tile distance
