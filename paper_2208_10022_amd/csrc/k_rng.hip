@@ -886,7 +886,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
         const double d2 = pd2[p];
         const double *xs = Xx + x * dp;
         const double *ys = Xh + y * dp;
-        const double nrx = nrmx[x], nry = nrmh[y];
+        const double nry = nrmh[y];
         const double dxy_hi = sqrt_hi(d2);
         const float *xf = F32 ? Xxf + x * dp : nullptr;
         const float *yf = F32 ? Xhf + y * dp : nullptr;
