@@ -8,6 +8,8 @@ step = build the GRNG of the pivot layer, then the exact RNG of all points
 resident in device memory before timing starts.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+``--workload subspace3`` times the 1M x 32-D three-layer build instead (for
+profiling that configuration; the benchmark line is the default workload).
 """
 from __future__ import annotations
 
@@ -128,6 +130,9 @@ def parse():
     ap.add_argument("--stage4-pivots", type=int, default=0, help="Stage IV pivot witnesses (autotune 0)")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
     ap.add_argument("--queries", type=int, default=4096, help="queries timed against the built index (0 = none)")
+    ap.add_argument("--workload", default="clustered", choices=["clustered", "subspace3"],
+                    help="clustered: the 100k x 16-D two-layer build (the benchmark); subspace3: the 1M x 32-D "
+                         "three-layer build (100 coarse, 3,000 fine pivots)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
     return ap.parse_args()
@@ -206,15 +211,14 @@ def main():
     import paper_2208_10022_amd as P
 
     dev = torch.device("cuda:0")
-    W = synth.clustered(n=args.n)
-    L = W.layers[0]
+    W = synth.subspace3() if args.workload == "subspace3" else synth.clustered(n=args.n)
     X = torch.from_numpy(W.X).to(dev)
-    pid = torch.from_numpy(L.pivot_ids).to(dev)
-    rad = torch.from_numpy(L.radii).to(dev)
+    layers = [(torch.from_numpy(L.pivot_ids).to(dev), torch.from_numpy(L.radii).to(dev)) for L in W.layers]
     torch.cuda.synchronize()
 
     def step(idx):
-        idx.build_grng_layer(0, pid, rad)
+        for level, (pid, rad) in enumerate(layers):
+            idx.build_grng_layer(level, pid, rad)
         idx.build_rng()
 
     idx = P.Index(X, grid_exp=W.q, precision=args.precision, autotune=args.autotune,
@@ -245,7 +249,15 @@ def main():
     queries = query_throughput(idx, W, args.queries) if args.queries > 0 else None
     idx.close()
 
-    workload = "clustered-n%d-d16-m1000-p%d" % (W.n, args.precision)
+    sizes = [int(len(L.pivot_ids)) for L in W.layers]
+    if args.workload == "subspace3":
+        workload = "subspace3-n%d-d%d-m%d-p%d" % (W.n, W.d, sizes[-1], args.precision)
+        described = ("three-layer GRNG->GRNG->RNG, N=%d, D=%d near an 8-D subspace, %d coarse and %d fine "
+                     "pivots" % (W.n, W.d, sizes[0], sizes[-1]))
+    else:
+        workload = "clustered-n%d-d16-m1000-p%d" % (W.n, args.precision)
+        described = ("two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), 1,000 random pivots with "
+                     "100-NN radii" % W.n)
     line = {
         "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
         "value": ms / 1000.0,
@@ -259,9 +271,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f32",
         "data": "synthetic",
-        "config": {"workload": "two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), "
-                               "1,000 random pivots with 100-NN radii" % W.n,
-                   "n": W.n, "d": W.d, "pivots": int(len(L.pivot_ids)), "grid_exp": W.q,
+        "config": {"workload": described,
+                   "n": W.n, "d": W.d, "pivots": sizes[-1] if len(sizes) == 1 else sizes, "grid_exp": W.q,
                    "precision": "float64 distances" if args.precision == 0 else
                    "float32 screens, float64 re-decision of doubtful comparisons"},
         "edges": edges,
