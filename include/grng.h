@@ -74,7 +74,10 @@ enum {
 
 enum {
     GRNG_ORDER_DISTANCE = 0, /* witnesses visited nearest-first (Section 2, Stages III and V) */
-    GRNG_ORDER_LEARNED = 1   /* witness domains ranked by the learned scorer (grng_set_scorer) */
+    GRNG_ORDER_LEARNED = 1,  /* witness domains ranked by the learned scorer (grng_set_scorer) */
+    GRNG_ORDER_LUNE = 2      /* within each group of 64 domains taken nearest-first, a pair visits them by
+                                increasing max(d(x,p), d(y,p)) (pays off in high dimensions, where a
+                                witness test reads a long row) */
 };
 
 typedef struct grng_options {

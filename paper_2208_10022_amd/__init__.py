@@ -18,7 +18,7 @@ GRNG_OK = 0
 STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_EDEVICE", -4: "GRNG_ENOTGRID",
                 -5: "GRNG_ECAPACITY", -6: "GRNG_ESTATE"}
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
-ORDER_DISTANCE, ORDER_LEARNED = 0, 1
+ORDER_DISTANCE, ORDER_LEARNED, ORDER_LUNE = 0, 1, 2
 
 # Entry points declared in include/grng.h (checked by the CPU tests).
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",

@@ -373,7 +373,8 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
                         const int32_t *zstart, const int32_t *grp_off, const double *dvor,
                         const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
-                        const double *rel_d2x, const double *rad, const uint16_t *scorer, uint8_t *alive,
+                        const double *rel_d2x, const double *rad, const uint16_t *scorer, bool lune_order,
+                        uint8_t *alive,
                         uint64_t *work, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,

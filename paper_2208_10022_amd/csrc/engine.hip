@@ -84,7 +84,8 @@ void check_opts(const grng_options *o) {
     require(o != nullptr, GRNG_EINVAL, "options pointer is NULL");
     require(o->grid_exp >= 0 && o->grid_exp <= 60, GRNG_EINVAL, "grid_exp must be in [0, 60]");
     require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_BF16, GRNG_EINVAL, "unknown precision");
-    require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED, GRNG_EINVAL,
+    require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED ||
+                o->witness_order == GRNG_ORDER_LUNE, GRNG_EINVAL,
             "unknown witness order");
     require(o->use_graph == 0 || o->use_graph == 1, GRNG_EINVAL, "use_graph must be 0 or 1");
     require(o->autotune == 0 || o->autotune == 1, GRNG_EINVAL, "autotune must be 0 or 1");
@@ -678,6 +679,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                        S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),
                        rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
                        idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,
+                       idx->opt.witness_order == GRNG_ORDER_LUNE,
                        alive.as<uint8_t>(), ctr + C_WORK0, ctr);
     const double lms = lt.stop();
     bt.lune += lms;

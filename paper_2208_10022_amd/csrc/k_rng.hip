@@ -844,6 +844,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
     const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
     const double *__restrict__ rel_d2x, const double *__restrict__ rad, const uint16_t *__restrict__ scorer,
+    bool lune_order,
     uint8_t *__restrict__ alive, unsigned long long *work, unsigned long long *counters) {
     // Per-wave cell table in visit order: first member, exclusive member
     // prefix (entry 64 = total) and max(d(x,p), d(y,p)) lower bound.
@@ -913,6 +914,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 gmin = fmin(sqrt_hi(d2x), sqrt_hi(d2y));
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
                 scan = !surely_ge(gmax, dvor[g], dxy_hi);
+                if (lune_order) key = (float)(-gmax);   // nearest to both ends first
                 if (scan) {
                     z0 = zstart ? zstart[g] : grp_off[g];
                     nmem = grp_off[g + 1] - z0;
@@ -928,9 +930,10 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             if (__ballot(dead)) { dead = true; break; }
             if (!__ballot(scan && nmem > 0)) continue;
             // Visit order: chunk order (cells sorted by distance to x), or by
-            // descending learned score (wave bitonic sort of (score, lane)).
+            // descending key, the learned score or -max(d(x,p), d(y,p)) (wave
+            // bitonic sort of (key, lane)).
             int src = lane;
-            if (scorer) {
+            if (scorer || lune_order) {
                 float k = scan ? key : -INFINITY;
                 for (int sz = 2; sz <= 64; sz <<= 1)
                     for (int j = sz >> 1; j > 0; j >>= 1) {
@@ -1198,6 +1201,7 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
                         const int32_t *rel_grp, const double *rel_d2x, const double *rad, const uint16_t *scorer,
+                        bool lune_order,
                         uint8_t *alive, uint64_t *work, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
@@ -1211,11 +1215,13 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     if (f32)
         k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
-            rel_off, rel_grp, rel_d2x, rad, scorer, alive, (unsigned long long *)work, (unsigned long long *)counters);
+            rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            (unsigned long long *)counters);
     else
         k_lune_guided<false><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
-            rel_off, rel_grp, rel_d2x, rad, scorer, alive, (unsigned long long *)work, (unsigned long long *)counters);
+            rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 

@@ -86,6 +86,24 @@ def test_clustered_3000_d16_matches_golden(G, prec):
     assert st["candidate_pairs"] > 0
 
 
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_lune_visit_order_keeps_edges(G, prec):
+    """Visiting a pair's witness cells by max(d(x,p), d(y,p)) instead of
+    d(x,p) changes only the number of witness tests."""
+    say("lune visit order, precision", prec)
+    W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
+    L = W.layers[0]
+    E0, _, s0 = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec)
+    E, _, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec, witness_order=G.ORDER_LUNE)
+    assert np.array_equal(E, golden_edges("clustered_n3000_d16_rng_edges.txt"))
+    assert np.array_equal(E, E0)
+    assert st["exhaustive_pairs"] == s0["exhaustive_pairs"] and st["lune_tests"] > 0
+    W = synth.clustered(n=900, d=96, clusters=3, m=24, knn=30, q=18, sub=8)
+    L = W.layers[0]
+    E, _, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec, witness_order=G.ORDER_LUNE)
+    assert np.array_equal(E, native.rng_edges(W.X, W.q))
+
+
 @pytest.mark.parametrize("n,d,m,clusters,seed", [
     (1037, 2, 30, 4, 0), (2111, 3, 70, 6, 1), (1500, 5, 16, 3, 2), (777, 16, 100, 5, 3),
     (2049, 7, 64, 9, 4), (300, 1, 10, 2, 5), (1900, 12, 1, 4, 6), (650, 33, 20, 3, 7),
