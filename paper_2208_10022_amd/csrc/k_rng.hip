@@ -961,78 +961,93 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             int kc[4] = {0, 0, 0, 0};   // per-slot cursors into the table (monotone)
             for (int base = 0; base < total; base += 256) {
                 bool wit = false;
+                // Slots of this step: witness id, its cell's table entry and
+                // d(z, p), the four loads of d(z, p) in flight together.
+                int32_t zz[4], ce[4];
+                bool ok[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int sl = base + 64 * u + lane;
-                    if (sl < total) {
+                    ok[u] = sl < total;
+                    zz[u] = 0;
+                    ce[u] = 0;
+                    if (ok[u]) {
                         while (pre[kc[u] + 1] <= sl) ++kc[u];
-                        const int64_t z = z0t[kc[u]] + (sl - pre[kc[u]]);
+                        ce[u] = kc[u];
+                        zz[u] = z0t[kc[u]] + (sl - pre[kc[u]]);
                         // The pair's own points are never witnesses (max = d(x,y)).
-                        if (z == y || (xself && z == x)) continue;
-                        // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y);
-                        // by the same triangle inequality also when d(z,p) -
-                        // min(d(x,p), d(y,p)) >= d(x,y).  The stored d(z,p) is an
-                        // upper bound; 1 - 2^-21 of it is a lower bound.
-                        const double dzh = F32 ? (double)dhomef[z] : dhome[z];
-                        if (!surely_ge(gmt[kc[u]], dzh, dxy_hi) &&
-                            !surely_ge(dzh * (1.0 - 0x1p-21), gmn[kc[u]], dxy_hi)) {
-                            bool exact = !F32;
-                            if (F32) {
-                                const float *zr = Xhf + z * dp;
-                                float sx = 0.f, sy = 0.f;
-                                for (int cc = 0; cc < dp; cc += 4) {
-                                    // Early out every 8 coordinates: adding non-negative
-                                    // terms never lowers a rounded sum, so a partial sum
-                                    // at or above thi proves the full one is too, and z
-                                    // is no witness.  Most candidates end at the first
-                                    // check, reading half a 16-D row.
-                                    if (cc >= 8 && (cc & 7) == 0 && !(sx < thi && sy < thi)) break;
-                                    const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
-                                    float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
-                                    float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
-                                    sx = fmaf(a0, a0, sx);
-                                    sx = fmaf(a1, a1, sx);
-                                    sx = fmaf(a2, a2, sx);
-                                    sx = fmaf(a3, a3, sx);
-                                    a0 = yf[cc] - zv.x;
-                                    a1 = yf[cc + 1] - zv.y;
-                                    a2 = yf[cc + 2] - zv.z;
-                                    a3 = yf[cc + 3] - zv.w;
-                                    sy = fmaf(a0, a0, sy);
-                                    sy = fmaf(a1, a1, sy);
-                                    sy = fmaf(a2, a2, sy);
-                                    sy = fmaf(a3, a3, sy);
-                                }
-                                if (sx < tlo && sy < tlo)
-                                    wit = true;
-                                else if (!(sx >= thi || sy >= thi))
-                                    exact = true;   // too close to call in float32
-                                nrecheck += exact;
+                        ok[u] = !(zz[u] == y || (xself && zz[u] == x));
+                    }
+                }
+                double dzv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) dzv[u] = ok[u] ? (F32 ? (double)dhomef[zz[u]] : dhome[zz[u]]) : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!ok[u]) continue;
+                    const int64_t z = zz[u];
+                    const double dzh = dzv[u];
+                    // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y);
+                    // by the same triangle inequality also when d(z,p) -
+                    // min(d(x,p), d(y,p)) >= d(x,y).  The stored d(z,p) is an
+                    // upper bound; 1 - 2^-21 of it is a lower bound.
+                    if (!surely_ge(gmt[ce[u]], dzh, dxy_hi) && !surely_ge(dzh * (1.0 - 0x1p-21), gmn[ce[u]], dxy_hi)) {
+                        bool exact = !F32;
+                        if (F32) {
+                            const float *zr = Xhf + z * dp;
+                            float sx = 0.f, sy = 0.f;
+                            for (int cc = 0; cc < dp; cc += 4) {
+                                // Early out every 8 coordinates: adding non-negative
+                                // terms never lowers a rounded sum, so a partial sum
+                                // at or above thi proves the full one is too, and z
+                                // is no witness.  Most candidates end at the first
+                                // check, reading half a 16-D row.
+                                if (cc >= 8 && (cc & 7) == 0 && !(sx < thi && sy < thi)) break;
+                                const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
+                                float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
+                                float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
+                                sx = fmaf(a0, a0, sx);
+                                sx = fmaf(a1, a1, sx);
+                                sx = fmaf(a2, a2, sx);
+                                sx = fmaf(a3, a3, sx);
+                                a0 = yf[cc] - zv.x;
+                                a1 = yf[cc + 1] - zv.y;
+                                a2 = yf[cc + 2] - zv.z;
+                                a3 = yf[cc + 3] - zv.w;
+                                sy = fmaf(a0, a0, sy);
+                                sy = fmaf(a1, a1, sy);
+                                sy = fmaf(a2, a2, sy);
+                                sy = fmaf(a3, a3, sy);
                             }
-                            if (exact) {
-                                // Exact: on the grid every difference, square and
-                                // partial sum is an integer multiple of 2^-2q below
-                                // 2^53.  The partial sums are exact lower bounds, so
-                                // the same early out applies.
-                                const double *zr = Xh + z * dp;
-                                double sx = 0.0, sy = 0.0;
-                                for (int cc = 0; cc < dp; cc += 2) {
-                                    if (cc >= 8 && (cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
-                                    const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
-                                    double e = xs[cc] - zv.x;
-                                    sx = fma(e, e, sx);
-                                    e = xs[cc + 1] - zv.y;
-                                    sx = fma(e, e, sx);
-                                    e = ys[cc] - zv.x;
-                                    sy = fma(e, e, sy);
-                                    e = ys[cc + 1] - zv.y;
-                                    sy = fma(e, e, sy);
-                                }
-                                wit = wit || (sx < d2 && sy < d2);
-                            }
-                            ndist += 2;
-                            ++ntests;
+                            if (sx < tlo && sy < tlo)
+                                wit = true;
+                            else if (!(sx >= thi || sy >= thi))
+                                exact = true;   // too close to call in float32
+                            nrecheck += exact;
                         }
+                        if (exact) {
+                            // Exact: on the grid every difference, square and
+                            // partial sum is an integer multiple of 2^-2q below
+                            // 2^53.  The partial sums are exact lower bounds, so
+                            // the same early out applies.
+                            const double *zr = Xh + z * dp;
+                            double sx = 0.0, sy = 0.0;
+                            for (int cc = 0; cc < dp; cc += 2) {
+                                if (cc >= 8 && (cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
+                                const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
+                                double e = xs[cc] - zv.x;
+                                sx = fma(e, e, sx);
+                                e = xs[cc + 1] - zv.y;
+                                sx = fma(e, e, sx);
+                                e = ys[cc] - zv.x;
+                                sy = fma(e, e, sy);
+                                e = ys[cc + 1] - zv.y;
+                                sy = fma(e, e, sy);
+                            }
+                            wit = wit || (sx < d2 && sy < d2);
+                        }
+                        ndist += 2;
+                        ++ntests;
                     }
                 }
                 if (__ballot(wit)) { dead = true; break; }
@@ -1206,12 +1221,14 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
-    // Three workgroups (12 waves) per CU: the waves claim pairs dynamically,
-    // so the grid only sets how many scan at once, and more concurrent waves
-    // stream more distinct witness rows through the same caches (16 waves
-    // per CU measured 8% slower on the 100k x 16-D build, 8 waves 31%).
-    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * 3));
+    // The waves claim pairs dynamically, so the grid only sets how many scan
+    // at once.  The float32 scan waits on witness-row loads: four workgroups
+    // (16 waves) per CU, as many as its registers allow, hide more of that
+    // latency than three (15% faster on the 100k x 16-D build).  The float64
+    // scan reads twice the bytes per row and is 9% slower with 16 waves than
+    // with 12.
     const bool f32 = Xxf && Xhf && dhomef;
+    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * (f32 ? 4 : 3)));
     if (f32)
         k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
