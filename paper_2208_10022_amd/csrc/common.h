@@ -370,7 +370,7 @@ void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const 
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
-                        const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
+                        int64_t nh, const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
                         const int32_t *zstart, const int32_t *grp_off, const double *dvor,
                         const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
                         const double *rel_d2x, const double *rad, const uint16_t *scorer, bool lune_order,

@@ -673,7 +673,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     EventTimer lt(s);
     const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
-                       X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.dhome.as<double>(),
+                       X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.n, S.dhome.as<double>(),
                        f32 ? X.Xf.as<float>() : nullptr, f32 ? S.Xf.as<float>() : nullptr,
                        f32 ? S.dhomef.as<float>() : nullptr, zstart,
                        S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),

@@ -1212,7 +1212,7 @@ void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const 
 
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                         int dp, const double *Xx, const double *nrmx, const double *Xh, const double *nrmh,
-                        const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
+                        int64_t nh, const double *dhome, const float *Xxf, const float *Xhf, const float *dhomef,
                         const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
                         const int32_t *rel_grp, const double *rel_d2x, const double *rad, const uint16_t *scorer,
@@ -1222,13 +1222,15 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
     // The waves claim pairs dynamically, so the grid only sets how many scan
-    // at once.  The float32 scan waits on witness-row loads: four workgroups
-    // (16 waves) per CU, as many as its registers allow, hide more of that
-    // latency than three (15% faster on the 100k x 16-D build).  The float64
-    // scan reads twice the bytes per row and is 9% slower with 16 waves than
-    // with 12.
+    // at once.  While the float32 witness rows fit in the 256 MiB last-level
+    // cache, the scan waits on their load latency, and four workgroups (16
+    // waves) per CU, as many as its registers allow, hide more of it than
+    // three (15% faster on the 100k x 16-D build).  Rows streamed from HBM
+    // (1M x 96-D: 384 MB) and the float64 scan (twice the bytes per row) run
+    // 9-10% faster with three.
     const bool f32 = Xxf && Xhf && dhomef;
-    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * (f32 ? 4 : 3)));
+    const bool cached = f32 && nh * (int64_t)dp * 4 <= (int64_t)256 << 20;
+    const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * (cached ? 4 : 3)));
     if (f32)
         k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
