@@ -961,8 +961,10 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             int kc[4] = {0, 0, 0, 0};   // per-slot cursors into the table (monotone)
             for (int base = 0; base < total; base += 256) {
                 bool wit = false;
-                // Slots of this step: witness id, its cell's table entry and
-                // d(z, p), the four loads of d(z, p) in flight together.
+                // A step runs in phases so that the loads of its four slots
+                // are in flight together: slot -> witness id and cell entry,
+                // then d(z, p), then Proposition 4, then the first 8
+                // coordinates of the rows that pass it.
                 int32_t zz[4], ce[4];
                 bool ok[4];
 #pragma unroll
@@ -982,70 +984,101 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                 double dzv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) dzv[u] = ok[u] ? (F32 ? (double)dhomef[zz[u]] : dhome[zz[u]]) : 0.0;
+                // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y);
+                // by the same triangle inequality also when d(z,p) -
+                // min(d(x,p), d(y,p)) >= d(x,y).  The stored d(z,p) is an
+                // upper bound; 1 - 2^-21 of it is a lower bound.
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!ok[u]) continue;
-                    const int64_t z = zz[u];
-                    const double dzh = dzv[u];
-                    // Proposition 4: skip z when max(d(x,p), d(y,p)) - d(z,p) >= d(x,y);
-                    // by the same triangle inequality also when d(z,p) -
-                    // min(d(x,p), d(y,p)) >= d(x,y).  The stored d(z,p) is an
-                    // upper bound; 1 - 2^-21 of it is a lower bound.
-                    if (!surely_ge(gmt[ce[u]], dzh, dxy_hi) && !surely_ge(dzh * (1.0 - 0x1p-21), gmn[ce[u]], dxy_hi)) {
-                        bool exact = !F32;
-                        if (F32) {
-                            const float *zr = Xhf + z * dp;
-                            float sx = 0.f, sy = 0.f;
-                            for (int cc = 0; cc < dp; cc += 4) {
-                                // Early out every 8 coordinates: adding non-negative
-                                // terms never lowers a rounded sum, so a partial sum
-                                // at or above thi proves the full one is too, and z
-                                // is no witness.  Most candidates end at the first
-                                // check, reading half a 16-D row.
-                                if (cc >= 8 && (cc & 7) == 0 && !(sx < thi && sy < thi)) break;
-                                const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
-                                float a0 = xf[cc] - zv.x, a1 = xf[cc + 1] - zv.y;
-                                float a2 = xf[cc + 2] - zv.z, a3 = xf[cc + 3] - zv.w;
-                                sx = fmaf(a0, a0, sx);
-                                sx = fmaf(a1, a1, sx);
-                                sx = fmaf(a2, a2, sx);
-                                sx = fmaf(a3, a3, sx);
-                                a0 = yf[cc] - zv.x;
-                                a1 = yf[cc + 1] - zv.y;
-                                a2 = yf[cc + 2] - zv.z;
-                                a3 = yf[cc + 3] - zv.w;
-                                sy = fmaf(a0, a0, sy);
-                                sy = fmaf(a1, a1, sy);
-                                sy = fmaf(a2, a2, sy);
-                                sy = fmaf(a3, a3, sy);
-                            }
-                            if (sx < tlo && sy < tlo)
-                                wit = true;
-                            else if (!(sx >= thi || sy >= thi))
-                                exact = true;   // too close to call in float32
-                            nrecheck += exact;
+                for (int u = 0; u < 4; ++u)
+                    ok[u] = ok[u] && !surely_ge(gmt[ce[u]], dzv[u], dxy_hi) &&
+                            !surely_ge(dzv[u] * (1.0 - 0x1p-21), gmn[ce[u]], dxy_hi);
+                // Exact test: on the grid every difference, square and partial
+                // sum is an integer multiple of 2^-2q below 2^53.  The partial
+                // sums are exact lower bounds, so the early out below applies.
+                auto exact_witness = [&](int64_t z) {
+                    const double *zr = Xh + z * dp;
+                    double sx = 0.0, sy = 0.0;
+                    for (int cc = 0; cc < dp; cc += 2) {
+                        if (cc >= 8 && (cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
+                        const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
+                        double e = xs[cc] - zv.x;
+                        sx = fma(e, e, sx);
+                        e = xs[cc + 1] - zv.y;
+                        sx = fma(e, e, sx);
+                        e = ys[cc] - zv.x;
+                        sy = fma(e, e, sy);
+                        e = ys[cc + 1] - zv.y;
+                        sy = fma(e, e, sy);
+                    }
+                    return sx < d2 && sy < d2;
+                };
+                if (F32) {
+                    float4 r0[4], r1[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        r0[u] = r1[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        if (ok[u]) {
+                            const float *zr = Xhf + (int64_t)zz[u] * dp;
+                            r0[u] = *reinterpret_cast<const float4 *>(zr);
+                            if (dp > 4) r1[u] = *reinterpret_cast<const float4 *>(zr + 4);
                         }
-                        if (exact) {
-                            // Exact: on the grid every difference, square and
-                            // partial sum is an integer multiple of 2^-2q below
-                            // 2^53.  The partial sums are exact lower bounds, so
-                            // the same early out applies.
-                            const double *zr = Xh + z * dp;
-                            double sx = 0.0, sy = 0.0;
-                            for (int cc = 0; cc < dp; cc += 2) {
-                                if (cc >= 8 && (cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
-                                const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
-                                double e = xs[cc] - zv.x;
-                                sx = fma(e, e, sx);
-                                e = xs[cc + 1] - zv.y;
-                                sx = fma(e, e, sx);
-                                e = ys[cc] - zv.x;
-                                sy = fma(e, e, sy);
-                                e = ys[cc + 1] - zv.y;
-                                sy = fma(e, e, sy);
-                            }
-                            wit = wit || (sx < d2 && sy < d2);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (!ok[u]) continue;
+                        // Direct-form float32 sums, coordinates 0-7 from the
+                        // registers (zero past dp), the rest from the row.
+                        float sx = 0.f, sy = 0.f, e;
+                        e = xf[0] - r0[u].x; sx = fmaf(e, e, sx);
+                        e = xf[1] - r0[u].y; sx = fmaf(e, e, sx);
+                        e = xf[2] - r0[u].z; sx = fmaf(e, e, sx);
+                        e = xf[3] - r0[u].w; sx = fmaf(e, e, sx);
+                        e = yf[0] - r0[u].x; sy = fmaf(e, e, sy);
+                        e = yf[1] - r0[u].y; sy = fmaf(e, e, sy);
+                        e = yf[2] - r0[u].z; sy = fmaf(e, e, sy);
+                        e = yf[3] - r0[u].w; sy = fmaf(e, e, sy);
+                        if (dp > 4) {
+                            e = xf[4] - r1[u].x; sx = fmaf(e, e, sx);
+                            e = xf[5] - r1[u].y; sx = fmaf(e, e, sx);
+                            e = xf[6] - r1[u].z; sx = fmaf(e, e, sx);
+                            e = xf[7] - r1[u].w; sx = fmaf(e, e, sx);
+                            e = yf[4] - r1[u].x; sy = fmaf(e, e, sy);
+                            e = yf[5] - r1[u].y; sy = fmaf(e, e, sy);
+                            e = yf[6] - r1[u].z; sy = fmaf(e, e, sy);
+                            e = yf[7] - r1[u].w; sy = fmaf(e, e, sy);
                         }
+                        const float *zr = Xhf + (int64_t)zz[u] * dp;
+                        for (int cc = 8; cc < dp; cc += 4) {
+                            // Early out every 8 coordinates: adding non-negative
+                            // terms never lowers a rounded sum, so a partial sum
+                            // at or above thi proves the full one is too, and z
+                            // is no witness.  Most candidates end at the first
+                            // check, reading half a 16-D row.
+                            if ((cc & 7) == 0 && !(sx < thi && sy < thi)) break;
+                            const float4 zv = *reinterpret_cast<const float4 *>(zr + cc);
+                            e = xf[cc] - zv.x; sx = fmaf(e, e, sx);
+                            e = xf[cc + 1] - zv.y; sx = fmaf(e, e, sx);
+                            e = xf[cc + 2] - zv.z; sx = fmaf(e, e, sx);
+                            e = xf[cc + 3] - zv.w; sx = fmaf(e, e, sx);
+                            e = yf[cc] - zv.x; sy = fmaf(e, e, sy);
+                            e = yf[cc + 1] - zv.y; sy = fmaf(e, e, sy);
+                            e = yf[cc + 2] - zv.z; sy = fmaf(e, e, sy);
+                            e = yf[cc + 3] - zv.w; sy = fmaf(e, e, sy);
+                        }
+                        if (sx < tlo && sy < tlo) {
+                            wit = true;
+                        } else if (!(sx >= thi || sy >= thi)) {
+                            ++nrecheck;   // too close to call in float32
+                            wit = wit || exact_witness(zz[u]);
+                        }
+                        ndist += 2;
+                        ++ntests;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (!ok[u]) continue;
+                        wit = wit || exact_witness(zz[u]);
                         ndist += 2;
                         ++ntests;
                     }
