@@ -173,29 +173,48 @@ __global__ void k_inverse(const int32_t *perm, int64_t n, int32_t *inv) {
     if (i < n) inv[perm[i]] = (int32_t)i;
 }
 
-// Single-workgroup exclusive scan: each of 1024 threads owns a contiguous chunk.
+// Single-workgroup exclusive scan in passes of 4096 entries: each thread
+// takes 4 consecutive entries (coalesced loads and stores across the wave),
+// waves scan their sums with shuffles, and the 16 wave totals carry the
+// running offset from pass to pass.
 template <class TI>
 __global__ __launch_bounds__(1024) void k_scan(const TI *in, int64_t n, int64_t *out) {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    const int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
-    int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += (int64_t)in[i];
-    part[t] = s;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t v = t >= o ? part[t - o] : 0;
+    constexpr int kPer = 4;
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += 1024 * kPer) {
+        const int64_t i0 = b0 + (int64_t)t * kPer;
+        int64_t v[kPer], sum = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            v[u] = i0 + u < n ? (int64_t)in[i0 + u] : 0;
+            sum += v[u];
+        }
+        int64_t inc = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t up = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += up;
+        }
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
-        part[t] += v;
-        __syncthreads();
+        int64_t before = 0, total = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t x = wsum[j];
+            before += j < w ? x : 0;
+            total += x;
+        }
+        int64_t run = carry + before + inc - sum;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (i0 + u < n) out[i0 + u] = run;
+            run += v[u];
+        }
+        carry += total;
+        __syncthreads();   // wsum is rewritten by the next pass
     }
-    int64_t run = part[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        out[i] = run;
-        run += (int64_t)in[i];
-    }
-    if (t == 1023) out[n] = part[1023];
+    if (t == 0) out[n] = carry;
 }
 
 __global__ void k_bits_transpose(const uint64_t *rows, int64_t n, int32_t words, int64_t m, uint64_t *cols,

@@ -752,30 +752,39 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
     const double dmax_hi = sqrt_hi(dmax2);
     const double *row = dxp + (int64_t)perm[i] * m;
     int64_t pos = 0;
-    for (int64_t k0 = 0; k0 < m; k0 += 64) {
-        const int64_t k = k0 + lane;
-        bool keep = false;
-        double d2 = INFINITY;
-        if (k < m && gcount[k] > 0) {
-            d2 = row[k];
+    for (int64_t k0 = 0; k0 < m; k0 += 256) {
+        // four groups of 64 cells per pass, their loads in flight together
+        double d2[4], dv[4];
+        int32_t gc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + 64 * u + lane;
+            const bool in = k < m;
+            d2[u] = in ? row[k] : INFINITY;
+            dv[u] = in ? dvor[k] : 0.0;
+            gc[u] = in ? gcount[k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + 64 * u + lane;
             // skip when d(x, p_k) - radius_k >= the row's largest pair distance,
             // tested on squares (d2 is exact; the margin covers the rounding of
             // the right side)
-            const double r = dvor[k] + dmax_hi;
-            keep = !(d2 >= r * r * (1.0 + 1e-12));
-        }
-        const uint64_t bal = __ballot(keep);
-        if (pass == 1 && keep) {
-            const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
-            if (sorted) {
-                key[t] = d2;
-                kid[t] = (int32_t)k;
-            } else {
-                rel_grp[o + t] = (int32_t)k;
-                rel_d2x[o + t] = d2;
+            const double r = dv[u] + dmax_hi;
+            const bool keep = gc[u] > 0 && !(d2[u] >= r * r * (1.0 + 1e-12));
+            const uint64_t bal = __ballot(keep);
+            if (pass == 1 && keep) {
+                const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
+                if (sorted) {
+                    key[t] = d2[u];
+                    kid[t] = (int32_t)k;
+                } else {
+                    rel_grp[o + t] = (int32_t)k;
+                    rel_d2x[o + t] = d2[u];
+                }
             }
+            pos += __popcll(bal);
         }
-        pos += __popcll(bal);
     }
     if (pass == 0) {
         if (lane == 0) rel_cnt[i] = (int32_t)pos;
