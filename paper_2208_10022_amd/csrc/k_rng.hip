@@ -1084,10 +1084,40 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                         ++ntests;
                     }
                 } else {
+                    // float64 rows: the first 4 coordinates of every slot that
+                    // passed Proposition 4 are fetched together (dp >= 4).
+                    double2 q0[4], q1[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        q0[u] = q1[u] = make_double2(0.0, 0.0);
+                        if (ok[u]) {
+                            const double *zr = Xh + (int64_t)zz[u] * dp;
+                            q0[u] = *reinterpret_cast<const double2 *>(zr);
+                            q1[u] = *reinterpret_cast<const double2 *>(zr + 2);
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         if (!ok[u]) continue;
-                        wit = wit || exact_witness(zz[u]);
+                        double sx = 0.0, sy = 0.0, e;
+                        e = xs[0] - q0[u].x; sx = fma(e, e, sx);
+                        e = xs[1] - q0[u].y; sx = fma(e, e, sx);
+                        e = xs[2] - q1[u].x; sx = fma(e, e, sx);
+                        e = xs[3] - q1[u].y; sx = fma(e, e, sx);
+                        e = ys[0] - q0[u].x; sy = fma(e, e, sy);
+                        e = ys[1] - q0[u].y; sy = fma(e, e, sy);
+                        e = ys[2] - q1[u].x; sy = fma(e, e, sy);
+                        e = ys[3] - q1[u].y; sy = fma(e, e, sy);
+                        const double *zr = Xh + (int64_t)zz[u] * dp;
+                        for (int cc = 4; cc < dp; cc += 2) {
+                            if ((cc & 7) == 0 && !(sx < d2 && sy < d2)) break;
+                            const double2 zv = *reinterpret_cast<const double2 *>(zr + cc);
+                            e = xs[cc] - zv.x; sx = fma(e, e, sx);
+                            e = xs[cc + 1] - zv.y; sx = fma(e, e, sx);
+                            e = ys[cc] - zv.x; sy = fma(e, e, sy);
+                            e = ys[cc + 1] - zv.y; sy = fma(e, e, sy);
+                        }
+                        wit = wit || (sx < d2 && sy < d2);
                         ndist += 2;
                         ++ntests;
                     }
