@@ -718,28 +718,30 @@ __global__ void k_pairs_all(int64_t nA, const double *__restrict__ XA, const dou
 // pair (x, y) of x only if d(x, p_c) - radius(c) < max_y d(x, y)
 // (Proposition 3 with the x-side distance alone).  pass 0 counts, pass 1
 // fills the cells sorted by d(x, p_c) ascending with their exact d^2(x, p_c).
-constexpr int kRelSortMax = 4096;   // kept cells sorted in LDS per row (12 bytes each)
+constexpr int kRelSortMax = 4096;   // kept cells sorted in LDS per row (8-byte keys)
+constexpr int kRelThreads = 256;    // threads per row in the writing pass (they share the sort)
 
-__global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, const int32_t *perm,
-                                                        const double *dxp, const double *dvor, const int32_t *gcount,
-                                                        const uint64_t *dmax_bits, const int64_t *rel_off,
-                                                        int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
-                                                        int32_t cap, int pass) {
-    // Pass 0 counts the cells of row point i that may hold a witness of any
-    // of its pairs (Proposition 3 with the row's largest pair distance);
-    // pass 1 writes them, nearest pivot first (a bitonic sort in LDS of
-    // cap entries, a power of two), or in pivot order when there are more
-    // than cap of them (the order only steers the scan, it never changes a
-    // verdict).
+__global__ __launch_bounds__(kRelThreads) void k_relevant_groups(int64_t n, int64_t m, const int32_t *perm,
+                                                                 const double *dxp, const double *dvor,
+                                                                 const int32_t *gcount, const uint64_t *dmax_bits,
+                                                                 const int64_t *rel_off, int32_t *rel_cnt,
+                                                                 int32_t *rel_grp, double *rel_d2x, int32_t cap,
+                                                                 int pass) {
+    // Pass 0 (one wave per row) counts the cells of row point i that may hold
+    // a witness of any of its pairs (Proposition 3 with the row's largest pair
+    // distance); pass 1 writes them, nearest pivot first (a bitonic sort in
+    // LDS of at most cap entries, a power of two, by the whole workgroup), or
+    // in pivot order when there are more than cap of them (the order only
+    // steers the scan, it never changes a verdict).  Sort key: the float32
+    // bits of d^2 (monotone in d^2 for non-negative values) above the cell id.
     extern __shared__ __align__(16) unsigned char smem[];
-    double *key = (double *)smem;
-    int32_t *kid = (int32_t *)(key + cap);
-    const int lane = threadIdx.x;
+    uint64_t *key = (uint64_t *)smem;
+    const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
     const int64_t i = blockIdx.x;
     if (i >= n) return;
     const double dmax2 = __longlong_as_double((long long)dmax_bits[i]);
     if (!(dmax2 > 0.0)) {
-        if (pass == 0 && lane == 0) rel_cnt[i] = 0;
+        if (pass == 0 && tid == 0) rel_cnt[i] = 0;
         return;
     }
     int64_t o = 0, cnt = 0;
@@ -751,73 +753,67 @@ __global__ __launch_bounds__(64) void k_relevant_groups(int64_t n, int64_t m, co
     const bool sorted = cnt <= cap;
     const double dmax_hi = sqrt_hi(dmax2);
     const double *row = dxp + (int64_t)perm[i] * m;
-    int64_t pos = 0;
-    for (int64_t k0 = 0; k0 < m; k0 += 256) {
-        // four groups of 64 cells per pass, their loads in flight together
-        double d2[4], dv[4];
-        int32_t gc[4];
+    if (tid < 64) {
+        int64_t pos = 0;
+        for (int64_t k0 = 0; k0 < m; k0 += 256) {
+            // four groups of 64 cells per pass, their loads in flight together
+            double d2[4], dv[4];
+            int32_t gc[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = k0 + 64 * u + lane;
-            const bool in = k < m;
-            d2[u] = in ? row[k] : INFINITY;
-            dv[u] = in ? dvor[k] : 0.0;
-            gc[u] = in ? gcount[k] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = k0 + 64 * u + lane;
-            // skip when d(x, p_k) - radius_k >= the row's largest pair distance,
-            // tested on squares (d2 is exact; the margin covers the rounding of
-            // the right side)
-            const double r = dv[u] + dmax_hi;
-            const bool keep = gc[u] > 0 && !(d2[u] >= r * r * (1.0 + 1e-12));
-            const uint64_t bal = __ballot(keep);
-            if (pass == 1 && keep) {
-                const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
-                if (sorted) {
-                    key[t] = d2[u];
-                    kid[t] = (int32_t)k;
-                } else {
-                    rel_grp[o + t] = (int32_t)k;
-                    rel_d2x[o + t] = d2[u];
-                }
+            for (int u = 0; u < 4; ++u) {
+                const int64_t k = k0 + 64 * u + lane;
+                const bool in = k < m;
+                d2[u] = in ? row[k] : INFINITY;
+                dv[u] = in ? dvor[k] : 0.0;
+                gc[u] = in ? gcount[k] : 0;
             }
-            pos += __popcll(bal);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t k = k0 + 64 * u + lane;
+                // skip when d(x, p_k) - radius_k >= the row's largest pair
+                // distance, tested on squares (d2 is exact; the margin covers
+                // the rounding of the right side)
+                const double r = dv[u] + dmax_hi;
+                const bool keep = gc[u] > 0 && !(d2[u] >= r * r * (1.0 + 1e-12));
+                const uint64_t bal = __ballot(keep);
+                if (pass == 1 && keep) {
+                    const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (sorted) {
+                        key[t] = ((uint64_t)__float_as_uint((float)d2[u]) << 32) | (uint64_t)(uint32_t)k;
+                    } else {
+                        rel_grp[o + t] = (int32_t)k;
+                        rel_d2x[o + t] = d2[u];
+                    }
+                }
+                pos += __popcll(bal);
+            }
         }
+        if (pass == 0 && lane == 0) rel_cnt[i] = (int32_t)pos;
     }
-    if (pass == 0) {
-        if (lane == 0) rel_cnt[i] = (int32_t)pos;
-        return;
-    }
-    if (!sorted) return;
+    if (pass == 0 || !sorted) return;   // uniform over the workgroup
     int32_t P = 64;
     while (P < cnt) P <<= 1;
-    for (int64_t t = cnt + lane; t < P; t += 64) {
-        key[t] = INFINITY;
-        kid[t] = INT32_MAX;
-    }
+    for (int64_t t = cnt + tid; t < P; t += nt) key[t] = ~0ull;
     __syncthreads();
     for (int32_t size = 2; size <= P; size <<= 1) {
         for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t t = lane; t < (P >> 1); t += 64) {
+            for (int32_t t = tid; t < (P >> 1); t += nt) {
                 const int32_t lo = 2 * t - (t & (stride - 1));
                 const int32_t hi = lo + stride;
                 const bool up = (lo & size) == 0;
-                const double ka = key[lo], kb = key[hi];
-                const int32_t ia = kid[lo], ib = kid[hi];
-                const bool gt = ka > kb || (ka == kb && ia > ib);
-                if (gt == up) {
-                    key[lo] = kb; key[hi] = ka;
-                    kid[lo] = ib; kid[hi] = ia;
+                const uint64_t ka = key[lo], kb = key[hi];
+                if ((ka > kb) == up) {
+                    key[lo] = kb;
+                    key[hi] = ka;
                 }
             }
             __syncthreads();
         }
     }
-    for (int64_t t = lane; t < cnt; t += 64) {
-        rel_grp[o + t] = kid[t];
-        rel_d2x[o + t] = key[t];
+    for (int64_t t = tid; t < cnt; t += nt) {
+        const int32_t k = (int32_t)(uint32_t)key[t];
+        rel_grp[o + t] = k;
+        rel_d2x[o + t] = row[k];   // the exact value, not the float32 key
     }
 }
 
@@ -1260,13 +1256,13 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
     require(n <= 0x7fffffffLL, GRNG_EINVAL, "too many points for the witness-cell pass");
     int32_t cap = 64;   // sort capacity: the layer size rounded up to a power of two, at most kRelSortMax
     while (cap < m && cap < kRelSortMax) cap <<= 1;
-    const size_t lds = (size_t)cap * (sizeof(double) + sizeof(int32_t));
+    const size_t lds = (size_t)cap * sizeof(uint64_t);
     if (rel_off == nullptr) {
         k_relevant_groups<<<(unsigned)n, 64, 0, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
                                                      nullptr, nullptr, cap, 0);
     } else {
-        k_relevant_groups<<<(unsigned)n, 64, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt,
-                                                       rel_grp, rel_d2x, cap, 1);
+        k_relevant_groups<<<(unsigned)n, kRelThreads, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off,
+                                                                rel_cnt, rel_grp, rel_d2x, cap, 1);
     }
     GRNG_LAUNCHED();
 }
