@@ -180,6 +180,13 @@ __device__ inline uint64_t parents_mask(const int64_t *__restrict__ par_off, con
 // rows and pivot distances are dead, and D(U,U) reuses them.  D(T,T) has
 // bytes of its own when they fit, so that it is kept while consecutive tile
 // pairs share T (the list is sorted by T); otherwise it reuses them too.
+// The Stage V witness matrices D(T,T) and D(U,U) hold float32 entries, or
+// 16-bit upper bounds (h16) where that halves their bytes enough for two
+// workgroups per CU.
+constexpr int kDh = kTile + 2;   // row stride (16-bit entries) of the 16-bit witness matrices
+__host__ __device__ inline size_t pairs_wmat_bytes(bool h16) {
+    return h16 ? 2 * (size_t)kTile * kDh : 4 * (size_t)kTile * kDl;
+}
 __host__ __device__ inline size_t pairs_lds_phase_a(int dp) {
     return 8 * (size_t)kPiv * (dp + 1) + 4 * 2 * (size_t)kTile * kXs;
 }
@@ -187,14 +194,29 @@ __host__ __device__ inline size_t pairs_lds_fixed(int dp) {
     const size_t ld = (size_t)dp + 1;
     return 8 * (2 * kTile * ld + 2 * kTile + kPiv + 3 * kTile) + 4 * (size_t)kTile * kDl;
 }
-__host__ __device__ inline bool pairs_keep_tt(int dp) {
-    const size_t dmat = 4 * (size_t)kTile * kDl, pa = pairs_lds_phase_a(dp);
+__host__ __device__ inline bool pairs_keep_tt(int dp, bool h16) {
+    const size_t dmat = pairs_wmat_bytes(h16), pa = pairs_lds_phase_a(dp);
     return pairs_lds_fixed(dp) + dmat + (pa > dmat ? pa : dmat) <= 160 * 1024 - 256;
 }
-__host__ __device__ inline size_t pairs_lds_bytes(int dp) {
-    const size_t dmat = 4 * (size_t)kTile * kDl, pa = pairs_lds_phase_a(dp);
-    return pairs_lds_fixed(dp) + (pairs_keep_tt(dp) ? dmat + (pa > dmat ? pa : dmat) : (pa > 2 * dmat ? pa : 2 * dmat));
+__host__ __device__ inline size_t pairs_lds_bytes(int dp, bool h16) {
+    const size_t dmat = pairs_wmat_bytes(h16), pa = pairs_lds_phase_a(dp);
+    return pairs_lds_fixed(dp) +
+           (pairs_keep_tt(dp, h16) ? dmat + (pa > dmat ? pa : dmat) : (pa > 2 * dmat ? pa : 2 * dmat));
 }
+// Two 8-wave workgroups per CU need each at most half of the 160 KiB of LDS
+// (allocated in 512-byte granules, with the kernel's static bytes).
+inline bool pairs_two_per_cu(size_t lds) { return 2 * ((lds + 64 + 511) / 512 * 512) <= 160 * 1024; }
+
+// Witness-matrix entries: float32, or the upper 16 bits of the float32 bit
+// pattern rounded up (an upper bound with 8 significant bits; non-negative
+// values only, whose bit patterns order as unsigned integers).
+__device__ inline void put_wmat(float *p, double v) { *p = (float)v; }
+__device__ inline void put_wmat(uint16_t *p, double v) {
+    const uint32_t b = __float_as_uint(__double2float_ru(v));
+    *p = (uint16_t)((b + 0xffffu) >> 16);
+}
+__device__ inline float get_wmat(const float *p) { return *p; }
+__device__ inline float get_wmat(const uint16_t *p) { return __uint_as_float((uint32_t)*p << 16); }
 
 // Rows [0, rows) of a tile into LDS (row stride ld doubles), zero rows past
 // len; spread over nthr threads (t = this thread's index among them), four
@@ -238,10 +260,10 @@ constexpr int kPairWaves = kPairThreads / 64;
 // One wave, NB independent 16x16 blocks of |a_i - b_j|^2 at once: exact f64
 // MFMA results rounded to nearest float32 (the MFMA chains interleave, so the
 // matrix unit is not idle on dependences).
-template <int NB>
+template <int NB, typename OT>
 __device__ inline void dist_blocks(const double *const sa[NB], const double *const na[NB], const double *const sb[NB],
                                    const double *const nb[NB], const int r0[NB], const int c0[NB], int dp, int ld,
-                                   float *const D[NB], const int dld[NB]) {
+                                   OT *const D[NB], const int dld[NB]) {
     const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
     v4d acc[NB];
 #pragma unroll
@@ -260,7 +282,7 @@ __device__ inline void dist_blocks(const double *const sa[NB], const double *con
     for (int q = 0; q < NB; ++q)
         for (int r = 0; r < 4; ++r) {
             const int i = r0[q] + 4 * r + kl, j = c0[q] + il;
-            D[q][i * dld[q] + j] = (float)(na[q][i] + nb[q][j] - 2.0 * acc[q][r]);
+            put_wmat(&D[q][i * dld[q] + j], na[q][i] + nb[q][j] - 2.0 * acc[q][r]);
         }
 }
 
@@ -335,6 +357,7 @@ __global__ __launch_bounds__(256) void k_pair_masks(int64_t tp0, int64_t n, cons
     }
 }
 
+template <typename WT>   // witness-matrix entry: float, or uint16_t upper bounds
 __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs_tiled(
     int64_t ntp, const uint64_t *__restrict__ rec, const double *__restrict__ XA, const double *__restrict__ nrmA,
     const double *__restrict__ XB, const double *__restrict__ nrmB, int mode, int dp, int32_t K,
@@ -350,12 +373,16 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     double *nX = sY + kTile * ld, *nY = nX + kTile, *nP = nY + kTile;
     uint64_t *mX = (uint64_t *)(nP + kPiv), *mY = mX + kTile, *surv = mY + kTile;
     float *DTU = (float *)(surv + kTile);
-    float *region = DTU + kTile * kDl;
-    const bool keep_tt = pairs_keep_tt(dp);
-    float *DTT = region, *region2 = keep_tt ? region + kTile * kDl : region;
+    constexpr bool h16 = sizeof(WT) == 2;
+    constexpr int wld = h16 ? kDh : kDl;   // row stride of D(T,T) and D(U,U)
+    const size_t wbytes = pairs_wmat_bytes(h16);
+    unsigned char *region = (unsigned char *)(DTU + kTile * kDl);
+    const bool keep_tt = pairs_keep_tt(dp, h16);
+    WT *DTT = (WT *)region;
+    unsigned char *region2 = keep_tt ? region + wbytes : region;
     double *sP = (double *)region2;
     float *XP = (float *)(sP + kPiv * ld), *YP = XP + kTile * kXs;
-    float *DUU = keep_tt ? region2 : region + kTile * kDl;
+    WT *DUU = (WT *)(keep_tt ? region2 : region + wbytes);
     int32_t tt_start = -1, sx_start = -1;   // tiles whose D(T,T) / rows are in LDS (block-uniform)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool self = (mode & PM_SELF) != 0;
@@ -379,8 +406,10 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         // wave-uniform from here on: the record head is read by scalar loads
         const uint64_t *rc = rec + tp * kPairRecWords;
         const uint64_t m0 = rc[0], m1 = rc[1], m2 = rc[2];
-        const int32_t sT = (int32_t)m0, lT = (int32_t)(m0 >> 32), a = (int32_t)m1;
-        const int32_t lU = (int32_t)(m1 >> 32), sU = (int32_t)m2, b = (int32_t)(m2 >> 32);
+        // (the two home cells, in the low half of m1 and the high half of m2,
+        // are not needed here)
+        const int32_t sT = (int32_t)m0, lT = (int32_t)(m0 >> 32);
+        const int32_t lU = (int32_t)(m1 >> 32), sU = (int32_t)m2;
         // 1. candidate masks and norms (waves 6, 7), rows of T (threads
         // 0-255) and U (256-511), pivot rows (wave 5).
         if (w == 6) {
@@ -423,7 +452,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             const int c0[3] = {0, (id0 & 3) * 16, (id1 & 3) * 16};
             float *D[3] = {ys ? YP : XP, DTU, DTU};
             const int dld[3] = {kXs, kDl, kDl};
-            dist_blocks<3>(sa, na, sb, nb, r0, c0, dp, ld, D, dld);
+            dist_blocks<3, float>(sa, na, sb, nb, r0, c0, dp, ld, D, dld);
             if ((lane & 15) >= K) {   // unused pivot slots never witness
                 float *Pd = ys ? YP : XP;
                 for (int r = 0; r < 4; ++r) Pd[(pr + 4 * r + (lane >> 4)) * kXs + (lane & 15)] = INFINITY;
@@ -493,8 +522,8 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             const bool us = !need_tt || w >= 4;
             const int nh = need_tt ? 2 : 1;
             const double *sa[2], *na[2];
-            int r0[2], c0[2], dld[2] = {kDl, kDl};
-            float *D[2];
+            int r0[2], c0[2], dld[2] = {wld, wld};
+            WT *D[2];
             for (int h = 0; h < nh; ++h) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
@@ -505,18 +534,19 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                     c0[q] = (id & 3) * 16;
                     D[q] = us ? DUU : DTT;
                 }
-                dist_blocks<2>(sa, na, sa, na, r0, c0, dp, ld, D, dld);
+                dist_blocks<2, WT>(sa, na, sa, na, r0, c0, dp, ld, D, dld);
             }
         }
         __syncthreads();
         // 3. Stage V: each wave walks rows w, w+8, ...; every Stage IV survivor
         // (i, j) is tested against the points of T and U, one lane per witness
-        // z, with the float32 certificate above.
+        // z, with the float32 certificate above (16-bit witness-matrix entries
+        // are upper bounds of the exact values, so a kill stays a proof).
         for (int i = w; i < lT; i += kPairWaves) {
             uint64_t row = surv[i];
             if (!row) continue;
             // the x side of every test of this row, once per row
-            const float ax = (self && lane < lT) ? DTT[i * kDl + lane] : INFINITY;
+            const float ax = (self && lane < lT) ? get_wmat(&DTT[i * wld + lane]) : INFINITY;
             const float au = lane < lU ? DTU[i * kDl + lane] : INFINITY;
             double rmax = -1.0;
             while (row) {
@@ -524,7 +554,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                 row &= row - 1;
                 const float t = DTU[i * kDl + j] * kCertain;
                 const float by = (self && lane < lT) ? DTU[lane * kDl + j] : INFINITY;
-                const float bu = lane < lU ? DUU[j * kDl + lane] : INFINITY;
+                const float bu = lane < lU ? get_wmat(&DUU[j * wld + lane]) : INFINITY;
                 if (__ballot((ax < t && by < t) || (au < t && bu < t))) continue;   // max(., .) < t
                 // survivor: exact d^2, the dot product spread over the lanes
                 // (every partial sum is exact, so the order does not matter)
@@ -1228,15 +1258,23 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const d
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the pair kernel");
     require(K >= 1 && K <= kPiv, GRNG_EINVAL, "Stage IV pivot count out of range");
     launch_fill_u64(s, work, kXcds * kWorkStride, 0ull);
-    const size_t lds = pairs_lds_bytes(dp);
+    // 16-bit witness matrices only where they make room for a second
+    // workgroup per CU (32-D rows, for instance): they cost some Stage V
+    // kills (8 significant bits), which then go to the exhaustive scan.
+    const bool h16 = !pairs_two_per_cu(pairs_lds_bytes(dp, false)) && pairs_two_per_cu(pairs_lds_bytes(dp, true));
+    const size_t lds = pairs_lds_bytes(dp, h16);
     require(lds <= 160 * 1024, GRNG_EINVAL, "dimension too large for the pair kernel's LDS tiles");
-    if (lds > 64 * 1024)
-        GRNG_HIP(hipFuncSetAttribute((const void *)k_pairs_tiled, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds));
+    const void *fn = h16 ? (const void *)k_pairs_tiled<uint16_t> : (const void *)k_pairs_tiled<float>;
+    if (lds > 64 * 1024) GRNG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(ntp, kPairChunk), 256 * 4));
-    k_pairs_tiled<<<(unsigned)grid, kPairThreads, lds, s>>>(ntp, rec, XA, nrmA, XB, nrmB, mode, dp, K, Xp, nrmp,
-                                                   out, (unsigned long long *)dmax_bits, (unsigned long long *)work,
-                                                   (unsigned long long *)counters);
+    if (h16)
+        k_pairs_tiled<uint16_t><<<(unsigned)grid, kPairThreads, lds, s>>>(
+            ntp, rec, XA, nrmA, XB, nrmB, mode, dp, K, Xp, nrmp, out, (unsigned long long *)dmax_bits,
+            (unsigned long long *)work, (unsigned long long *)counters);
+    else
+        k_pairs_tiled<float><<<(unsigned)grid, kPairThreads, lds, s>>>(
+            ntp, rec, XA, nrmA, XB, nrmB, mode, dp, K, Xp, nrmp, out, (unsigned long long *)dmax_bits,
+            (unsigned long long *)work, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
