@@ -64,8 +64,8 @@ typedef enum grng_status {
 /* Arithmetic of the exhaustive witness scan (Section 2, Stage VI), where most
  * witness tests are spent.  Every kept/eliminated decision is exact in all
  * modes; the pivot and in-tile certificates before the scan always compare
- * float32 roundings of exact float64 tiles and only eliminate on a proven
- * witness. */
+ * float32 roundings (or upper bounds) of exact float64 tiles and only
+ * eliminate on a proven witness. */
 enum {
     GRNG_PREC_FP64 = 0, /* exact float64 squared distance for every witness test */
     GRNG_PREC_FP32 = 1, /* float32 rows with an error-bounded screen; undecided tests are recomputed in float64 */
