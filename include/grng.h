@@ -108,7 +108,8 @@ typedef struct grng_stats {
     int64_t tile_pairs;           /* 64-point tile pairs scanned for candidate pairs */
     int64_t vgrng_pivots;         /* Proposition 1 witness pivots per block used by the last build */
     int64_t stage4_pivots;        /* Stage IV pivot witnesses used by the last build */
-    int64_t reserved_i[1];
+    int64_t unsorted_cell_rows;   /* rows of the last build whose witness-cell list was longer than the
+                                     4,096 entries sorted on chip, and was scanned in pivot order */
     double distance_computations; /* squared distances produced (the paper's cost unit, Section 1) */
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */

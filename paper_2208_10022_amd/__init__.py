@@ -43,7 +43,7 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_edges", C.c_int64), ("n_layers", C.c_int64), ("orphans", C.c_int64),
                 ("tile_pairs", C.c_int64), ("vgrng_pivots", C.c_int64), ("stage4_pivots", C.c_int64),
-                ("reserved_i", C.c_int64 * 1),
+                ("unsorted_cell_rows", C.c_int64),
                 ("distance_computations", C.c_double), ("witness_tests", C.c_double),
                 ("candidate_pairs", C.c_double), ("stage4_survivors", C.c_double),
                 ("exhaustive_pairs", C.c_double), ("lune_tests", C.c_double), ("rechecks", C.c_double),

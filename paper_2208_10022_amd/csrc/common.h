@@ -175,6 +175,7 @@ enum Counter {
     C_LUNE,           // witness predicates evaluated by the exhaustive scan
     C_TPV,            // tile pairs that reached Stage V (D(U,U) computed)
     C_TTV,            // D(T,T) computations (not repeated while consecutive tile pairs share T)
+    C_UNSORTED,       // rows whose witness-cell list exceeded the sort capacity
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,
@@ -365,7 +366,8 @@ void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double 
                       const double *nrmB, int dp, bool self, PairList out, uint64_t *counters);
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
-                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x);
+                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
+                            uint64_t *counters);
 void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,

@@ -660,7 +660,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     rel_cnt.alloc(4 * (size_t)n);
     rel_off.alloc(8 * (size_t)(n + 1));
     launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
-                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr);
+                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr, ctr);
     launch_scan_i32_to_i64(s, rel_cnt.as<int32_t>(), n, rel_off.as<int64_t>());
     std::vector<int64_t> tot;
     d2h(tot, rel_off.as<int64_t>() + n, 1, s);
@@ -668,7 +668,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     rel_d2x.alloc(8 * (size_t)std::max<int64_t>(tot[0], 1));
     launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
                            dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(),
-                           rel_d2x.as<double>());
+                           rel_d2x.as<double>(), ctr);
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
     const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
@@ -720,6 +720,7 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.ms_pair_masks = bt.masks;
     idx->stats.ms_lune = bt.lune;
     idx->stats.tile_pairs = bt.tile_pairs;
+    idx->stats.unsorted_cell_rows = (int64_t)c[C_UNSORTED];
     idx->stats.vgrng_pivots = idx->layers.empty() ? 0 : vgrng_pivots(idx, idx->layers.back().m);
     idx->stats.stage4_pivots = idx->layers.empty() ? 0 : stage4_pivots(idx);
     idx->stats.ms_autotune = idx->ms_tune;

@@ -756,7 +756,7 @@ __global__ __launch_bounds__(kRelThreads) void k_relevant_groups(int64_t n, int6
                                                                  const int32_t *gcount, const uint64_t *dmax_bits,
                                                                  const int64_t *rel_off, int32_t *rel_cnt,
                                                                  int32_t *rel_grp, double *rel_d2x, int32_t cap,
-                                                                 int pass) {
+                                                                 int pass, unsigned long long *counters) {
     // Pass 0 (one wave per row) counts the cells of row point i that may hold
     // a witness of any of its pairs (Proposition 3 with the row's largest pair
     // distance); pass 1 writes them, nearest pivot first (a bitonic sort in
@@ -781,6 +781,7 @@ __global__ __launch_bounds__(kRelThreads) void k_relevant_groups(int64_t n, int6
         if (cnt == 0) return;
     }
     const bool sorted = cnt <= cap;
+    if (pass == 1 && !sorted && tid == 0) atomicAdd(&counters[C_UNSORTED], 1ull);
     const double dmax_hi = sqrt_hi(dmax2);
     const double *row = dxp + (int64_t)perm[i] * m;
     if (tid < 64) {
@@ -1289,7 +1290,8 @@ void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double 
 
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
-                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x) {
+                            const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
+                            uint64_t *counters) {
     if (n == 0) return;
     require(n <= 0x7fffffffLL, GRNG_EINVAL, "too many points for the witness-cell pass");
     int32_t cap = 64;   // sort capacity: the layer size rounded up to a power of two, at most kRelSortMax
@@ -1297,10 +1299,11 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
     const size_t lds = (size_t)cap * sizeof(uint64_t);
     if (rel_off == nullptr) {
         k_relevant_groups<<<(unsigned)n, 64, 0, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
-                                                     nullptr, nullptr, cap, 0);
+                                                     nullptr, nullptr, cap, 0, (unsigned long long *)counters);
     } else {
         k_relevant_groups<<<(unsigned)n, kRelThreads, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off,
-                                                                rel_cnt, rel_grp, rel_d2x, cap, 1);
+                                                                rel_cnt, rel_grp, rel_d2x, cap, 1,
+                                                                (unsigned long long *)counters);
     }
     GRNG_LAUNCHED();
 }

@@ -244,6 +244,28 @@ def test_clustered_full_size_sampled_rows(G):
     assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
 
 
+def test_witness_cells_beyond_the_sort_capacity(G):
+    """4,500 pivots and one far outlier: the outlier's pairs are long, so every
+    cell may hold a witness for them and its cell list (more than the 4,096
+    entries sorted in LDS) is scanned in pivot order.  Sampled rows, the
+    outlier's among them, equal the oracle's."""
+    say("4500 pivots with a far outlier n=12001 d=3")
+    W = synth.clustered(n=12000, d=3, clusters=6, m=4500, knn=8, sub=21)
+    X = np.vstack([W.X, np.full((1, 3), 25.0, np.float32)])   # 25 * 2^19 < 2^24: on the grid
+    pid = W.layers[0].pivot_ids
+    rad = synth.knn_radii(X, W.q, pid, 8)
+    E, _, st = gpu_edges(G, X, W.q, [(pid, rad)])
+    say("stats", st)
+    assert st["unsorted_cell_rows"] > 0   # the pivot-order path ran
+    g = np.random.default_rng(5)
+    xs = np.concatenate([[X.shape[0] - 1], g.choice(W.n, 12, replace=False)])
+    rows = native.rng_rows(X, W.q, xs)
+    assert len(rows[0]) > 0
+    for x, row in zip(xs, rows):
+        got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
+        assert np.array_equal(got, row), x
+
+
 def test_float32_screen_redecides_exact_ties(G):
     """3-4-5 triangles A=(0,0), B=(5,0), C=(3,4) far apart: for the pair
     (A, B) the point C sits exactly on the lune boundary (d(A,C) = d(A,B) = 5),
