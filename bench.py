@@ -61,6 +61,40 @@ def measured_traffic(kernel: str, workload: str):
 PAIR_RECORD_BYTES = 8 * (12 + 2 * 64)   # tile bounds, pivot ids and the two candidate-mask vectors
 
 
+def attainable_peaks(torch) -> dict:
+    """Attainable roofs on this device, beside the published ones: a 4 GiB
+    device-to-device copy (bytes read + written per second, best of 5) and a
+    float64 8192^3 library GEMM (best of 5)."""
+    out = {}
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(6):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    out["copy_gb_s"] = 2 * nbytes / (best / 1e3) / 1e9
+    out["hbm_peak_gb_s"] = MI355X_HBM_GBS
+    del src, dst
+    n = 8192
+    a = torch.rand(n, n, dtype=torch.float64, device="cuda:0")
+    b = torch.rand(n, n, dtype=torch.float64, device="cuda:0")
+    best = float("inf")
+    for _ in range(6):
+        ev[0].record()
+        torch.matmul(a, b)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    out["dgemm_tflop_s"] = 2 * n ** 3 / (best / 1e3) / 1e12
+    out["fp64_mfma_peak_tflop_s"] = MI355X_FP64_TFLOPS
+    return out
+
+
 def kernel_rooflines(st: dict) -> dict:
     """Per main kernel of the last build: time and achieved fraction of its roof.
 
@@ -135,6 +169,8 @@ def parse():
                          "three-layer build (100 coarse, 3,000 fine pivots)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
+    ap.add_argument("--attainable", action="store_true",
+                    help="only measure attainable peaks: device copy bandwidth and a float64 library GEMM")
     return ap.parse_args()
 
 
@@ -205,6 +241,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_mib": args.copy_calibration_mb, "copies": 3}))
+        return
+
+    if args.attainable:
+        print(json.dumps(attainable_peaks(torch)))
         return
 
     import synth
