@@ -286,9 +286,9 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     const int32_t *__restrict__ home, const int32_t *__restrict__ wknn, int32_t kw, int64_t xbase,
     const float *__restrict__ ax, uint64_t *__restrict__ g_rows, uint64_t *__restrict__ v_rows,
     unsigned long long *counters) {
-    __shared__ float sA[kVT_X][kVT_K + 1];
-    __shared__ float sD[kVT_K][kVT_J];
-    __shared__ float sV[kVT_K][kVT_J];
+    __shared__ __align__(16) float sA[kVT_X][kVT_K + 2];   // rows 8-byte aligned: pairs of k in one load
+    __shared__ __align__(16) float sD[kVT_K][kVT_J];
+    __shared__ __align__(16) float sV[kVT_K][kVT_J];
     __shared__ int32_t sK[kVT_K];
     __shared__ uint64_t sCand[kVT_X];
     __shared__ unsigned long long sG[kVT_X], sVb[kVT_X];
@@ -343,13 +343,19 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         __syncthreads();
 #pragma unroll 2
         for (int kk = 0; kk < kVT_K; kk += 2) {
+            // a thread's four columns are adjacent: one 16-byte load per row of
+            // D and V, one 8-byte load per point row for two witnesses
             uint32_t a[2][4], d[2][4], v[2][4];
+            for (int r = 0; r < 4; ++r) {
+                const uint2 t = *reinterpret_cast<const uint2 *>(&sA[ty + 16 * r][kk]);
+                a[0][r] = t.x;
+                a[1][r] = t.y;
+            }
             for (int h = 0; h < 2; ++h) {
-                for (int r = 0; r < 4; ++r) a[h][r] = __float_as_uint(sA[ty + 16 * r][kk + h]);
-                for (int c = 0; c < 4; ++c) {
-                    d[h][c] = __float_as_uint(sD[kk + h][tx + 16 * c]);
-                    v[h][c] = __float_as_uint(sV[kk + h][tx + 16 * c]);
-                }
+                const uint4 td = *reinterpret_cast<const uint4 *>(&sD[kk + h][4 * tx]);
+                const uint4 tv = *reinterpret_cast<const uint4 *>(&sV[kk + h][4 * tx]);
+                d[h][0] = td.x; d[h][1] = td.y; d[h][2] = td.z; d[h][3] = td.w;
+                v[h][0] = tv.x; v[h][1] = tv.y; v[h][2] = tv.z; v[h][3] = tv.w;
             }
             for (int r = 0; r < 4; ++r)
                 for (int c = 0; c < 4; ++c) {
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         if (i >= n) continue;
         const double *row = dxp + (int64_t)perm[i] * m;
         for (int c = 0; c < 4; ++c) {
-            const int jc = tx + 16 * c;
+            const int jc = 4 * tx + c;
             const int64_t j = j0 + jc;
             if (j >= m) continue;
             const double dj = sqrt(row[j]) * (1.0 - 1e-15);
