@@ -908,6 +908,11 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const double g32 = (double)(dp + 8) * 0x1p-24;
     const bool xself = Xx == Xh;   // x is a point of the scanned set (not a query)
     int64_t cur = 0, cend = 0;   // the wave's claimed chunk (uniform)
+    // The first 64 cells of row point cx, held per lane: consecutive pairs of
+    // a wave mostly share their row point (the list is sorted by it).
+    int64_t cx = -1;
+    int32_t cg = 0;
+    double cd2x = 0.0, csx = 0.0, cnp = 0.0, cdv = 0.0;
     for (;;) {
         if (cur >= cend) {
             int64_t b = -1, e = -1;
@@ -937,19 +942,30 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             int32_t z0 = 0, nmem = 0;
             float key = -INFINITY;
             if (c < r1) {
-                const int32_t g = rel_grp[c];
-                const double d2x = rel_d2x[c];
-                const double d2y = nry + nrmp[g] - 2.0 * dot_lds(ys, Xp + (int64_t)g * dp, dp);
+                const bool hit = c0 == r0 && x == cx;
+                const int32_t g = hit ? cg : rel_grp[c];
+                const double d2x = hit ? cd2x : rel_d2x[c];
+                const double npg = hit ? cnp : nrmp[g];
+                const double dvg = hit ? cdv : dvor[g];
+                const double sxg = hit ? csx : sqrt(d2x);
+                if (c0 == r0 && !hit) {
+                    cg = g;
+                    cd2x = d2x;
+                    cnp = npg;
+                    cdv = dvg;
+                    csx = sxg;
+                }
+                const double d2y = nry + npg - 2.0 * dot_lds(ys, Xp + (int64_t)g * dp, dp);
                 ++ndist;
                 ++ntests;
                 // Stage IV: the cell's pivot itself as a witness (exact); not
                 // when only part of each cell may witness (zstart given).
                 if (!zstart && d2x < d2 && d2y < d2) dead = true;
-                const double dxl = sqrt_lo(d2x), dyl = sqrt_lo(d2y);
+                const double dxl = sxg * (1.0 - 1e-15), dyl = sqrt_lo(d2y);
                 gmax = fmax(dxl, dyl);
-                gmin = fmin(sqrt_hi(d2x), sqrt_hi(d2y));
+                gmin = fmin(sxg * (1.0 + 1e-15), sqrt_hi(d2y));
                 // Proposition 3: skip the cell when it lies wholly outside the lune.
-                scan = !surely_ge(gmax, dvor[g], dxy_hi);
+                scan = !surely_ge(gmax, dvg, dxy_hi);
                 if (lune_order) key = (float)(-gmax);   // nearest to both ends first
                 if (scan) {
                     z0 = zstart ? zstart[g] : grp_off[g];
@@ -963,6 +979,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                     }
                 }
             }
+            if (c0 == r0) cx = x;
             if (__ballot(dead)) { dead = true; break; }
             if (!__ballot(scan && nmem > 0)) continue;
             // Visit order: chunk order (cells sorted by distance to x), or by
