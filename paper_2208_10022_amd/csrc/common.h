@@ -302,7 +302,7 @@ void launch_relative_parents(hipStream_t s, int64_t mc, const int32_t *coarse_po
 void launch_guided_candidates(hipStream_t s, int64_t mf, const uint64_t *parent_bits, int32_t cwords,
                               const uint64_t *coarse_bits, int64_t mc, uint64_t *cand_bits, int32_t fwords);
 void launch_point_pass1(hipStream_t s, int64_t n, int64_t m, const double *dxp, const double *rad,
-                        int32_t *home, double *d2home, int32_t *npar);
+                        int32_t *home, double *d2home, int32_t *npar, int32_t *second);
 void launch_group_radius(hipStream_t s, int64_t n, const int32_t *home, const double *d2home,
                          uint64_t *d2vor_bits, int32_t *gcount);
 void launch_parents(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const double *rad,

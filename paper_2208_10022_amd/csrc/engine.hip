@@ -374,8 +374,11 @@ void prepare_aux(grng_index *idx, const Layer &L, LayerAux &aux) {
 //     groups (cell radii, sizes) and the shifted pivot tables in aux are filled.
 //   cells != nullptr: P is a query set; cell radii and sizes come from `cells`.
 // is_new (host, optional): per input index, 1 for points inserted in this batch.
+// locality: inside a home cell, group the points by their second-nearest
+// pivot (a full build only: insertion needs each cell's old points first).
 void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double *X, const double *nrm, int64_t n,
-                    const PointState *cells, const std::vector<uint8_t> *is_new, PointState &P, BuildTimes &bt) {
+                    const PointState *cells, const std::vector<uint8_t> *is_new, PointState &P, BuildTimes &bt,
+                    bool locality = false) {
     hipStream_t s = idx->stream;
     const int64_t m = L.m;
     const int dp = idx->dp;
@@ -387,26 +390,43 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     P.dxp.alloc(sizeof(double) * (size_t)(n * m));
     launch_dist2(s, X, nrm, n, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, P.dxp.as<double>(), m, true);
     // A2: parent counts, home cell, cell radius.
-    DevBuf home, d2home, npar, d2vor, gcount;
+    DevBuf home, d2home, npar, d2vor, gcount, second;
     home.alloc(4 * (size_t)n);
     d2home.alloc(8 * (size_t)n);
     npar.alloc(4 * (size_t)n);
+    if (locality) second.alloc(4 * (size_t)n);
     launch_point_pass1(s, n, m, P.dxp.as<double>(), L.rad.as<double>(), home.as<int32_t>(), d2home.as<double>(),
-                       npar.as<int32_t>());
+                       npar.as<int32_t>(), locality ? second.as<int32_t>() : nullptr);
     std::vector<int32_t> h_home, h_npar, h_gcount((size_t)m, 0);
     std::vector<double> h_d2home, h_d2vor((size_t)m, 0.0);
     d2h(h_home, home.p, (size_t)n, s);
     trace("pivot distances and home cells", 0.0, n * m);
     d2h(h_npar, npar.p, (size_t)n, s);
     if (indexed) d2h(h_d2home, d2home.p, (size_t)n, s);
-    // Home order: stable counting sort by home cell (host, O(n)).
+    // Home order: stable counting sort by home cell (host, O(n)), after one by
+    // the second-nearest pivot when asked, so that a 64-point tile of a cell
+    // faces fewer neighbouring cells.
+    std::vector<int32_t> order((size_t)n);
+    if (locality) {
+        std::vector<int32_t> h_second;
+        d2h(h_second, second.p, (size_t)n, s);
+        std::vector<int64_t> at((size_t)m + 1, 0);
+        for (int64_t x = 0; x < n; ++x) ++at[(size_t)h_second[x] + 1];
+        for (int64_t c = 0; c < m; ++c) at[c + 1] += at[c];
+        for (int64_t x = 0; x < n; ++x) order[at[h_second[x]]++] = (int32_t)x;
+    } else {
+        for (int64_t x = 0; x < n; ++x) order[x] = (int32_t)x;
+    }
     for (int64_t x = 0; x < n; ++x) ++h_gcount[h_home[x]];
     P.h_off.assign((size_t)m + 1, 0);
     for (int64_t c = 0; c < m; ++c) P.h_off[c + 1] = P.h_off[c] + h_gcount[c];
     P.h_perm.resize((size_t)n);
     {
         std::vector<int32_t> pos(P.h_off.begin(), P.h_off.end() - 1);
-        for (int64_t x = 0; x < n; ++x) P.h_perm[pos[h_home[x]]++] = (int32_t)x;
+        for (int64_t t = 0; t < n; ++t) {
+            const int32_t x = order[t];
+            P.h_perm[pos[h_home[x]]++] = x;
+        }
     }
     std::vector<int32_t> home_h((size_t)n);
     std::vector<int64_t> par_off((size_t)n + 1, 0);
@@ -700,7 +720,7 @@ void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &ed
                       ExhaustiveState &ex) {
     const Layer &L = idx->layers.back();
     prepare_aux(idx, L, aux);
-    prepare_points(idx, L, aux, idx->X.as<double>(), idx->nrm.as<double>(), idx->n, nullptr, nullptr, ps, bt);
+    prepare_points(idx, L, aux, idx->X.as<double>(), idx->nrm.as<double>(), idx->n, nullptr, nullptr, ps, bt, true);
     Pairs P;
     DevBuf dmax, alive;
     int64_t np = 0;

@@ -172,29 +172,41 @@ __global__ void k_guided_candidates(int64_t mf, const uint64_t *pbits, int32_t c
 
 // Wave per point (original order): parent count, nearest pivot, its distance^2.
 __global__ __launch_bounds__(256) void k_point_pass1(int64_t n, int64_t m, const double *dxp, const double *rad,
-                                                     int32_t *home, double *d2home, int32_t *npar) {
+                                                     int32_t *home, double *d2home, int32_t *npar, int32_t *second) {
     const int lane = threadIdx.x & 63;
     const int64_t x = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (x >= n) return;
     int cnt = 0;
-    double best = INFINITY;
-    int64_t bk = m;
+    double best = INFINITY, best2 = INFINITY;   // nearest and second-nearest pivot
+    int64_t bk = m, bk2 = m;
     for (int64_t k = lane; k < m; k += 64) {
         const double d2 = dxp[x * m + k];
         const double r = rad[k];
         if (d2 <= r * r) ++cnt;   // exact: r*r is exact on the grid
-        if (d2 < best) { best = d2; bk = k; }
+        if (d2 < best) {
+            best2 = best; bk2 = bk;
+            best = d2; bk = k;
+        } else if (d2 < best2) {
+            best2 = d2; bk2 = k;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         cnt += __shfl_xor(cnt, o, kWave);
-        const double ob = __shfl_xor(best, o, kWave);
-        const int64_t ok = __shfl_xor(bk, o, kWave);
-        if (ob < best || (ob == best && ok < bk)) { best = ob; bk = ok; }
+        const double ob = __shfl_xor(best, o, kWave), ob2 = __shfl_xor(best2, o, kWave);
+        const int64_t ok = __shfl_xor(bk, o, kWave), ok2 = __shfl_xor(bk2, o, kWave);
+        // merge two (best, second) lists, ties by pivot index
+        const bool mine = best < ob || (best == ob && bk < ok);
+        const double w1 = mine ? best : ob, l1 = mine ? ob : best, s1 = mine ? best2 : ob2;
+        const int64_t wk = mine ? bk : ok, lk = mine ? ok : bk, sk = mine ? bk2 : ok2;
+        const bool lose = l1 < s1 || (l1 == s1 && lk < sk);
+        best = w1; bk = wk;
+        best2 = lose ? l1 : s1; bk2 = lose ? lk : sk;
     }
     if (lane == 0) {
         home[x] = (int32_t)bk;
         d2home[x] = best;
         npar[x] = cnt;
+        if (second) second[x] = bk2 < m ? (int32_t)bk2 : (int32_t)bk;
     }
 }
 
@@ -433,9 +445,9 @@ void launch_guided_candidates(hipStream_t s, int64_t mf, const uint64_t *parent_
 }
 
 void launch_point_pass1(hipStream_t s, int64_t n, int64_t m, const double *dxp, const double *rad,
-                        int32_t *home, double *d2home, int32_t *npar) {
+                        int32_t *home, double *d2home, int32_t *npar, int32_t *second) {
     if (n == 0) return;
-    k_point_pass1<<<(unsigned)div_up(n, 4), 256, 0, s>>>(n, m, dxp, rad, home, d2home, npar);
+    k_point_pass1<<<(unsigned)div_up(n, 4), 256, 0, s>>>(n, m, dxp, rad, home, d2home, npar, second);
     GRNG_LAUNCHED();
 }
 
