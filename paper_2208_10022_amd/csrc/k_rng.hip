@@ -126,7 +126,7 @@ constexpr int kPiv = 16;        // pivot witnesses per tile pair (one MFMA colum
 constexpr int kDl = kTile + 1;  // row stride (floats) of the in-tile distance matrices
 constexpr float kCertain = 1.0f - 0x1p-21f;   // threshold factor of the float32 witness certificate
 constexpr int kXs = kPiv + 4;   // row stride (floats) of the pivot distances: 16-byte aligned rows
-constexpr int kPairChunk = 8;   // tile pairs claimed per atomic
+constexpr int kPairChunk = 32;   // tile pairs claimed per atomic: consecutive ones mostly share T, whose rows and D(T,T) stay in LDS
 constexpr int kPairRecMeta = 12;  // record words before the masks: tiles' start, length, home cell; pivot ids
 constexpr int kPairRecWords = kPairRecordWords;
 static_assert(kPairRecWords == kPairRecMeta + 2 * kTile, "record layout");
