@@ -16,14 +16,28 @@ from decimal import Decimal, getcontext
 import numpy as np
 
 
+GRID_KMAX = 2 ** 24          # every grid integer satisfies |k| < 2**24
+GRID_SUM_LIMIT = 2 ** 51     # and dimension * kmax**2 < 2**51
+
+
 def to_grid(X, q: int) -> np.ndarray:
-    """Exact integer coordinates k = x * 2**q (int64); raises if x is off the grid."""
+    """Exact integer coordinates k = x * 2**q (int64); raises if x is off the grid.
+
+    Enforces the exactness contract the oracle relies on: |k| < 2**24 and
+    d * kmax**2 < 2**51, so a squared distance, (2 kmax)**2 * d < 2**53, and
+    every partial sum of one fit int64 (and float64) with room to spare.
+    """
     A = np.asarray(X, dtype=np.float64) * (2.0 ** q)
     K = np.rint(A)
     if not np.array_equal(A, K):
         raise ValueError(f"input is not on the 2**-{q} grid")
-    if K.size and np.abs(K).max() >= 2.0 ** 31:
-        raise ValueError("grid integers exceed int32 range")
+    if K.size:
+        kmax = int(np.abs(K).max())
+        if kmax >= GRID_KMAX:
+            raise ValueError("grid integers must satisfy |k| < 2**24")
+        d = K.shape[-1] if K.ndim > 1 else 1
+        if d * kmax * kmax >= GRID_SUM_LIMIT:
+            raise ValueError("grid integers too large: need d * kmax**2 < 2**51")
     return K.astype(np.int64)
 
 
