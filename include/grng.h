@@ -69,7 +69,7 @@ typedef enum grng_status {
 enum {
     GRNG_PREC_FP64 = 0, /* exact float64 squared distance for every witness test */
     GRNG_PREC_FP32 = 1, /* float32 rows with an error-bounded screen; undecided tests are recomputed in float64 */
-    GRNG_PREC_BF16 = 2  /* accepted; currently the same screen as GRNG_PREC_FP32 */
+    GRNG_PREC_BF16 = 2  /* not implemented: grng_create returns GRNG_EINVAL */
 };
 
 enum {
@@ -85,8 +85,8 @@ typedef struct grng_options {
     int32_t grid_exp;      /* q: every coordinate and radius is an integer multiple of 2^-q; 0..60 */
     int32_t precision;     /* GRNG_PREC_* */
     int32_t witness_order; /* GRNG_ORDER_* */
-    int32_t use_graph;     /* 0 or 1; no effect in this version (every call sizes its buffers on the host
-                              between launches, and launch overhead is below 1% of a call) */
+    int32_t use_graph;     /* must be 0: graph capture is not implemented (grng_create returns GRNG_EINVAL
+                              for any other value) */
     int32_t autotune;      /* 1: the first grng_build_rng with a pivot layer times complete builds over a
                               small set of witness-pivot counts (vgrng_pivots, then stage4_pivots) and
                               keeps the fastest for later builds, insertions and queries of this index;
@@ -202,8 +202,8 @@ grng_status grng_query_neighbors(grng_index *idx, const float *q_dev, int64_t nq
                                  int32_t *nbrs_dev, int64_t capacity, int64_t *needed);
 
 /* Copy an edge set into uv_dev (int32 [2*E], device): layer >= 0 gives the
- * GRNG of that pivot layer as pairs of positions in its pivot list; layer = -1
- * gives the exemplar RNG as point ids.  Canonical order (u < v, sorted).
+ * GRNG of that pivot layer, layer = -1 the exemplar RNG, both as point ids
+ * (pivots are points, Section 1).  Canonical order (u < v, sorted).
  * If E > capacity (in pairs), returns ECAPACITY with *num_edges = E and
  * copies nothing.  uv_dev may be NULL with capacity 0 to query E.
  * Errors: EINVAL, ESTATE, ECAPACITY, EDEVICE. */

@@ -388,6 +388,7 @@ void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const in
                       int32_t *fill, int32_t *nbr, int pass);
 void launch_pairs_to_ids(hipStream_t s, int64_t np, int32_t *px, int32_t *py, const int32_t *mx, const int32_t *my);
 void launch_sort_segments(hipStream_t s, int64_t nseg, const int64_t *off, int32_t *vals);
+void launch_map_ids(hipStream_t s, int64_t count, int32_t *v, const int32_t *map);
 void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const int32_t *inv, int32_t *px, int32_t *py);
 
 // k_edges.hip

@@ -17,16 +17,20 @@ namespace grng {
 namespace {
 
 thread_local std::string g_last_error;
-int64_t g_alloc_calls = 0;
-int64_t g_fail_at = -2;   // -2: not read yet; -1: disabled
 
-int64_t fail_at() {
-    if (g_fail_at == -2) {
-        const char *e = std::getenv("GRNG_FAIL_ALLOC_AT");
-        g_fail_at = e ? std::atoll(e) : -1;
-    }
-    return g_fail_at;
+// Failure injection for tests of the error paths: with GRNG_FAIL_ALLOC_AT=k
+// in the environment, the k-th device allocation of each C-ABI call fails
+// with GRNG_ENOMEM (the variable is read at the start of every call).
+thread_local int64_t g_alloc_calls = 0;
+thread_local int64_t g_fail_at = -1;   // -1: disabled
+
+void arm_failure_injection() {
+    const char *e = std::getenv("GRNG_FAIL_ALLOC_AT");
+    g_fail_at = (e && *e) ? std::atoll(e) : -1;
+    g_alloc_calls = 0;
 }
+
+int64_t fail_at() { return g_fail_at; }
 
 constexpr int kDefaultK = kPivWitness;
 constexpr int kDefaultVgrngPivots = 256;
@@ -83,11 +87,12 @@ void zero(DevBuf &b, hipStream_t s) { launch_fill_u64(s, b.as<uint64_t>(), (int6
 void check_opts(const grng_options *o) {
     require(o != nullptr, GRNG_EINVAL, "options pointer is NULL");
     require(o->grid_exp >= 0 && o->grid_exp <= 60, GRNG_EINVAL, "grid_exp must be in [0, 60]");
-    require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_BF16, GRNG_EINVAL, "unknown precision");
+    require(o->precision == GRNG_PREC_FP64 || o->precision == GRNG_PREC_FP32, GRNG_EINVAL,
+            "precision must be GRNG_PREC_FP64 or GRNG_PREC_FP32");
     require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED ||
                 o->witness_order == GRNG_ORDER_LUNE, GRNG_EINVAL,
             "unknown witness order");
-    require(o->use_graph == 0 || o->use_graph == 1, GRNG_EINVAL, "use_graph must be 0 or 1");
+    require(o->use_graph == 0, GRNG_EINVAL, "use_graph must be 0 (graph capture is not implemented)");
     require(o->autotune == 0 || o->autotune == 1, GRNG_EINVAL, "autotune must be 0 or 1");
     require(o->stage4_pivots >= 0 && o->stage4_pivots <= kPivWitness, GRNG_EINVAL, "stage4_pivots must be in [0, 16]");
     require(o->vgrng_pivots >= 0, GRNG_EINVAL, "vgrng_pivots must be >= 0");
@@ -1081,6 +1086,9 @@ void do_get_edges(const grng_index *idx, int32_t layer, int32_t *uv, int64_t cap
     if (ne == 0) return;
     require(uv != nullptr, GRNG_EINVAL, "uv pointer is NULL");
     GRNG_HIP(hipMemcpyAsync(uv, src->p, sizeof(int32_t) * 2 * (size_t)ne, hipMemcpyDeviceToDevice, idx->stream));
+    // A layer's edges are kept as positions in its pivot list; the caller gets
+    // point ids.  Pivot ids ascend, so the mapping keeps the canonical order.
+    if (layer >= 0) launch_map_ids(idx->stream, 2 * ne, uv, idx->layers[layer].pid.as<int32_t>());
     GRNG_HIP(hipStreamSynchronize(idx->stream));
 }
 
@@ -1180,6 +1188,7 @@ struct PoolScope {
 template <class F>
 grng_status guarded(F &&f) {
     try {
+        arm_failure_injection();
         f();
         return GRNG_OK;
     } catch (const Error &e) {
@@ -1262,7 +1271,7 @@ void DevBuf::alloc(size_t nbytes) {
     nbytes = (nbytes + 7) & ~size_t(7);
     if (nbytes == 0) nbytes = 8;
     ++g_alloc_calls;
-    if (fail_at() >= 0 && g_alloc_calls == fail_at())
+    if (fail_at() > 0 && g_alloc_calls == fail_at())
         throw Error(GRNG_ENOMEM, "device allocation failed (injected by GRNG_FAIL_ALLOC_AT)");
     if (g_pool) {
         size_t cls = 0;

@@ -150,6 +150,12 @@ __global__ void k_pairs_to_ids(int64_t np, int32_t *px, int32_t *py, const int32
     py[p] = my[py[p]];
 }
 
+// Values through a table: v[t] = map[v[t]] (pivot-list positions to point ids).
+__global__ void k_map_ids(int64_t count, int32_t *v, const int32_t *map) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < count) v[t] = map[v[t]];
+}
+
 inline unsigned grid1(int64_t work) { return (unsigned)(div_up(work, 256) < 1 ? 1 : div_up(work, 256)); }
 
 }  // namespace
@@ -179,6 +185,12 @@ void launch_edges_to_pairs(hipStream_t s, int64_t ne, const int32_t *uv, const i
 void launch_pairs_to_ids(hipStream_t s, int64_t np, int32_t *px, int32_t *py, const int32_t *mx, const int32_t *my) {
     if (np == 0) return;
     k_pairs_to_ids<<<grid1(np), 256, 0, s>>>(np, px, py, mx, my);
+    GRNG_LAUNCHED();
+}
+
+void launch_map_ids(hipStream_t s, int64_t count, int32_t *v, const int32_t *map) {
+    if (count == 0) return;
+    k_map_ids<<<grid1(count), 256, 0, s>>>(count, v, map);
     GRNG_LAUNCHED();
 }
 

@@ -80,3 +80,39 @@ def test_host_validation_without_device(L):
     assert lib.grng_insert_batch(None, None, 1) == -1
     assert lib.grng_get_stats(None, None) == -1
     lib.grng_destroy(None)
+
+
+def test_unimplemented_options_are_rejected(L):
+    """Options the library does not implement fail with EINVAL instead of
+    silently running something else."""
+    lib = L.lib()
+    h = C.c_void_p()
+    for kw in ({"precision": L.PREC_BF16}, {"use_graph": 1}):
+        opt = L.Options(grid_exp=3, **kw)
+        assert lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, C.byref(opt)) == -1, kw
+        assert not h.value
+
+
+_FAIL_ALLOC_SCRIPT = r"""
+import ctypes as C, sys
+sys.path.insert(0, %r)
+import paper_2208_10022_amd as P
+lib = P.lib()
+h = C.c_void_p(12345)
+opt = P.Options(grid_exp=3)
+st = lib.grng_create(C.byref(h), C.c_void_p(8), 10, 2, None, C.byref(opt))
+print(st, h.value, P.last_error())
+"""
+
+
+def test_failure_injection_hook_reports_enomem():
+    """GRNG_FAIL_ALLOC_AT=k makes the k-th device allocation of the process
+    fail.  grng_create's first allocation comes before any HIP call, so on a
+    host without a GPU the call returns ENOMEM, with *out left NULL."""
+    env = dict(os.environ, GRNG_FAIL_ALLOC_AT="1")
+    out = subprocess.run(["python", "-c", _FAIL_ALLOC_SCRIPT % ROOT], capture_output=True, text=True, env=env,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    st, hv, *msg = out.stdout.split(maxsplit=2)
+    assert int(st) == -2 and hv == "None"
+    assert "GRNG_FAIL_ALLOC_AT" in " ".join(msg)

@@ -72,7 +72,7 @@ def test_uniform2d_1000_guided_matches_golden(G):
     rad = synth.knn_radii(W.X, W.q, pid, 25)
     E, lay, _ = gpu_edges(G, W.X, W.q, [(pid, rad)])
     assert np.array_equal(E, golden_edges("uniform2d_n1000_rng_edges.txt"))
-    assert np.array_equal(lay[0], native.grng_edges(W.X[pid], rad, W.q))
+    assert np.array_equal(lay[0], pid[native.grng_edges(W.X[pid], rad, W.q)])
 
 
 @pytest.mark.parametrize("prec", PRECISIONS)
@@ -82,7 +82,7 @@ def test_clustered_3000_d16_matches_golden(G, prec):
     L = W.layers[0]
     E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec)
     assert np.array_equal(E, golden_edges("clustered_n3000_d16_rng_edges.txt"))
-    assert np.array_equal(lay[0], golden_edges("clustered_n3000_d16_m60_grng_edges.txt"))
+    assert np.array_equal(lay[0], L.pivot_ids[golden_edges("clustered_n3000_d16_m60_grng_edges.txt")])
     assert st["candidate_pairs"] > 0
 
 
@@ -120,7 +120,7 @@ def test_guided_and_bruteforce_match_oracle_ragged(G, n, d, m, clusters, seed, p
     want = native.rng_edges(W.X, W.q)
     E, lay, _ = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=prec)
     assert np.array_equal(E, want)
-    assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
+    assert np.array_equal(lay[0], L.pivot_ids[native.grng_edges(W.X[L.pivot_ids], L.radii, W.q)])
     Eb, _, _ = gpu_edges(G, W.X, W.q, precision=prec)
     assert np.array_equal(Eb, want)
 
@@ -241,7 +241,7 @@ def test_clustered_full_size_sampled_rows(G):
         got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
         assert np.array_equal(got, row), x
     # GRNG of the full 1,000-pivot layer in full.
-    assert np.array_equal(lay[0], native.grng_edges(W.X[L.pivot_ids], L.radii, W.q))
+    assert np.array_equal(lay[0], L.pivot_ids[native.grng_edges(W.X[L.pivot_ids], L.radii, W.q)])
 
 
 def test_witness_cells_beyond_the_sort_capacity(G):
@@ -319,8 +319,8 @@ def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed, prec):
     W = synth.subspace3(n=n, d=d, m_fine=mf, m_coarse=mc, sub=seed)
     (Lc, Lf) = W.layers
     E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)], precision=prec)
-    assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
-    assert np.array_equal(lay[1], native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q))
+    assert np.array_equal(lay[0], Lc.pivot_ids[native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q)])
+    assert np.array_equal(lay[1], Lf.pivot_ids[native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)])
     assert np.array_equal(E, native.rng_edges(W.X, W.q))
 
 
@@ -336,8 +336,8 @@ def test_subspace3_full_size_sampled_rows(G):
     (Lc, Lf) = W.layers
     E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)], precision=1)
     say("stats", st)
-    assert np.array_equal(lay[0], native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q))
-    want_f = native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)
+    assert np.array_equal(lay[0], Lc.pivot_ids[native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q)])
+    want_f = Lf.pivot_ids[native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)]
     assert np.array_equal(lay[1], want_f)
     g = np.random.default_rng(7)
     xs = g.choice(W.n, 12, replace=False)
@@ -345,3 +345,33 @@ def test_subspace3_full_size_sampled_rows(G):
     for x, row in zip(xs, rows):
         got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
         assert np.array_equal(got, row), x
+
+
+def test_failed_allocation_leaves_the_index_unchanged(G, monkeypatch):
+    """GRNG_FAIL_ALLOC_AT=k fails the k-th device allocation of a call: the
+    call returns ENOMEM and the index keeps its previous graph, so later calls
+    work as before."""
+    say("failure injection in build_rng and insert_batch")
+    W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
+    L = W.layers[0]
+    idx = G.Index(to_dev(W.X), grid_exp=W.q, precision=1)
+    idx.build_grng_layer(0, to_dev(L.pivot_ids), to_dev(L.radii))
+    idx.build_rng()
+    E0 = idx.edges().cpu().numpy()
+    B = synth.insert_batches(W, n_batches=1, lo=300, hi=301, sub=9)[0]
+    for k in (1, 5, 20):
+        monkeypatch.setenv("GRNG_FAIL_ALLOC_AT", str(k))
+        with pytest.raises(G.GrngError) as e:
+            idx.build_rng()
+        assert e.value.status == -2, k
+        with pytest.raises(G.GrngError) as e:
+            idx.insert_batch(to_dev(B))
+        assert e.value.status == -2, k
+        monkeypatch.delenv("GRNG_FAIL_ALLOC_AT")
+        assert np.array_equal(idx.edges().cpu().numpy(), E0), k
+        assert idx.stats()["n_points"] == W.n
+    idx.build_rng()
+    assert np.array_equal(idx.edges().cpu().numpy(), E0)
+    idx.insert_batch(to_dev(B))
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), native.rng_edges(np.vstack([W.X, B]), W.q))
+    idx.close()
