@@ -45,6 +45,9 @@ def lib():
         L.oracle_query_row.argtypes = [_i32p, C.c_int64, C.c_int32, _i32p, _i64p]
         L.oracle_rng_rows.restype = C.c_int64
         L.oracle_rng_rows.argtypes = [_i32p, C.c_int64, C.c_int32, _i64p, C.c_int64, C.c_int32, _i64p, _i64p]
+        L.oracle_rng_rows_cap.restype = C.c_int64
+        L.oracle_rng_rows_cap.argtypes = [_i32p, C.c_int64, C.c_int32, _i64p, C.c_int64, C.c_int32, C.c_int32,
+                                          C.c_int64, _i64p, _i64p]
         L.oracle_rng_edges.restype = C.c_int64
         L.oracle_rng_edges.argtypes = [_i32p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(_i64p)]
         L.oracle_grng_edges.restype = C.c_int64
@@ -65,7 +68,11 @@ def _ints32(X, q):
 
 
 def default_threads() -> int:
-    return max(1, min(os.cpu_count() or 1, 16))
+    """Every host core the process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
 
 
 def rng_edges(X, q: int, threads: int | None = None) -> np.ndarray:
@@ -102,6 +109,43 @@ def rng_rows(X, q: int, xs, threads: int | None = None) -> list:
     if rc < 0:
         raise MemoryError("oracle_rng_rows failed")
     return [out[i * n:i * n + counts[i]].copy() for i in range(len(xs))]
+
+
+def rng_rows_compact(X, q: int, xs, threads: int | None = None, upper: bool = False, cap: int = 1024,
+                     K=None) -> list:
+    """RNG neighbour lists of the points xs (each sorted ascending), for large N:
+    memory is len(xs) * cap ids, and rows with more neighbours are redone with
+    a larger cap.  upper=True decides only the neighbours y > x of each row.
+    K: the grid integers of X when the caller already has them."""
+    K = _ints32(X, q) if K is None else K
+    n, d = K.shape
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.int64))
+    out_rows = [None] * len(xs)
+    todo = np.arange(len(xs))
+    while len(todo):
+        sub = np.ascontiguousarray(xs[todo])
+        counts = np.zeros(len(sub), dtype=np.int64)
+        out = np.empty(len(sub) * cap, dtype=np.int64)
+        rc = lib().oracle_rng_rows_cap(K.ctypes.data_as(_i32p), n, d, sub.ctypes.data_as(_i64p), len(sub),
+                                       threads or default_threads(), 1 if upper else 0, cap,
+                                       counts.ctypes.data_as(_i64p), out.ctypes.data_as(_i64p))
+        if rc < 0:
+            raise MemoryError("oracle_rng_rows_cap failed")
+        over, grow = [], cap
+        for j, i in enumerate(todo):
+            if counts[j] >= 0:
+                out_rows[i] = out[j * cap:j * cap + counts[j]].copy()
+            else:
+                over.append(i)
+                grow = max(grow, int(-counts[j]))
+        cap = grow
+        todo = np.asarray(over, dtype=np.int64)
+    return out_rows
+
+
+def grid_ints32(X, q: int) -> np.ndarray:
+    """The int32 grid integers the C oracle takes (checked against the contract)."""
+    return _ints32(X, q)
 
 
 def query_row(X, q: int, qpt) -> np.ndarray:

@@ -121,6 +121,40 @@ int64_t oracle_rng_rows(const int32_t *K, int64_t n, int32_t d, const int64_t *x
     return err;
 }
 
+/* Rows of several points in parallel into a caller buffer of `cap` ids per
+ * row: out is nx*cap int64.  counts[i] = the row's neighbour count; a row
+ * with more than cap neighbours is not written and gets counts[i] = -count.
+ * upper != 0 decides only the neighbours y > x of each row (the share of a
+ * row that the full build decides), else every y. */
+int64_t oracle_rng_rows_cap(const int32_t *K, int64_t n, int32_t d, const int64_t *xs, int64_t nx,
+                            int32_t nthreads, int32_t upper, int64_t cap, int64_t *counts, int64_t *out)
+{
+    int64_t err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        okey *keys = (okey *)malloc(sizeof(okey) * (size_t)(n > 0 ? n : 1));
+        int64_t *buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+        if (!keys || !buf) {
+#pragma omp atomic write
+            err = -1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = row_neighbours(K, n, d, K + xs[i] * d, xs[i], upper ? xs[i] : -1, keys, buf);
+                if (c <= cap) {
+                    memcpy(out + i * cap, buf, sizeof(int64_t) * (size_t)c);
+                    counts[i] = c;
+                } else {
+                    counts[i] = -c;
+                }
+            }
+        }
+        free(keys);
+        free(buf);
+    }
+    return err;
+}
+
 /* All RNG edges (u < v), sorted; *out_uv receives a malloc'd array of 2E int64. */
 int64_t oracle_rng_edges(const int32_t *K, int64_t n, int32_t d, int32_t nthreads, int64_t **out_uv)
 {

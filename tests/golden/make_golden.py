@@ -5,7 +5,8 @@ the oracle (``oracle``); nothing here touches the HIP library.  Re-running it
 must reproduce the committed files byte for byte (checked by
 tests/test_golden_files.py).
 
-Usage:  python tests/golden/make_golden.py
+Usage:  python tests/golden/make_golden.py [--large]
+        (--large also writes the full-size digests, minutes of CPU time)
 """
 import os
 import sys
@@ -45,9 +46,33 @@ def files():
     return out
 
 
+def edge_digest_text(E, header):
+    """Edge count and the sha256 of the canonical int32 (u, v) array, as the
+    library returns it (little-endian, u < v, sorted)."""
+    import hashlib
+    A = np.ascontiguousarray(np.asarray(E, dtype="<i4").reshape(-1, 2))
+    lines = ["# " + h for h in header] + ["edges %d" % len(A), "sha256 %s" % hashlib.sha256(A.tobytes()).hexdigest()]
+    return "\n".join(lines) + "\n"
+
+
+def large_files():
+    """Digests of full edge sets that take the C oracle minutes (not rerun by the CPU suite)."""
+    out = {}
+    W = synth.clustered()
+    E = native.rng_edges(W.X, W.q)
+    out["clustered_n100000_d16_rng_digest.txt"] = edge_digest_text(E, [
+        "RNG of synth.clustered() (100,000 points, 16-D, 32 clusters) by the definition",
+        "(Section 1, RNG equation) with the C oracle: edge count and sha256 of the",
+        "canonical little-endian int32 (u < v, sorted) array."])
+    return out
+
+
 if __name__ == "__main__":
     native.build(force=False)
-    for name, text in files().items():
+    todo = dict(files())
+    if "--large" in sys.argv:
+        todo.update(large_files())
+    for name, text in todo.items():
         with open(os.path.join(HERE, name), "w") as f:
             f.write(text)
         print("wrote", name, text.count("\n"), "lines")

@@ -209,3 +209,18 @@ def test_theorem2_coarse_nonlink_implies_fine_nonlink():
                             checks += 1
                             assert (min(i, j), max(i, j)) not in Gf
     assert checks > 0
+
+
+def test_c_oracle_compact_and_upper_rows(oracle_native):
+    """The bounded-memory row oracle equals the full-row one (rows longer than
+    the first capacity are redone), and its upper rows are the full edge
+    list's rows y > x."""
+    W = synth.clustered(n=1500, d=8, clusters=4, m=0, q=19, sub=13)
+    xs = np.arange(0, 1500, 11)
+    full = oracle_native.rng_rows(W.X, W.q, xs)
+    comp = oracle_native.rng_rows_compact(W.X, W.q, xs, cap=3)
+    assert all(np.array_equal(a, b) for a, b in zip(full, comp))
+    E = oracle_native.rng_edges(W.X, W.q)
+    up = oracle_native.rng_rows_compact(W.X, W.q, xs, upper=True)
+    for x, r in zip(xs, up):
+        assert np.array_equal(r, np.sort(E[E[:, 0] == x, 1])), x
