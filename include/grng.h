@@ -242,6 +242,24 @@ int32_t grng_mlp_params(void);
 grng_status grng_mlp_grad(const float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
                           float *grad_dev, float *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same loss and gradient as grng_mlp_grad, bit for bit, but
+ * with no allocation.  The per-block partial gradients go to a fixed scratch
+ * array in the library's device memory (10.5 MB on each device the library
+ * runs on, held until the process ends), so n is limited to
+ * GRNG_MLP_NOALLOC_MAX_SAMPLES; larger n returns GRNG_EINVAL.  The loss is
+ * written to loss_dev (float32, device) instead of a host float, and the call
+ * returns without synchronizing `stream`.  The stream must belong to the
+ * current device.  Every call on a device shares that device's scratch:
+ * calls whose work overlaps on one device (other host threads, other
+ * streams) race and give undefined results; calls queued on one stream are
+ * safe.  Nothing in the scratch needs clearing between calls (each call
+ * writes every entry it reads).  Errors: EINVAL, EDEVICE. */
+#define GRNG_MLP_NOALLOC_MAX_SAMPLES (1 << 24)
+grng_status grng_mlp_grad_noalloc(const float *theta_dev, const float *feats_dev, const uint8_t *labels_dev,
+                                  int64_t n, float *grad_dev, float *loss_dev, void *stream);
+
 /* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step size
  * lr) on theta_dev in place; *loss = loss after the last step. */
 grng_status grng_mlp_train(float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,

@@ -23,7 +23,7 @@ ORDER_DISTANCE, ORDER_LEARNED, ORDER_LUNE = 0, 1, 2
 # Entry points declared in include/grng.h (checked by the CPU tests).
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
                  "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy",
-                 "grng_mlp_params", "grng_mlp_grad", "grng_mlp_train", "grng_mlp_score", "grng_log_witness_cells",
+                 "grng_mlp_params", "grng_mlp_grad", "grng_mlp_grad_noalloc", "grng_mlp_train", "grng_mlp_score", "grng_log_witness_cells",
                  "grng_set_scorer")
 MLP_FEATURES, MLP_HIDDEN = 8, 64
 
@@ -82,6 +82,7 @@ def lib():
             "grng_destroy": (None, [vp]),
             "grng_mlp_params": (i32, []),
             "grng_mlp_grad": (i32, [vp, vp, vp, i64, vp, C.POINTER(C.c_float), vp]),
+            "grng_mlp_grad_noalloc": (i32, [vp, vp, vp, i64, vp, vp, vp]),
             "grng_mlp_train": (i32, [vp, vp, vp, i64, i32, C.c_float, C.POINTER(C.c_float), vp]),
             "grng_mlp_score": (i32, [vp, vp, i64, vp, vp]),
             "grng_log_witness_cells": (i32, [vp, i64, vp, vp, i64, C.POINTER(i64)]),
@@ -145,6 +146,20 @@ def mlp_grad(theta, feats, labels, stream=None):
     check(lib().grng_mlp_grad(_dev_ptr(theta, "float32"), _dev_ptr(feats, "float32"), _dev_ptr(labels, "uint8"),
                               feats.shape[0], _dev_ptr(g, "float32"), C.byref(loss), _stream_handle(stream)))
     return g, float(loss.value)
+
+
+MLP_NOALLOC_MAX_SAMPLES = 1 << 24
+
+
+def mlp_grad_noalloc(theta, feats, labels, grad_out, loss_out, stream=None) -> None:
+    """grng_mlp_grad_noalloc: gradient into grad_out (float32 [P], device) and the
+    loss into loss_out (float32 [1], device); the library allocates nothing."""
+    _mlp_inputs(theta, feats, labels)
+    if grad_out.numel() != mlp_params() or loss_out.numel() < 1:
+        raise ValueError("grad_out must hold %d floats and loss_out at least one" % mlp_params())
+    check(lib().grng_mlp_grad_noalloc(_dev_ptr(theta, "float32"), _dev_ptr(feats, "float32"),
+                                      _dev_ptr(labels, "uint8"), feats.shape[0], _dev_ptr(grad_out, "float32"),
+                                      _dev_ptr(loss_out, "float32"), _stream_handle(stream)))
 
 
 def mlp_train(theta, feats, labels, steps: int, lr: float, stream=None) -> float:

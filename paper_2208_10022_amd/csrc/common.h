@@ -223,7 +223,12 @@ __device__ inline float mlp_score_bf16(const uint16_t *wb, const float *f) {
 
 // k_mlp.hip
 void launch_mlp_grad(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels, int64_t n,
-                     float *grad, float *loss, DevBuf &scratch);
+                     float *grad, float *loss, DevBuf &work);
+// The same gradient with the partials in the library's fixed device scratch
+// (no allocation); n <= kNoAllocMaxSamples.
+constexpr int64_t kNoAllocMaxSamples = GRNG_MLP_NOALLOC_MAX_SAMPLES;
+void launch_mlp_grad_noalloc(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels,
+                             int64_t n, float *grad, float *loss_dev);
 void launch_adam(hipStream_t s, float *theta, const float *g, float *m, float *v, int t, float lr);
 void launch_pack_bf16(hipStream_t s, const float *theta, uint16_t *out);
 void launch_mlp_score(hipStream_t s, const uint16_t *wb, const float *feats, int64_t n, float *scores);

@@ -1341,6 +1341,15 @@ grng_status grng_mlp_grad(const float *theta_dev, const float *feats_dev, const 
     return guarded([&] { do_mlp_grad(theta_dev, feats_dev, labels_dev, n, grad_dev, loss, stream); });
 }
 
+grng_status grng_mlp_grad_noalloc(const float *theta_dev, const float *feats_dev, const uint8_t *labels_dev,
+                                  int64_t n, float *grad_dev, float *loss_dev, void *stream) {
+    return guarded([&] {
+        require(theta_dev && feats_dev && labels_dev && grad_dev && loss_dev, GRNG_EINVAL, "NULL argument");
+        launch_mlp_grad_noalloc(static_cast<hipStream_t>(stream), theta_dev, feats_dev, labels_dev, n, grad_dev,
+                                loss_dev);
+    });
+}
+
 grng_status grng_mlp_train(float *theta_dev, const float *feats_dev, const uint8_t *labels_dev, int64_t n,
                            int32_t steps, float lr, float *loss, void *stream) {
     return guarded([&] { do_mlp_train(theta_dev, feats_dev, labels_dev, n, steps, lr, loss, stream); });

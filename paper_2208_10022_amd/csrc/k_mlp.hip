@@ -12,6 +12,8 @@
 // per-block partial gradients reduced in a fixed order (deterministic), then
 // an Adam step.  Scoring in the scan uses the weights rounded to bf16 with
 // float32 accumulation.
+#include <mutex>
+
 #include "common.h"
 
 namespace grng {
@@ -229,17 +231,64 @@ __global__ __launch_bounds__(256) void k_log_cells(
 
 }  // namespace
 
-void launch_mlp_grad(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels, int64_t n,
-                     float *grad, float *loss, DevBuf &scratch) {
-    require(n >= 1, GRNG_EINVAL, "need at least one sample");
-    const int64_t per = 4096;
-    const int64_t nb = div_up(n, per);
-    scratch.ensure(sizeof(float) * (size_t)(nb * P + nb));
-    float *partial = scratch.as<float>(), *pl = partial + nb * P;
-    k_mlp_grad_partial<<<(unsigned)nb, 256, 0, s>>>(theta, feats, labels, n, per, partial, pl);
+namespace {
+
+constexpr int64_t kGradPerBlock = 4096;   // samples per block of the partial-gradient kernel
+
+// Partial gradients of ceil(n / kGradPerBlock) blocks ([nb][P], then [nb]
+// losses) in `partial`, reduced in a fixed order into grad and *loss.
+void grad_into(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels, int64_t n,
+               float *grad, float *loss, float *partial) {
+    const int64_t nb = div_up(n, kGradPerBlock);
+    float *pl = partial + nb * P;
+    k_mlp_grad_partial<<<(unsigned)nb, 256, 0, s>>>(theta, feats, labels, n, kGradPerBlock, partial, pl);
     GRNG_LAUNCHED();
     k_mlp_reduce<<<(unsigned)div_up(P, 256), 256, 0, s>>>(partial, pl, nb, grad, loss);
     GRNG_LAUNCHED();
+}
+
+// Fixed device scratch of the allocation-free gradient: room for the
+// partials of kNoAllocMaxSamples samples (4,096 blocks x 642 floats, 10.5 MB
+// per device, held until the process ends).  Host code never passes the
+// array's name to a kernel: on the host it is only a stand-in for the
+// symbol; the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr int64_t kNoAllocBlocks = kNoAllocMaxSamples / kGradPerBlock;
+static_assert(kNoAllocBlocks * kGradPerBlock == kNoAllocMaxSamples, "whole blocks");
+static __device__ __align__(256) float scratch[kNoAllocBlocks * (P + 1)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
+float *scratch_of_current_device() {
+    int dev = 0;
+    GRNG_HIP(hipGetDevice(&dev));
+    require(dev >= 0 && dev < kMaxDevices, GRNG_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        GRNG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+
+}  // namespace
+
+void launch_mlp_grad(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels, int64_t n,
+                     float *grad, float *loss, DevBuf &work) {
+    require(n >= 1, GRNG_EINVAL, "need at least one sample");
+    const int64_t nb = div_up(n, kGradPerBlock);
+    work.ensure(sizeof(float) * (size_t)(nb * P + nb));
+    grad_into(s, theta, feats, labels, n, grad, loss, work.as<float>());
+}
+
+void launch_mlp_grad_noalloc(hipStream_t s, const float *theta, const float *feats, const uint8_t *labels,
+                             int64_t n, float *grad, float *loss_dev) {
+    require(n >= 1 && n <= kNoAllocMaxSamples, GRNG_EINVAL,
+            "grng_mlp_grad_noalloc takes 1 to GRNG_MLP_NOALLOC_MAX_SAMPLES samples");
+    grad_into(s, theta, feats, labels, n, grad, loss_dev, scratch_of_current_device());
 }
 
 void launch_adam(hipStream_t s, float *theta, const float *g, float *m, float *v, int t, float lr) {
