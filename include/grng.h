@@ -69,7 +69,11 @@ typedef enum grng_status {
 enum {
     GRNG_PREC_FP64 = 0, /* exact float64 squared distance for every witness test */
     GRNG_PREC_FP32 = 1, /* float32 rows with an error-bounded screen; undecided tests are recomputed in float64 */
-    GRNG_PREC_BF16 = 2  /* not implemented: grng_create returns GRNG_EINVAL */
+    GRNG_PREC_BF16 = 2  /* GRNG_PREC_FP32, but the pair kernel's distance tiles come from bf16 MFMA with
+                           float32 accumulation on cell-centred coordinates split into two bf16 parts
+                           (three products per tile), with a per-tile error bound; a certificate kills a
+                           pair only outside the bound, and pairs within it go on to the exhaustive scan,
+                           which re-decides them exactly */
 };
 
 enum {
@@ -137,7 +141,9 @@ typedef struct grng_stats {
     double ms_autotune;           /* device time of the autotuner's trial builds (0 when it has not run) */
     double ms_pair_masks;         /* device time of the candidate-mask pass before the pair kernel (last build);
                                      ms_pairs is the pair kernel alone */
-    double reserved[1];
+    double screen_uncertain;      /* GRNG_PREC_BF16: pairs the pair kernel passed on to the exhaustive scan
+                                     although an in-tile witness lay within the bf16 tiles' error bound (the scan
+                                     re-decides them exactly); 0 in the other modes */
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -158,6 +158,7 @@ struct PointState {
 // Pivot-side tables of the finest layer used by every pass over points.
 struct LayerAux {
     DevBuf Xp, nrmp;               // pivot coordinates and norms
+    DevBuf Xpf;                    // float [m][dp] the same coordinates (exact: grid values)
     DevBuf pknn;                   // int32 [m][16] nearest pivots of each pivot
     DevBuf wknn;                   // int32 [m][kw] nearest pivots of each pivot (Proposition 1 witnesses)
     int32_t kw = 0;
@@ -176,6 +177,7 @@ enum Counter {
     C_TPV,            // tile pairs that reached Stage V (D(U,U) computed)
     C_TTV,            // D(T,T) computations (not repeated while consecutive tile pairs share T)
     C_UNSORTED,       // rows whose witness-cell list exceeded the sort capacity
+    C_UNCERTAIN,      // bf16 pair kernel: survivors with an in-tile witness within the error bound
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,
@@ -367,6 +369,12 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const d
                         const double *XB, const double *nrmB, int mode, int dp, int32_t K,
                         const double *Xp, const double *nrmp, PairList out, uint64_t *dmax_bits, uint64_t *work,
                         uint64_t *counters);
+// bf16 tiles; survivors are written with d2 = -1: launch_pairs_exact_d2 fills
+// in their exact squared distances (and the per-row maxima) afterwards.
+void launch_pairs_bf16(hipStream_t s, int64_t ntp, const uint64_t *rec, const float *XAf, const float *XBf, int mode,
+                       int dp, int32_t K, const float *Xpf, PairList out, uint64_t *work, uint64_t *counters);
+void launch_pairs_exact_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *XA,
+                           const double *XB, double *d2, uint64_t *dmax_bits);
 void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,
                       const double *nrmB, int dp, bool self, PairList out, uint64_t *counters);
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,

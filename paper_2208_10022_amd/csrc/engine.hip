@@ -87,8 +87,7 @@ void zero(DevBuf &b, hipStream_t s) { launch_fill_u64(s, b.as<uint64_t>(), (int6
 void check_opts(const grng_options *o) {
     require(o != nullptr, GRNG_EINVAL, "options pointer is NULL");
     require(o->grid_exp >= 0 && o->grid_exp <= 60, GRNG_EINVAL, "grid_exp must be in [0, 60]");
-    require(o->precision == GRNG_PREC_FP64 || o->precision == GRNG_PREC_FP32, GRNG_EINVAL,
-            "precision must be GRNG_PREC_FP64 or GRNG_PREC_FP32");
+    require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_BF16, GRNG_EINVAL, "unknown precision");
     require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED ||
                 o->witness_order == GRNG_ORDER_LUNE, GRNG_EINVAL,
             "unknown witness order");
@@ -360,6 +359,8 @@ void prepare_aux(grng_index *idx, const Layer &L, LayerAux &aux) {
     aux.nrmp.alloc(sizeof(double) * (size_t)m);
     launch_gather_rows(s, idx->X.as<double>(), L.pid.as<int32_t>(), m, dp, aux.Xp.as<double>());
     launch_gather_f64(s, idx->nrm.as<double>(), L.pid.as<int32_t>(), m, aux.nrmp.as<double>());
+    aux.Xpf.alloc(sizeof(float) * (size_t)(m * dp));
+    launch_to_f32(s, aux.Xp.as<double>(), m * dp, aux.Xpf.as<float>());
     aux.pknn.alloc(4 * (size_t)(m * kPivWitness));
     launch_pivot_knn(s, m, L.dpp2.as<double>(), kPivWitness, aux.pknn.as<int32_t>());
     // Proposition 1 witnesses per point block: the pivots nearest its home cell.
@@ -620,6 +621,7 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     // Tile-pair records (bounds, pivot ids and candidate masks), written by
     // the mask pass and streamed by the pair kernel, in chunks of at most
     // 2^21 tile pairs (2.3 GB).
+    const bool bf16 = idx->opt.precision == GRNG_PREC_BF16;
     const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 21);
     DevBuf rec;
     rec.alloc(8 * (size_t)kPairRecordWords * (size_t)std::max<int64_t>(chunk, 1));
@@ -635,9 +637,13 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
                               aux.pknn.as<int32_t>(), K, rec.as<uint64_t>());
             ms_m += mt.stop();
             EventTimer pt(s);
-            launch_pairs_tiled(s, nc, rec.as<uint64_t>(), A.Xh.as<double>(), A.nrmh.as<double>(), B.Xh.as<double>(),
-                               B.nrmh.as<double>(), mode, idx->dp, K, aux.Xp.as<double>(),
-                               aux.nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
+            if (bf16)
+                launch_pairs_bf16(s, nc, rec.as<uint64_t>(), A.Xf.as<float>(), B.Xf.as<float>(), mode, idx->dp, K,
+                                  aux.Xpf.as<float>(), P.view(), ctr + C_WORK0, ctr);
+            else
+                launch_pairs_tiled(s, nc, rec.as<uint64_t>(), A.Xh.as<double>(), A.nrmh.as<double>(),
+                                   B.Xh.as<double>(), B.nrmh.as<double>(), mode, idx->dp, K, aux.Xp.as<double>(),
+                                   aux.nrmp.as<double>(), P.view(), dmax.as<uint64_t>(), ctr + C_WORK0, ctr);
             ms += pt.stop();
         }
         bt.masks += ms_m;
@@ -647,7 +653,15 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
         std::vector<uint64_t> h;
         d2h(h, P.count.p, 1, s);
         np = (int64_t)h[0];
-        if (np <= cap) break;
+        if (np <= cap) {
+            if (bf16) {   // exact squared distances of the survivors, and each row's largest
+                EventTimer dt(s);
+                launch_pairs_exact_d2(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), idx->dp, A.Xh.as<double>(),
+                                      B.Xh.as<double>(), P.d2.as<double>(), dmax.as<uint64_t>());
+                bt.pairs += dt.stop();
+            }
+            break;
+        }
         require(attempt < 2, GRNG_EDEVICE, "survivor count changed between identical passes");
         cap = np;   // rerun with room for every survivor, from the counters as they were
         GRNG_HIP(hipMemcpyAsync(idx->counters.p, snapshot.data(), 8 * C_NUM, hipMemcpyHostToDevice, s));
@@ -756,6 +770,7 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.rechecks = (double)c[C_RECHECK];
     idx->stats.exhaustive_pairs = (double)c[C_SURV];
     idx->stats.lune_tests = (double)c[C_LUNE];
+    idx->stats.screen_uncertain = (double)c[C_UNCERTAIN];
     // Bytes a witness test reads: the witness row and its cell-distance
     // bound (float32 with the float32 screen, float64 otherwise); a test
     // that ends early on a partial sum reads less.

@@ -41,7 +41,7 @@ def query_lists(idx, Q):
     return [nb[off[i]:off[i + 1]] for i in range(len(Q))]
 
 
-@pytest.mark.parametrize("layered,prec", [(True, 0), (True, 1), (False, 0)])
+@pytest.mark.parametrize("layered,prec", [(True, 0), (True, 1), (True, 2), (False, 0)])
 def test_query_neighbors_match_oracle(G, layered, prec):
     say("query", layered, "precision", prec)
     W = synth.clustered(n=2500, d=16, clusters=6, m=60, knn=40, sub=3)
@@ -75,7 +75,8 @@ def test_query_capacity_protocol(G):
 
 
 @pytest.mark.parametrize("layered,prec,lo,hi", [(True, 0, 100, 900), (True, 1, 100, 900), (False, 0, 100, 900),
-                                               (True, 1, 10, 150), (True, 0, 10, 150)])
+                                               (True, 1, 10, 150), (True, 0, 10, 150), (True, 2, 100, 900),
+                                               (True, 2, 10, 150)])
 def test_insert_batches_match_rebuild_oracle(G, layered, prec, lo, hi):
     """Batches of 400 or more points into 50 pivot cells take the dense path
     (batch points in their cells' tiles); smaller ones the sparse path (the

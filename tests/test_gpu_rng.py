@@ -28,9 +28,10 @@ def G():
     return P
 
 
-# Both distance precisions must give identical edges: float64 everywhere
-# (0), and float32 screens with exact float64 re-decision (1).
-PRECISIONS = [0, 1]
+# Every arithmetic form must give identical edges: float64 everywhere (0),
+# float32 screens with exact float64 re-decision (1), and bf16 MFMA distance
+# tiles with a per-tile error bound in the pair kernel (2).
+PRECISIONS = [0, 1, 2]
 
 
 def golden_edges(name):
@@ -282,7 +283,7 @@ def test_float32_screen_redecides_exact_ties(G):
     for prec in PRECISIONS:
         E, _, st = gpu_edges(G, P, 0, [(pid, rad)], precision=prec)
         assert np.array_equal(E, want), prec
-        if prec == 1:
+        if prec >= 1:
             assert st["rechecks"] > 0
         else:
             assert st["rechecks"] == 0
@@ -311,7 +312,8 @@ def test_grng_layer_exact_ties_use_the_integer_predicate(G):
 
 
 @pytest.mark.parametrize("n,d,mf,mc,seed,prec", [(6000, 32, 240, 12, 0, 0), (6000, 32, 240, 12, 0, 1),
-                                                 (3000, 8, 150, 20, 1, 1)])
+                                                 (6000, 32, 240, 12, 0, 2), (3000, 8, 150, 20, 1, 1),
+                                                 (3000, 8, 150, 20, 1, 2)])
 def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed, prec):
     """Coarse layer -> guided fine layer (Theorem 2) -> RNG, on the
     8-dimensional-subspace workload family at reduced size."""
