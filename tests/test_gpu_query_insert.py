@@ -110,32 +110,3 @@ def test_insert_order_invariance_and_duplicates(G):
     i1.close()
     allX = np.vstack([W.X, b[0], b[1], dup])
     assert np.array_equal(e1, native.rng_edges(allX, W.q))
-
-
-def test_insert_64_batches_full_size(G):
-    """64 batches of log-uniform sizes in [1,000, 50,000] into the 100k x 16-D
-    index; RNG rows of sampled old and new points match the oracle after
-    batches 1, 2, 8, 16, 32 and 64."""
-    say("insert 64 batches into the 100k index")
-    W = synth.clustered()
-    batches = synth.insert_batches(W)
-    L = W.layers[0]
-    idx = make_index(G, W.X, W.q, (L.pivot_ids, L.radii), precision=1)
-    allX = [W.X]
-    g = np.random.default_rng(3)
-    for bi, B in enumerate(batches, 1):
-        idx.insert_batch(to_dev(B))
-        allX.append(B)
-        if bi not in (1, 2, 8, 16, 32, 64):
-            continue
-        X = np.vstack(allX)
-        E = idx.edges().cpu().numpy().astype(np.int64)
-        n0 = len(X) - len(B)
-        xs = np.concatenate([g.choice(n0, 3, replace=False), n0 + g.choice(len(B), 3, replace=False)])
-        rows = native.rng_rows(X, W.q, xs)
-        for x, row in zip(xs, rows):
-            got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
-            assert np.array_equal(got, row), (bi, x)
-        say("batch", bi, "n", len(X), "edges", len(E))
-    assert idx.stats()["n_points"] == sum(len(b) for b in allX)
-    idx.close()

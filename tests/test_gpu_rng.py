@@ -220,31 +220,6 @@ def test_error_statuses(G):
     del torch
 
 
-def test_clustered_full_size_sampled_rows(G):
-    """The 100k x 16-D, 32-cluster, 1,000-pivot workload in the bench's launch
-    configuration, in both precisions: sampled rows compared with the oracle
-    one by one, and the two edge sets compared in full."""
-    say("clustered full size n=100000 d=16 m=1000")
-    W = synth.clustered()
-    L = W.layers[0]
-    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=0)
-    say("stats fp64", st)
-    E32, lay32, st32 = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii)], precision=1)
-    say("stats fp32", st32)
-    assert np.array_equal(E32, E)
-    assert np.array_equal(lay32[0], lay[0])
-    assert np.all(E[:, 0] < E[:, 1])
-    assert np.all(np.diff(E[:, 0]) >= 0)
-    g = np.random.default_rng(99)
-    xs = g.choice(W.n, 48, replace=False)
-    rows = native.rng_rows(W.X, W.q, xs)
-    for x, row in zip(xs, rows):
-        got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
-        assert np.array_equal(got, row), x
-    # GRNG of the full 1,000-pivot layer in full.
-    assert np.array_equal(lay[0], L.pivot_ids[native.grng_edges(W.X[L.pivot_ids], L.radii, W.q)])
-
-
 def test_witness_cells_beyond_the_sort_capacity(G):
     """4,500 pivots and one far outlier: the outlier's pairs are long, so every
     cell may hold a witness for them and its cell list (more than the 4,096
@@ -324,29 +299,6 @@ def test_three_layer_hierarchy_matches_oracle(G, n, d, mf, mc, seed, prec):
     assert np.array_equal(lay[0], Lc.pivot_ids[native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q)])
     assert np.array_equal(lay[1], Lf.pivot_ids[native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)])
     assert np.array_equal(E, native.rng_edges(W.X, W.q))
-
-
-def test_subspace3_full_size_sampled_rows(G):
-    """The three-layer workload at full size: 1,000,000 points in 32-D near an
-    8-D subspace, 100 coarse and 3,000 fine pivots.  Both GRNG layers are
-    checked (coarse in full, fine on sampled rows) and RNG rows of sampled
-    points are compared with the oracle one by one.  At this size the
-    Proposition 1 witness distances are gathered in two passes of points and
-    the 146M tile-pair records are written in 70 chunks."""
-    say("subspace3 full size n=1000000 d=32 m=100/3000")
-    W = synth.subspace3()
-    (Lc, Lf) = W.layers
-    E, lay, st = gpu_edges(G, W.X, W.q, [(Lc.pivot_ids, Lc.radii), (Lf.pivot_ids, Lf.radii)], precision=1)
-    say("stats", st)
-    assert np.array_equal(lay[0], Lc.pivot_ids[native.grng_edges(W.X[Lc.pivot_ids], Lc.radii, W.q)])
-    want_f = Lf.pivot_ids[native.grng_edges(W.X[Lf.pivot_ids], Lf.radii, W.q)]
-    assert np.array_equal(lay[1], want_f)
-    g = np.random.default_rng(7)
-    xs = g.choice(W.n, 12, replace=False)
-    rows = native.rng_rows(W.X, W.q, xs)
-    for x, row in zip(xs, rows):
-        got = np.sort(np.concatenate([E[E[:, 0] == x, 1], E[E[:, 1] == x, 0]]))
-        assert np.array_equal(got, row), x
 
 
 def test_failed_allocation_leaves_the_index_unchanged(G, monkeypatch):
