@@ -1,15 +1,25 @@
-"""Benchmark of the exact two-layer GRNG -> RNG build on one MI355X.
+"""Benchmark of the exact GRNG-guided RNG build on one MI355X.
 
-Workload: 100,000 points in 16-D, a Gaussian mixture of 32 isotropic clusters
-(centres uniform in [0,10]^16, sigma 0.5) on the 2^-19 grid, with 1,000 random
-pivots whose radius is the distance to their 100th nearest other point.  One
-step = build the GRNG of the pivot layer, then the exact RNG of all points
-(every kept/eliminated decision exact).  Inputs (points, pivot ids, radii) are
-resident in device memory before timing starts.
+Default workload (the largest single-GPU configuration): 1,000,000 points in
+32-D near a random 8-dimensional subspace (noise sigma 0.01, 2^-21 grid), a
+three-layer hierarchy of 100 coarse and 3,000 fine pivots (the coarse layer a
+subset of the fine one).  One step = build the GRNG of both pivot layers,
+then the exact RNG of all points, in the bf16 form (bf16 MFMA distance tiles
+with a per-tile error bound in the pair kernel; every kept/eliminated
+decision exact).  After the timed steps the plain float32 form builds the
+same graph once; its time and its edge set (compared in full) go into the
+line's "forms" object.  Inputs (points, pivot ids, radii) are resident in
+device memory before timing starts.
+
+Other workloads (--workload), each printing its own line:
+  clustered    100k x 16-D, 32 clusters, 1,000 pivots (plain float32 form),
+               plus RNG-neighbour query throughput;
+  clustered96  1M x 96-D, 256 clusters, 10,000 pivots: the learned and the
+               lune visit orders against the distance order;
+  insert       64 batches into the 100k index: the incremental insertion
+               against a rebuild at every batch.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
-``--workload subspace3`` times the 1M x 32-D three-layer build instead (for
-profiling that configuration; the benchmark line is the default workload).
 """
 from __future__ import annotations
 
@@ -22,16 +32,27 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks, and the VALU issue peak derived from unit counts:
+# Published MI355X peaks (dense), and the VALU rates derived from unit counts:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s (one
-# float32 min or max per lane per cycle; packed FP32 is not used).
+# 32-bit min, max or compare per lane per cycle) and twice that in float32
+# flops for fused multiply-adds (78.6 TFLOP/s; packed FP32 is not used).
 MI355X_HBM_GBS = 8000.0
 MI355X_FP64_TFLOPS = 78.6
+MI355X_BF16_TFLOPS = 2500.0
 MI355X_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+MI355X_FP32_VALU_TFLOPS = 2 * MI355X_VALU_TOPS
 
+PRECISION_NAMES = {0: "float64 tiles and scan", 1: "float64 MFMA tiles, float32 screens with float64 re-decision",
+                   2: "bf16 MFMA tiles (two-part split, float32 accumulation) with a per-tile error bound, "
+                      "float32 screens with float64 re-decision"}
+PRECISION_DTYPE = {0: "f64", 1: "f64", 2: "bf16"}
+PAIR_KERNEL = {0: "k_pairs_tiled", 1: "k_pairs_tiled", 2: "k_pairs_bf16"}
 
-KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "common.h"], "k_pair_masks": ["k_rng.hip", "common.h"],
-                  "k_lune_guided": ["k_rng.hip", "common.h"], "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
+KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "dev_util.h", "common.h"],
+                  "k_pairs_bf16": ["k_pairs_bf16.hip", "dev_util.h", "common.h"],
+                  "k_pair_masks": ["k_rng.hip", "dev_util.h", "common.h"],
+                  "k_lune_guided": ["k_rng.hip", "dev_util.h", "common.h"],
+                  "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
 
 
 def source_hash(kernel: str) -> str:
@@ -45,7 +66,7 @@ def source_hash(kernel: str) -> str:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    """HBM bytes per build from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source and this workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -95,53 +116,70 @@ def attainable_peaks(torch) -> dict:
     return out
 
 
-def kernel_rooflines(st: dict) -> dict:
-    """Per main kernel of the last build: time and achieved fraction of its roof.
+def _entry(bound, achieved, peak, unit, ms, **extra):
+    r = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak, "ms": ms}
+    r.update(extra)
+    return r
 
-    k_vgrng_tiles  (min,max) product, VALU: 2 ops per (point, pivot j, pivot k)
-                   for each of two radius choices = 2 * vgrng_ops.
-    k_pairs_tiled  MFMA f64 distance tiles (pairs_flops) and the Stage IV
-                   (min,max) product on the VALU (stage4_ops); the roof is the
-                   one with the longer time at peak.
-    k_lune_guided  witness rows streamed: lune_bytes (row + cell bound per
-                   witness test) against HBM bandwidth.
-    k_pair_masks   one 1,120-byte record written per tile pair.
+
+def kernel_rooflines(st: dict, d: int, precision: int) -> dict:
+    """Per main kernel of the last build: the roof that binds it at peak, and
+    the achieved fraction, from algorithmic work only.
+
+    pair kernel   two roofs.  Matrix cores: the squared distances the method
+                  uses (candidate pairs, the pivot blocks, the Stage V witness
+                  matrices: pair_method_distances), 2 d flops each, against the
+                  MFMA peak of the tiles' type (bf16 or float64).  VALU: the
+                  Stage IV (min,max) product, one max and one min per
+                  (candidate pair, pivot witness).  The binding roof is the one
+                  with the longer time at peak; the other is reported beside
+                  it, with the dense-tile flops the kernel actually issues.
+    k_lune_guided one witness test = two squared distances of d coordinates
+                  (a subtraction and a fused multiply-add each), 4 d float32
+                  flops, against the float32 VALU rate (the witness rows are
+                  served from cache; HBM bytes are in 'traffic').
+    k_vgrng_tiles (min,max) product: 2 ops per (point, pivot j, witness k)
+                  for each of two radius choices = 2 * vgrng_ops.
+    k_pair_masks  one 1,120-byte record written per tile pair.
     """
     out = {}
-    ms = st["ms_vgrng"]
-    ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12
-    out["k_vgrng_tiles"] = {"bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS, "unit": "Tops/s",
-                            "frac": ach / MI355X_VALU_TOPS, "ms": ms}
+    pk = PAIR_KERNEL[precision]
     ms = st["ms_pairs"]
-    t_mfma = st["pairs_flops"] / (MI355X_FP64_TFLOPS * 1e12)
-    t_valu = st["stage4_ops"] / (MI355X_VALU_TOPS * 1e12)
+    flops = st["pair_method_distances"] * 2.0 * d
+    mfma_peak = MI355X_BF16_TFLOPS if precision == 2 else MI355X_FP64_TFLOPS
+    kp = (d + 31) // 32 * 32 if precision == 2 else (d + 3) // 4 * 4
+    dense = st["pair_tile_entries"] * 2.0 * kp * (3 if precision == 2 else 1)
+    valu_ops = 2.0 * st["candidate_pairs"] * st["stage4_pivots"]
+    t_mfma = flops / (mfma_peak * 1e12)
+    t_valu = valu_ops / (MI355X_VALU_TOPS * 1e12)
+    mfma_view = {"achieved": flops / (ms / 1e3) / 1e12, "peak": mfma_peak, "unit": "TFLOP/s",
+                 "frac": t_mfma / (ms / 1e3), "dense_tile_tflop_s": dense / (ms / 1e3) / 1e12}
+    valu_view = {"achieved": valu_ops / (ms / 1e3) / 1e12, "peak": MI355X_VALU_TOPS, "unit": "Tops/s",
+                 "frac": t_valu / (ms / 1e3)}
     if t_mfma >= t_valu:
-        ach = st["pairs_flops"] / (ms / 1e3) / 1e12
-        out["k_pairs_tiled"] = {"bound": "mfma", "achieved": ach, "peak": MI355X_FP64_TFLOPS, "unit": "TFLOP/s",
-                                "frac": ach / MI355X_FP64_TFLOPS, "ms": ms,
-                                "valu_frac": t_valu / (ms / 1e3)}
+        out[pk] = _entry("mfma", mfma_view["achieved"], mfma_peak, "TFLOP/s", ms, valu=valu_view,
+                         dense_tile_tflop_s=mfma_view["dense_tile_tflop_s"])
     else:
-        ach = st["stage4_ops"] / (ms / 1e3) / 1e12
-        out["k_pairs_tiled"] = {"bound": "alu", "achieved": ach, "peak": MI355X_VALU_TOPS, "unit": "Tops/s",
-                                "frac": ach / MI355X_VALU_TOPS, "ms": ms, "mfma_frac": t_mfma / (ms / 1e3)}
+        out[pk] = _entry("alu", valu_view["achieved"], MI355X_VALU_TOPS, "Tops/s", ms, mfma=mfma_view)
     ms = st["ms_lune"]
-    ach = st["lune_bytes"] / (ms / 1e3) / 1e9
-    out["k_lune_guided"] = {"bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                            "frac": ach / MI355X_HBM_GBS, "ms": ms,
-                            "note": "witness rows are served from L2/MALL, so the algorithmic bytes can exceed "
-                                    "the HBM roof"}
+    if ms > 0:
+        fl = st["lune_tests"] * 4.0 * d
+        out["k_lune_guided"] = _entry("alu", fl / (ms / 1e3) / 1e12, MI355X_FP32_VALU_TFLOPS, "TFLOP/s", ms)
+    ms = st["ms_vgrng"]
+    if ms > 0:
+        ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12
+        out["k_vgrng_tiles"] = _entry("alu", ach, MI355X_VALU_TOPS, "Tops/s", ms)
     ms = st["ms_pair_masks"]
     if ms > 0:
         ach = PAIR_RECORD_BYTES * st["tile_pairs"] / (ms / 1e3) / 1e9
-        out["k_pair_masks"] = {"bound": "hbm", "achieved": ach, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                               "frac": ach / MI355X_HBM_GBS, "ms": ms,
-                               "note": "record bytes written; the reads are dependent gathers (latency-bound)"}
+        out["k_pair_masks"] = _entry("hbm", ach, MI355X_HBM_GBS, "GB/s", ms,
+                                     note="record bytes written; the reads are dependent gathers")
     return out
 
 
-def roofline(st: dict, workload: str) -> dict:
-    """Roofline entry for the main kernel that took the longest in the last build."""
-    ks = kernel_rooflines(st)
+def roofline(st: dict, d: int, precision: int, workload: str) -> dict:
+    """Roofline entry of the main kernel that took the longest in the last build."""
+    ks = kernel_rooflines(st, d, precision)
     k = max(ks, key=lambda name: ks[name]["ms"])
     r = dict(ks[k])
     r["kernel"] = k
@@ -149,54 +187,43 @@ def roofline(st: dict, workload: str) -> dict:
     return r
 
 
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--precision", type=int, default=1, help="0 = float64 everywhere, 1 = float32 screens + "
-                    "float64 re-decision (the plain float32 form)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", type=int, default=1, help="1: the index autotunes its witness-pivot counts on "
-                    "the first (warmup) build")
-    ap.add_argument("--vgrng-pivots", type=int, default=0, help="Proposition 1 witness pivots per block (autotune 0)")
-    ap.add_argument("--stage4-pivots", type=int, default=0, help="Stage IV pivot witnesses (autotune 0)")
-    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
-    ap.add_argument("--queries", type=int, default=4096, help="queries timed against the built index (0 = none)")
-    ap.add_argument("--workload", default="clustered", choices=["clustered", "subspace3"],
-                    help="clustered: the 100k x 16-D two-layer build (the benchmark); subspace3: the 1M x 32-D "
-                         "three-layer build (100 coarse, 3,000 fine pivots)")
-    ap.add_argument("--copy-calibration-mb", type=int, default=0,
-                    help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
-    ap.add_argument("--attainable", action="store_true",
-                    help="only measure attainable peaks: device copy bandwidth and a float64 library GEMM")
-    return ap.parse_args()
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(W, rows_hint: int):
-    """The oracle (C, OpenMP) on a bounded sample: RNG rows of sampled points, scaled to all N rows."""
+def cpu_baseline(W, rows_hint: int, target_s: float = 15.0):
+    """The C oracle (OpenMP, every host core) on a bounded sample: RNG rows of
+    random points deciding only their neighbours y > x (the share of each row
+    the full-edge oracle decides), scaled by N / rows to the full build."""
     import numpy as np
 
     from oracle import native
     native.build(force=False)
     threads = native.default_threads()
+    K = native.grid_ints32(W.X, W.q)
     g = np.random.default_rng(7)
-    rows = rows_hint or 64
+    rows = rows_hint or 4 * threads
     xs = g.choice(W.n, rows, replace=False)
     t0 = time.perf_counter()
-    native.rng_rows(W.X, W.q, xs, threads=threads)
+    native.rng_rows_compact(W.X, W.q, xs, threads=threads, upper=True, K=K)
     dt = time.perf_counter() - t0
-    if not rows_hint and dt < 5.0:   # grow to roughly 10-30 s of CPU work
-        rows = int(min(W.n, max(rows, rows * 12.0 / max(dt, 1e-3))))
+    if not rows_hint and dt < target_s / 3:   # grow to about target_s of CPU work
+        rows = int(min(W.n, max(rows, rows * target_s / max(dt, 1e-3))))
         xs = g.choice(W.n, rows, replace=False)
         t0 = time.perf_counter()
-        native.rng_rows(W.X, W.q, xs, threads=threads)
+        native.rng_rows_compact(W.X, W.q, xs, threads=threads, upper=True, K=K)
         dt = time.perf_counter() - t0
-    est = dt * W.n / rows
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": "RNG rows of %d random points (each row scans all %d points), %.2f s measured, "
-                      "scaled by N/rows to the full build" % (rows, W.n, dt)}
+    return {"value": dt * W.n / rows, "unit": "s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": "RNG rows of %d random points, each deciding its neighbours y > x over all %d points "
+                      "(as the full oracle does), %.2f s measured on %d threads, scaled by N/rows to the "
+                      "full build" % (rows, W.n, dt, threads)}
 
 
 def query_throughput(idx, W, nq: int) -> dict:
@@ -225,6 +252,117 @@ def query_throughput(idx, W, nq: int) -> dict:
             "witness_tests_per_query": st["witness_tests"] / nq}
 
 
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="subspace3", choices=["subspace3", "clustered", "clustered96", "insert"])
+    ap.add_argument("--precision", type=int, default=-1, help="0 = float64 everywhere, 1 = float32 screens "
+                    "(the plain float32 form), 2 = bf16 tiles; -1 = the workload's form (2 for subspace3, "
+                    "else 1)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the comparison builds of the other forms")
+    ap.add_argument("--autotune", type=int, default=1, help="1: the index autotunes its witness-pivot counts on "
+                    "the first (warmup) build")
+    ap.add_argument("--vgrng-pivots", type=int, default=0, help="Proposition 1 witness pivots per block (autotune 0)")
+    ap.add_argument("--stage4-pivots", type=int, default=0, help="Stage IV pivot witnesses (autotune 0)")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle rows for the CPU baseline (0 = auto)")
+    ap.add_argument("--queries", type=int, default=4096, help="clustered: queries timed against the built index")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (scales rocprofv3 FETCH/WRITE counters)")
+    ap.add_argument("--attainable", action="store_true",
+                    help="only measure attainable peaks: device copy bandwidth and a float64 library GEMM")
+    return ap.parse_args()
+
+
+def workload_of(name):
+    import synth
+    if name == "subspace3":
+        W = synth.subspace3()
+        sizes = [len(L.pivot_ids) for L in W.layers]
+        desc = ("three-layer GRNG->GRNG->RNG, N=%d, D=%d near an 8-D subspace (noise 0.01), %d coarse and %d fine "
+                "pivots" % (W.n, W.d, sizes[0], sizes[1]))
+    elif name == "clustered96":
+        W = synth.clustered(n=1_000_000, d=96, clusters=256, sigma=1.0, m=10_000, knn=100, q=18)
+        desc = "two-layer GRNG->RNG, N=%d, D=96, 256 Gaussian clusters (sigma 1.0), 10,000 pivots with 100-NN radii" % W.n
+    else:
+        W = synth.clustered()
+        desc = ("two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), 1,000 random pivots with 100-NN "
+                "radii" % W.n)
+    return W, desc
+
+
+class Builder:
+    """One index over device-resident points and pivot layers; step() builds
+    every layer and the RNG (timed with device events on the current stream)."""
+
+    def __init__(self, P, W, **kw):
+        import torch
+        self.torch = torch
+        self.X = torch.from_numpy(W.X).cuda()
+        self.layers = [(torch.from_numpy(L.pivot_ids).cuda(), torch.from_numpy(L.radii).cuda()) for L in W.layers]
+        self.idx = P.Index(self.X, grid_exp=W.q, **kw)
+
+    def step(self):
+        for level, (pid, rad) in enumerate(self.layers):
+            self.idx.build_grng_layer(level, pid, rad)
+        self.idx.build_rng()
+
+    def timed(self):
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        self.step()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+
+def other_form(P, W, precision, st, witness_order=0, scorer=None):
+    """One warmed-up build of another form with the witness-pivot counts the
+    timed index settled on: (ms, edges as a host array, stats)."""
+    b = Builder(P, W, precision=precision, autotune=0, witness_order=witness_order,
+                vgrng_pivots=int(st["vgrng_pivots"]), stage4_pivots=int(st["stage4_pivots"]))
+    if scorer is not None:
+        b.idx.set_scorer(scorer)
+    b.step()
+    ms = b.timed()
+    E = b.idx.edges().cpu().numpy()
+    s2 = b.idx.stats()
+    b.idx.close()
+    return ms, E, s2
+
+
+def form_entry(ms, st, same, base_ms):
+    return {"ms": ms, "speedup_vs_plain": base_ms / ms, "identical_edges": bool(same),
+            "exhaustive_pairs": st["exhaustive_pairs"], "lune_tests": st["lune_tests"], "rechecks": st["rechecks"],
+            "screen_uncertain": st["screen_uncertain"], "ms_pairs": st["ms_pairs"], "ms_lune": st["ms_lune"]}
+
+
+def train_scorer(P):
+    """Scorer trained on witness-cell logs of the 100k x 16-D build and of a
+    small 2-D build (the learned form's training set)."""
+    import numpy as np
+    import torch
+
+    import synth
+    feats, labels = [], []
+    for W in (synth.clustered(), synth.clustered(n=20000, d=2, clusters=16, m=200, knn=50, q=19, sub=3)):
+        b = Builder(P, W, precision=1)
+        b.step()
+        f, lab = b.idx.log_witness_cells(20000)
+        feats.append(f)
+        labels.append(lab)
+        b.idx.close()
+    feats, labels = torch.cat(feats), torch.cat(labels)
+    theta = torch.from_numpy((np.random.default_rng(1).standard_normal(P.mlp_params()) * 0.1)
+                             .astype(np.float32)).cuda()
+    t0 = time.perf_counter()
+    loss = P.mlp_train(theta, feats, labels, steps=400, lr=3e-3)
+    return theta, {"samples": int(feats.shape[0]), "loss": loss, "train_s": time.perf_counter() - t0}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,62 +380,64 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_mib": args.copy_calibration_mb, "copies": 3}))
         return
-
     if args.attainable:
         print(json.dumps(attainable_peaks(torch)))
         return
+    if args.workload == "insert":
+        return bench_insert(args)
 
-    import synth
     import paper_2208_10022_amd as P
 
-    dev = torch.device("cuda:0")
-    W = synth.subspace3() if args.workload == "subspace3" else synth.clustered(n=args.n)
-    X = torch.from_numpy(W.X).to(dev)
-    layers = [(torch.from_numpy(L.pivot_ids).to(dev), torch.from_numpy(L.radii).to(dev)) for L in W.layers]
-    torch.cuda.synchronize()
-
-    def step(idx):
-        for level, (pid, rad) in enumerate(layers):
-            idx.build_grng_layer(level, pid, rad)
-        idx.build_rng()
-
-    idx = P.Index(X, grid_exp=W.q, precision=args.precision, autotune=args.autotune,
-                  vgrng_pivots=args.vgrng_pivots, stage4_pivots=args.stage4_pivots)
+    prec = args.precision if args.precision >= 0 else (2 if args.workload == "subspace3" else 1)
+    W, desc = workload_of(args.workload)
+    scorer, train = None, None
+    if args.workload == "clustered96":
+        scorer, train = train_scorer(P)
+    b = Builder(P, W, precision=prec, autotune=args.autotune, vgrng_pivots=args.vgrng_pivots,
+                stage4_pivots=args.stage4_pivots)
     if args.autotune and args.warmup < 1:
         print("--autotune needs at least one warmup step (the tuning runs there)", file=sys.stderr)
         sys.exit(2)
     for _ in range(args.warmup):
-        step(idx)
+        b.step()
     torch.cuda.synchronize()
-    times, stats = [], []
-    stream = torch.cuda.current_stream()
+    times = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        step(idx)
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-        stats.append(idx.stats())
+        times.append(b.timed())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms = float(np.median(times))
-    st = stats[-1]
-    edges = idx.num_edges()
-    queries = query_throughput(idx, W, args.queries) if args.queries > 0 else None
-    idx.close()
+    st = b.idx.stats()
+    E = b.idx.edges().cpu().numpy()
+    queries = query_throughput(b.idx, W, args.queries) if args.workload == "clustered" and args.queries else None
+    b.idx.close()
+
+    forms = None
+    if not args.no_forms:
+        forms = {"plain_float32": None}
+        if prec == 1:
+            base_ms, base_st = ms, st
+        else:
+            base_ms, E1, base_st = other_form(P, W, 1, st)
+            forms["plain_float32"] = form_entry(base_ms, base_st, np.array_equal(E1, E), base_ms)
+        if prec == 2:
+            forms["bf16"] = form_entry(ms, st, forms["plain_float32"]["identical_edges"], base_ms)
+        elif args.workload == "clustered":
+            ms2, E2, st2 = other_form(P, W, 2, st)
+            forms["bf16"] = form_entry(ms2, st2, np.array_equal(E2, E), base_ms)
+        if args.workload == "clustered96":
+            forms["plain_float32"] = form_entry(ms, st, True, ms)
+            ms_l, E_l, st_l = other_form(P, W, 1, st, witness_order=P.ORDER_LEARNED, scorer=scorer)
+            forms["learned"] = form_entry(ms_l, st_l, np.array_equal(E_l, E), ms)
+            forms["learned"]["scorer"] = train
+            ms_u, E_u, st_u = other_form(P, W, 1, st, witness_order=P.ORDER_LUNE)
+            forms["lune_order"] = form_entry(ms_u, st_u, np.array_equal(E_u, E), ms)
+        if forms["plain_float32"] is None:
+            forms["plain_float32"] = form_entry(base_ms, base_st, True, base_ms)
 
     sizes = [int(len(L.pivot_ids)) for L in W.layers]
-    if args.workload == "subspace3":
-        workload = "subspace3-n%d-d%d-m%d-p%d" % (W.n, W.d, sizes[-1], args.precision)
-        described = ("three-layer GRNG->GRNG->RNG, N=%d, D=%d near an 8-D subspace, %d coarse and %d fine "
-                     "pivots" % (W.n, W.d, sizes[0], sizes[-1]))
-    else:
-        workload = "clustered-n%d-d16-m1000-p%d" % (W.n, args.precision)
-        described = ("two-layer GRNG->RNG, N=%d, D=16, 32 Gaussian clusters (sigma 0.5), 1,000 random pivots with "
-                     "100-NN radii" % W.n)
+    workload = "%s-n%d-d%d-m%s-p%d" % (args.workload, W.n, W.d, "-".join(map(str, sizes)), prec)
     line = {
         "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
         "value": ms / 1000.0,
@@ -309,16 +449,16 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32",
+        "dtype": PRECISION_DTYPE[prec],
         "data": "synthetic",
-        "config": {"workload": described,
-                   "n": W.n, "d": W.d, "pivots": sizes[-1] if len(sizes) == 1 else sizes, "grid_exp": W.q,
-                   "precision": "float64 distances" if args.precision == 0 else
-                   "float32 screens, float64 re-decision of doubtful comparisons"},
-        "edges": edges,
+        "config": {"workload": desc, "n": W.n, "d": W.d, "pivots": sizes if len(sizes) > 1 else sizes[0],
+                   "grid_exp": W.q, "precision": PRECISION_NAMES[prec]},
+        "edges": int(st["n_edges"]),
+        "forms": forms,
         "witness_tests": st["witness_tests"],
         "witness_tests_per_s": st["witness_tests"] / (ms / 1000.0),
         "lune_tests_per_s": st["lune_tests"] / (st["ms_lune"] / 1000.0) if st["ms_lune"] > 0 else None,
+        "stage4_tests_per_s": st["candidate_pairs"] * st["stage4_pivots"] / (st["ms_pairs"] / 1000.0),
         # the work pruning avoids: every pair, and every (pair, witness) test
         "dense_pairs": W.n * (W.n - 1) // 2,
         "dense_tests": W.n * (W.n - 1) * (W.n - 2) // 2,
@@ -328,24 +468,75 @@ def main():
         "exhaustive_pairs": st["exhaustive_pairs"],
         "lune_tests": st["lune_tests"],
         "rechecks": st["rechecks"],
+        "screen_uncertain": st["screen_uncertain"],
         "tile_pairs": st["tile_pairs"],
         "vgrng_pivots": st["vgrng_pivots"],
         "stage4_pivots": st["stage4_pivots"],
         "ms_autotune_once": st["ms_autotune"],
         "orphans": st["orphans"],
-        "ms_layer": st["ms_layers"],
+        "ms_layers_last": st["ms_layers"],
         "ms_rng": st["ms_rng"],
         "ms_vgrng": st["ms_vgrng"],
         "ms_pair_masks": st["ms_pair_masks"],
         "ms_pairs": st["ms_pairs"],
         "ms_lune": st["ms_lune"],
         "queries": queries,
-        "roofline": roofline(st, workload),
-        "kernels": kernel_rooflines(st),
+        "roofline": roofline(st, W.d, prec, workload),
+        "kernels": kernel_rooflines(st, W.d, prec),
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, args.cpu_rows)
+    print(json.dumps(line), flush=True)
+
+
+def bench_insert(args):
+    """64 batches (log-uniform sizes in [1,000, 50,000]) into the 100k x 16-D
+    index: incremental insertion against a rebuild from scratch after every
+    batch, edges compared in full."""
+    import numpy as np
+    import torch
+
+    import paper_2208_10022_amd as P
+    import synth
+    W, desc = workload_of("clustered")
+    batches = synth.insert_batches(W)
+    b = Builder(P, W, precision=1)
+    b.step()
+    tune = b.idx.stats()
+    ins_ms, reb_ms, same = [], [], True
+    allX = [W.X]
+    for B in batches:
+        Bd = torch.from_numpy(B).cuda()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.idx.insert_batch(Bd)
+        e1.record()
+        e1.synchronize()
+        ins_ms.append(e0.elapsed_time(e1))
+        allX.append(B)
+        Wb = synth.Workload(name="all", X=np.vstack(allX), q=W.q, layers=W.layers)
+        r = Builder(P, Wb, precision=1, autotune=0, vgrng_pivots=int(tune["vgrng_pivots"]),
+                    stage4_pivots=int(tune["stage4_pivots"]))
+        r.step()
+        reb_ms.append(r.timed())
+        same = same and np.array_equal(r.idx.edges().cpu().numpy(), b.idx.edges().cpu().numpy())
+        r.idx.close()
+    n_final = b.idx.stats()["n_points"]
+    b.idx.close()
+    total = sum(ins_ms)
+    line = {
+        "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
+        "value": total / 1000.0, "unit": "s", "n_gpus": 1, "steps": len(batches), "warmup": 1,
+        "ms_per_step": total / len(batches), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "64 insertion batches (sizes log-uniform in [1000, 50000]) into the " + desc,
+                   "n_final": int(n_final), "precision": PRECISION_NAMES[1]},
+        "forms": {"batched_insert_total_ms": total, "rebuild_total_ms": sum(reb_ms),
+                  "speedup_vs_rebuild": sum(reb_ms) / total, "identical_edges_after_every_batch": bool(same),
+                  "insert_ms": ins_ms, "rebuild_ms": reb_ms},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -114,7 +114,10 @@ typedef struct grng_stats {
     int64_t stage4_pivots;        /* Stage IV pivot witnesses used by the last build */
     int64_t unsorted_cell_rows;   /* rows of the last build whose witness-cell list was longer than the
                                      4,096 entries sorted on chip, and was scanned in pivot order */
-    double distance_computations; /* squared distances produced (the paper's cost unit, Section 1) */
+    double distance_computations; /* squared distances produced (the paper's cost unit, Section 1): every
+                                     point-pivot entry, every entry of the pair kernel's distance tiles
+                                     (D(T,U), the pivot blocks, D(T,T), D(U,U) when computed) and two per
+                                     witness test of the exhaustive scan (plus one per witness cell's pivot) */
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
     double stage4_survivors;      /* pairs left after pivot witnesses (Stage IV) */
@@ -144,6 +147,10 @@ typedef struct grng_stats {
     double screen_uncertain;      /* GRNG_PREC_BF16: pairs the pair kernel passed on to the exhaustive scan
                                      although an in-tile witness lay within the bf16 tiles' error bound (the scan
                                      re-decides them exactly); 0 in the other modes */
+    double pair_tile_entries;     /* entries of the pair kernel's distance tiles computed in the last build:
+                                     D(T,U), the pivot blocks, and D(U,U), D(T,T) where Stage V ran */
+    double pair_method_distances; /* of those, the ones the method uses: candidate pairs' d(x,y), the pivot
+                                     blocks and the Stage V witness matrices */
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

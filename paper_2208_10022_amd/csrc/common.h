@@ -178,6 +178,9 @@ enum Counter {
     C_TTV,            // D(T,T) computations (not repeated while consecutive tile pairs share T)
     C_UNSORTED,       // rows whose witness-cell list exceeded the sort capacity
     C_UNCERTAIN,      // bf16 pair kernel: survivors with an in-tile witness within the error bound
+    C_PD_TU,          // pair kernels: entries of D(T,U) computed
+    C_PD_PIV,         // pair kernels: entries of the pivot blocks D(T,P), D(U,P) computed
+    C_PD_V,           // pair kernels: entries of the Stage V witness matrices D(U,U), D(T,T) computed
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,
@@ -357,6 +360,14 @@ constexpr int kPivWitness = 16;   // pivot witnesses per tile pair in the tiled 
 void launch_pivot_knn(hipStream_t s, int64_t m, const double *dpp2, int32_t K, int32_t *pknn);   // pknn [m][16]
 void launch_tile_vmask(hipStream_t s, int64_t ntiles, const int32_t *tiles, const uint64_t *v_rows, int32_t words,
                        uint64_t *tv);
+// Tile pairs are listed in cells (row tile T, block of 64 indexed tiles),
+// cells ordered by blocks of kTilePairBlockT row tiles (see k_tile_pairs);
+// pass 0 (off == null) counts per cell into cnt[tile_pair_cells(ntA, ntB)],
+// zeroed beforehand; pass 1 writes the pairs at the scanned cell offsets.
+constexpr int kTilePairBlockT = 16;
+inline int64_t tile_pair_cells(int64_t ntA, int64_t ntB) {
+    return (ntA + kTilePairBlockT - 1) / kTilePairBlockT * kTilePairBlockT * ((ntB + 63) / 64);
+}
 void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const uint64_t *tvA, const uint8_t *newA,
                        int64_t ntB, const int32_t *tilesB, const uint64_t *tvB, const uint8_t *newB, int32_t words,
                        int mode, const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU);

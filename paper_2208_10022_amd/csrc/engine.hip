@@ -348,6 +348,7 @@ void trace(const char *stage, double ms, int64_t count) {
 struct BuildTimes {
     double vgrng = 0, masks = 0, pairs = 0, lune = 0;
     int64_t tile_pairs = 0;
+    double host_dist = 0;   // squared distances of whole tables (point-pivot D_XP) computed on the way
 };
 
 // Pivot-side tables of the finest layer (coordinates, nearest pivots).
@@ -395,6 +396,7 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     // A1: exact point-pivot distances (MFMA f64 tiles), input order [n][m].
     P.dxp.alloc(sizeof(double) * (size_t)(n * m));
     launch_dist2(s, X, nrm, n, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, P.dxp.as<double>(), m, true);
+    bt.host_dist += (double)n * (double)m;
     // A2: parent counts, home cell, cell radius.
     DevBuf home, d2home, npar, d2vor, gcount, second;
     home.alloc(4 * (size_t)n);
@@ -587,15 +589,17 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     const int32_t K = stage4_pivots(idx);
     uint64_t *ctr = idx->counters.as<uint64_t>();
     DevBuf tcnt, toff, tpT, tpU;
-    tcnt.alloc(4 * (size_t)std::max<int64_t>(A.ntiles, 1));
-    toff.alloc(8 * (size_t)(A.ntiles + 1));
+    const int64_t ncell = tile_pair_cells(A.ntiles, B.ntiles);
+    tcnt.alloc(4 * (size_t)std::max<int64_t>(ncell, 2));
+    zero(tcnt, s);
+    toff.alloc(8 * (size_t)(ncell + 1));
     const bool with_new = (mode & PM_NEW_ONLY) != 0;
     const uint8_t *na = with_new ? A.tnew.as<uint8_t>() : nullptr, *nb = with_new ? B.tnew.as<uint8_t>() : nullptr;
     launch_tile_pairs(s, A.ntiles, A.tiles.as<int32_t>(), A.tv.as<uint64_t>(), na, B.ntiles, B.tiles.as<int32_t>(),
                       B.tv.as<uint64_t>(), nb, words, mode, nullptr, tcnt.as<int32_t>(), nullptr, nullptr);
-    launch_scan_i32_to_i64(s, tcnt.as<int32_t>(), A.ntiles, toff.as<int64_t>());
+    launch_scan_i32_to_i64(s, tcnt.as<int32_t>(), ncell, toff.as<int64_t>());
     std::vector<int64_t> ntp_h;
-    d2h(ntp_h, toff.as<int64_t>() + A.ntiles, 1, s);
+    d2h(ntp_h, toff.as<int64_t>() + ncell, 1, s);
     const int64_t ntp = ntp_h[0];
     tpT.alloc(4 * (size_t)std::max<int64_t>(ntp, 1));
     tpU.alloc(4 * (size_t)std::max<int64_t>(ntp, 1));
@@ -763,7 +767,7 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.vgrng_pivots = idx->layers.empty() ? 0 : vgrng_pivots(idx, idx->layers.back().m);
     idx->stats.stage4_pivots = idx->layers.empty() ? 0 : stage4_pivots(idx);
     idx->stats.ms_autotune = idx->ms_tune;
-    idx->stats.distance_computations = (double)c[C_DIST];
+    idx->stats.distance_computations = (double)c[C_DIST] + bt.host_dist;
     idx->stats.witness_tests = (double)c[C_WTEST];
     idx->stats.candidate_pairs = (double)c[C_CAND];
     idx->stats.stage4_survivors = (double)c[C_S4];
@@ -771,6 +775,8 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.exhaustive_pairs = (double)c[C_SURV];
     idx->stats.lune_tests = (double)c[C_LUNE];
     idx->stats.screen_uncertain = (double)c[C_UNCERTAIN];
+    idx->stats.pair_tile_entries = (double)(c[C_PD_TU] + c[C_PD_PIV] + c[C_PD_V]);
+    idx->stats.pair_method_distances = (double)(c[C_CAND] + c[C_PD_PIV] + c[C_PD_V]);
     // Bytes a witness test reads: the witness row and its cell-distance
     // bound (float32 with the float32 screen, float64 otherwise); a test
     // that ends early on a partial sum reads less.

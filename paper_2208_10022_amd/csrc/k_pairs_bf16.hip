@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     __shared__ float s_tau4, s_tau5;
     const bool self = (mode & PM_SELF) != 0;
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nunc = 0;
-    uint64_t ndist = 0;
+    uint64_t dtu = 0, dpv = 0, dv = 0;   // tile entries computed (thread 0)
     WaveOut wo;
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
@@ -417,12 +417,15 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             }
         }
         __syncthreads();
-        if (tid == 0) ndist += (uint64_t)lTn * (uint64_t)lUn + (uint64_t)(lTn + lUn) * (uint64_t)K;
+        if (tid == 0) {
+            dtu += (uint64_t)lTn * (uint64_t)lUn;
+            dpv += (uint64_t)(lTn + lUn) * (uint64_t)K;
+        }
         if (!s_any) continue;   // uniform
         ntpv += tid == 0;
         // 2c. D(U,U) and, when T's points may witness, D(T,T), over the pivot
         // region (two blocks of each per wave).
-        if (tid == 0) ndist += (uint64_t)lUn * lUn + (self ? (uint64_t)lTn * lTn : 0);
+        if (tid == 0) dv += (uint64_t)lUn * lUn + (self ? (uint64_t)lTn * lTn : 0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int id = 2 * w + q;
@@ -477,7 +480,12 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         if (nunc) atomicAdd(&counters[C_UNCERTAIN], (unsigned long long)nunc);
         if (ntpv) atomicAdd(&counters[C_TPV], (unsigned long long)ntpv);
         if (ntpv && self) atomicAdd(&counters[C_TTV], (unsigned long long)ntpv);
-        if (w == 0 && ndist) atomicAdd(&counters[C_DIST], (unsigned long long)ndist);
+        if (w == 0) {
+            atomicAdd(&counters[C_DIST], (unsigned long long)(dtu + dpv + dv));
+            atomicAdd(&counters[C_PD_TU], (unsigned long long)dtu);
+            atomicAdd(&counters[C_PD_PIV], (unsigned long long)dpv);
+            atomicAdd(&counters[C_PD_V], (unsigned long long)dv);
+        }
     }
 }
 

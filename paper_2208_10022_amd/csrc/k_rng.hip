@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const bool self = (mode & PM_SELF) != 0;
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nttv = 0;
+    uint64_t ndist = 0, dtu = 0, dpv = 0, dv = 0;   // tile entries computed (thread 0)
     WaveOut wo;
     __shared__ int64_t s_tp;
     __shared__ int s_any;
@@ -436,6 +437,10 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             }
         }
         __syncthreads();
+        if (tid == 0) {
+            dtu += (uint64_t)lT * (uint64_t)lU;
+            dpv += (uint64_t)(lT + lU) * (uint64_t)K;
+        }
         if (!s_any) continue;   // uniform: no Stage IV survivor in this tile pair
         ntpv += tid == 0;
         // 2c. D(U,U), written over the pivot data, which is dead now, and
@@ -446,6 +451,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             const bool need_tt = self && sT != tt_start;
             if (need_tt && keep_tt) tt_start = sT;
             nttv += need_tt && tid == 0;
+            if (tid == 0) dv += (uint64_t)lU * lU + (need_tt ? (uint64_t)lT * lT : 0);
             const bool us = !need_tt || w >= 4;
             const int nh = need_tt ? 2 : 1;
             const double *sa[2], *na[2];
@@ -516,6 +522,13 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
         if (ntpv) atomicAdd(&counters[C_TPV], (unsigned long long)ntpv);
         if (nttv) atomicAdd(&counters[C_TTV], (unsigned long long)nttv);
+        if (w == 0) {
+            ndist = dtu + dpv + dv;
+            atomicAdd(&counters[C_DIST], (unsigned long long)ndist);
+            atomicAdd(&counters[C_PD_TU], (unsigned long long)dtu);
+            atomicAdd(&counters[C_PD_PIV], (unsigned long long)dpv);
+            atomicAdd(&counters[C_PD_V], (unsigned long long)dv);
+        }
     }
 }
 
@@ -551,38 +564,50 @@ __global__ void k_tile_vmask(int64_t ntiles, const int32_t *tiles, const uint64_
     tv[e] = acc;
 }
 
+// Tile pairs in blocked order.  Cell (T, Ub) holds the pairs of row tile T
+// with the indexed tiles of the 64-wide block Ub; cells are ordered by blocks
+// of kTilePairBlockT consecutive row tiles, then Ub, then T:
+//     cell index ((T / kTilePairBlockT) * nUb + Ub) * kTilePairBlockT + T % kTilePairBlockT.
+// The pair kernel's workgroups claim consecutive chunks of this list, so
+// those running together on one XCD work on the same 64 indexed tiles, whose
+// rows are then read from that XCD's L2 instead of memory (row-major order
+// would spread them over a thousand different indexed tiles), while each
+// workgroup still keeps its row tile in LDS over a cell's pairs.
+// Pass 0 (off == null) writes each cell's pair count (cells never visited
+// must be zero beforehand); pass 1 writes the pairs at the scanned offsets.
 __global__ __launch_bounds__(64) void k_tile_pairs(int64_t ntA, const int32_t *tilesA, const uint64_t *tvA,
                                                    const uint8_t *newA, int64_t ntB, const int32_t *tilesB,
                                                    const uint64_t *tvB, const uint8_t *newB, int32_t words, int mode,
-                                                   const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
+                                                   int64_t nUb, const int64_t *off, int32_t *cnt, int32_t *oT,
+                                                   int32_t *oU) {
     const int lane = threadIdx.x;
     const int64_t T = blockIdx.x;
     const int32_t a = tilesA[3 * T + 2];
     const bool tnew = newA ? newA[T] != 0 : false;
-    int64_t pos = off ? off[T] : 0;
-    int c = 0;
-    for (int64_t u0 = (mode & PM_SELF) ? T : 0; u0 < ntB; u0 += 64) {
-        const int64_t U = u0 + lane;
+    const bool self = (mode & PM_SELF) != 0;
+    const int64_t cbase = (T / kTilePairBlockT) * nUb * kTilePairBlockT + T % kTilePairBlockT;
+    for (int64_t ub = self ? T / 64 : 0; ub < nUb; ++ub) {
+        const int64_t U = ub * 64 + lane;
         bool keep = false;
-        if (U < ntB) {
+        if (U < ntB && (!self || U >= T)) {
             const int32_t b = tilesB[3 * U + 2];
             // Cell b must survive the virtual-pivot test of some point of T; when
             // the row points are indexed points (their cell balls contain them),
             // cell a must also survive the test of some point of U.
             keep = (tvA[T * words + (b >> 6)] >> (b & 63)) & 1ull;
-            if (keep && (mode & PM_SELF)) keep = (tvB[U * words + (a >> 6)] >> (a & 63)) & 1ull;
+            if (keep && self) keep = (tvB[U * words + (a >> 6)] >> (a & 63)) & 1ull;
             if ((mode & PM_NEW_ONLY) && !tnew && !newB[U]) keep = false;
         }
         const uint64_t m = __ballot(keep);
-        if (off && keep) {
-            const int64_t slot = pos + __popcll(m & ((1ull << lane) - 1ull));
+        const int64_t c = cbase + ub * kTilePairBlockT;
+        if (!off) {
+            if (lane == 0) cnt[c] = __popcll(m);
+        } else if (keep) {
+            const int64_t slot = off[c] + __popcll(m & ((1ull << lane) - 1ull));
             oT[slot] = (int32_t)T;
             oU[slot] = (int32_t)U;
         }
-        pos += __popcll(m);
-        c += __popcll(m);
     }
-    if (!off && lane == 0) cnt[T] = c;
 }
 
 // The K nearest pivots of each pivot (itself first), ties by index; K > m
@@ -1181,8 +1206,9 @@ void launch_tile_pairs(hipStream_t s, int64_t ntA, const int32_t *tilesA, const 
                        int64_t ntB, const int32_t *tilesB, const uint64_t *tvB, const uint8_t *newB, int32_t words,
                        int mode, const int64_t *off, int32_t *cnt, int32_t *oT, int32_t *oU) {
     if (ntA == 0) return;
-    k_tile_pairs<<<(unsigned)ntA, 64, 0, s>>>(ntA, tilesA, tvA, newA, ntB, tilesB, tvB, newB, words, mode, off, cnt, oT,
-                                              oU);
+    const int64_t nUb = div_up(ntB, 64);
+    k_tile_pairs<<<(unsigned)ntA, 64, 0, s>>>(ntA, tilesA, tvA, newA, ntB, tilesB, tvB, newB, words, mode, nUb, off,
+                                              cnt, oT, oU);
     GRNG_LAUNCHED();
 }
 
