@@ -100,9 +100,29 @@ typedef struct grng_options {
                               cell, 0 = default (256), values >= the layer size use every pivot.  Any subset
                               of pivots is a valid witness set (fewer only prunes less), so edges never
                               depend on it. */
+    int32_t metric;        /* GRNG_METRIC_*: the distance of the RNG (0 = Euclidean) */
+    int32_t graph;         /* GRNG_GRAPH_*: the empty-region graph to build (0 = RNG) */
     int32_t reserved_i[1]; /* must be 0 */
-    uint64_t reserved[4];  /* must be 0 */
+    uint64_t reserved[3];  /* must be 0 */
 } grng_options;
+
+/* Other metrics and empty-region graphs (Section 1: a general metric space;
+ * the RNG is one of a family of empty-region graphs).  They are built by the
+ * exhaustive path only: an index with metric != GRNG_METRIC_L2 or graph !=
+ * GRNG_GRAPH_RNG takes no pivot layer (grng_build_grng_layer returns
+ * GRNG_EINVAL), and build_rng, insert_batch and query_neighbors test every
+ * pair against every point (at most 65,535 points, as for the Euclidean RNG
+ * without a layer).  Under the grid contract every L1 and L-infinity
+ * distance is exact in float64, so the decisions stay exact. */
+enum {
+    GRNG_METRIC_L2 = 0,   /* Euclidean */
+    GRNG_METRIC_L1 = 1,   /* sum of absolute coordinate differences */
+    GRNG_METRIC_LINF = 2  /* largest absolute coordinate difference */
+};
+enum {
+    GRNG_GRAPH_RNG = 0,     /* u, v linked iff no z has max(d(u,z), d(v,z)) < d(u,v) */
+    GRNG_GRAPH_GABRIEL = 1  /* Euclidean only: u, v linked iff no z has d(u,z)^2 + d(v,z)^2 < d(u,v)^2 */
+};
 
 typedef struct grng_stats {
     int64_t n_points;             /* points currently indexed */

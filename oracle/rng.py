@@ -10,6 +10,11 @@ the same decision since squaring is monotone on non-negative numbers.  Ties
 
 Gabriel graph (Section 1): u and v are linked iff for every other z,
 d^2(z,u) + d^2(z,v) >= d^2(u,v).
+
+Other metrics (the paper's setting is a general metric space, Section 1):
+``rng_edges_metric`` applies the same RNG definition with the L1 (sum of
+absolute differences) or L-infinity (largest absolute difference) distance,
+again on exact integers.
 """
 from __future__ import annotations
 
@@ -95,3 +100,49 @@ def nearest_neighbour(K: np.ndarray) -> np.ndarray:
 def average_degree(num_edges: int, n: int) -> float:
     """Average degree of an undirected graph: each edge adds one to two degrees."""
     return 2.0 * num_edges / n
+
+
+def metric_dists(K: np.ndarray, metric: str) -> np.ndarray:
+    """All pairwise distances of integer points, exact: 'l1' = sum of |differences|,
+    'linf' = largest |difference|, 'l2sq' = squared Euclidean distance."""
+    K = np.asarray(K, dtype=np.int64)
+    n = K.shape[0]
+    out = np.zeros((n, n), dtype=np.int64)
+    for t in range(K.shape[1]):
+        diff = np.abs(K[:, t][:, None] - K[:, t][None, :])
+        if metric == "l1":
+            out += diff
+        elif metric == "linf":
+            out = np.maximum(out, diff)
+        elif metric == "l2sq":
+            out += diff * diff
+        else:
+            raise ValueError(metric)
+    return out
+
+
+def rng_edges_metric(K: np.ndarray, metric: str) -> np.ndarray:
+    """RNG under another metric: (u, v) linked iff no z has max(d(u,z), d(v,z)) < d(u,v)."""
+    n = K.shape[0]
+    D = metric_dists(K, metric)
+    out = []
+    for u in range(n - 1):
+        v = np.arange(u + 1, n)
+        duv = D[u, v]
+        witness = (D[u][None, :] < duv[:, None]) & (D[v] < duv[:, None])
+        alive = ~witness.any(axis=1)
+        out.extend((u, int(w)) for w in v[alive])
+    return np.asarray(out, dtype=np.int64).reshape(-1, 2)
+
+
+def rng_edges_metric_loops(K, metric: str) -> list:
+    """Loop-only version of rng_edges_metric for tiny inputs (Python integers)."""
+    pts = [tuple(int(c) for c in row) for row in np.asarray(K)]
+    n = len(pts)
+
+    def dist(a, b):
+        diffs = [abs(x - y) for x, y in zip(pts[a], pts[b])]
+        return sum(diffs) if metric == "l1" else max(diffs, default=0)
+
+    return [(u, v) for u in range(n) for v in range(u + 1, n)
+            if all(max(dist(z, u), dist(z, v)) >= dist(u, v) for z in range(n) if z != u and z != v)]

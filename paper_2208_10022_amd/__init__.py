@@ -19,6 +19,8 @@ STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_ED
                 -5: "GRNG_ECAPACITY", -6: "GRNG_ESTATE"}
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 ORDER_DISTANCE, ORDER_LEARNED, ORDER_LUNE = 0, 1, 2
+METRIC_L2, METRIC_L1, METRIC_LINF = 0, 1, 2
+GRAPH_RNG, GRAPH_GABRIEL = 0, 1
 
 # Entry points declared in include/grng.h (checked by the CPU tests).
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
@@ -37,7 +39,8 @@ class GrngError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("grid_exp", C.c_int32), ("precision", C.c_int32), ("witness_order", C.c_int32),
                 ("use_graph", C.c_int32), ("autotune", C.c_int32), ("stage4_pivots", C.c_int32),
-                ("vgrng_pivots", C.c_int32), ("reserved_i", C.c_int32 * 1), ("reserved", C.c_uint64 * 4)]
+                ("vgrng_pivots", C.c_int32), ("metric", C.c_int32), ("graph", C.c_int32),
+                ("reserved_i", C.c_int32 * 1), ("reserved", C.c_uint64 * 3)]
 
 
 class Stats(C.Structure):
@@ -188,11 +191,12 @@ class Index:
 
     def __init__(self, points, grid_exp: int, precision: int = PREC_FP64, witness_order: int = ORDER_DISTANCE,
                  use_graph: int = 0, autotune: int = 0, stage4_pivots: int = 0, vgrng_pivots: int = 0,
-                 stream=None):
+                 metric: int = METRIC_L2, graph: int = GRAPH_RNG, stream=None):
         self._h = C.c_void_p()
         self._stream = stream
         opt = Options(grid_exp=grid_exp, precision=precision, witness_order=witness_order, use_graph=use_graph,
-                      autotune=autotune, stage4_pivots=stage4_pivots, vgrng_pivots=vgrng_pivots)
+                      autotune=autotune, stage4_pivots=stage4_pivots, vgrng_pivots=vgrng_pivots, metric=metric,
+                      graph=graph)
         n, d = points.shape
         check(lib().grng_create(C.byref(self._h), _dev_ptr(points, "float32", 2), n, d,
                                 _stream_handle(stream), C.byref(opt)))

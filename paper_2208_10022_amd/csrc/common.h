@@ -386,8 +386,11 @@ void launch_pairs_bf16(hipStream_t s, int64_t ntp, const uint64_t *rec, const fl
                        int dp, int32_t K, const float *Xpf, PairList out, uint64_t *work, uint64_t *counters);
 void launch_pairs_exact_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *XA,
                            const double *XB, double *d2, uint64_t *dmax_bits);
+// Exhaustive path: every pair with its distance key (squared Euclidean, L1
+// or L-infinity distance: GRNG_METRIC_*), then every pair against every point
+// for the graph's empty region (GRNG_GRAPH_*).
 void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,
-                      const double *nrmB, int dp, bool self, PairList out, uint64_t *counters);
+                      const double *nrmB, int dp, bool self, int metric, PairList out, uint64_t *counters);
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
@@ -404,7 +407,7 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         uint64_t *work, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
-                     int64_t z_from, uint8_t *alive, uint64_t *counters);
+                     int64_t z_from, int metric, int graph, uint8_t *alive, uint64_t *counters);
 void launch_pair_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *Xh,
                     const double *nrmh, double *d2, uint64_t *dmax_bits);
 void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,

@@ -95,8 +95,12 @@ void check_opts(const grng_options *o) {
     require(o->autotune == 0 || o->autotune == 1, GRNG_EINVAL, "autotune must be 0 or 1");
     require(o->stage4_pivots >= 0 && o->stage4_pivots <= kPivWitness, GRNG_EINVAL, "stage4_pivots must be in [0, 16]");
     require(o->vgrng_pivots >= 0, GRNG_EINVAL, "vgrng_pivots must be >= 0");
+    require(o->metric >= GRNG_METRIC_L2 && o->metric <= GRNG_METRIC_LINF, GRNG_EINVAL, "unknown metric");
+    require(o->graph == GRNG_GRAPH_RNG || o->graph == GRNG_GRAPH_GABRIEL, GRNG_EINVAL, "unknown graph");
+    require(o->graph == GRNG_GRAPH_RNG || o->metric == GRNG_METRIC_L2, GRNG_EINVAL,
+            "the Gabriel graph is defined for the Euclidean metric only");
     require(o->reserved_i[0] == 0, GRNG_EINVAL, "reserved option fields must be 0");
-    for (int t = 0; t < 4; ++t) require(o->reserved[t] == 0, GRNG_EINVAL, "reserved option fields must be 0");
+    for (int t = 0; t < 3; ++t) require(o->reserved[t] == 0, GRNG_EINVAL, "reserved option fields must be 0");
 }
 
 // Validate float32 values on the device: finite, on the 2^-q grid, |k| < 2^24.
@@ -221,6 +225,8 @@ void do_build_layer(grng_index *idx, int32_t layer, const int32_t *pid_dev, cons
     require(layer >= 0, GRNG_EINVAL, "layer must be >= 0");
     require(layer <= (int32_t)idx->layers.size(), GRNG_ESTATE, "layers must be built in order 0, 1, ...");
     require(m >= 1 && m <= idx->n, GRNG_EINVAL, "m must be in [1, n]");
+    require(idx->opt.metric == GRNG_METRIC_L2 && idx->opt.graph == GRNG_GRAPH_RNG, GRNG_EINVAL,
+            "pivot layers guide the Euclidean RNG only; other metrics and graphs are built exhaustively");
     hipStream_t s = idx->stream;
     EventTimer timer(s);
     reset_counters(idx);
@@ -322,14 +328,14 @@ void build_rng_brute(grng_index *idx, DevBuf &edges, int64_t &ne, double &ms_lun
     P.reserve(n * (n - 1) / 2);
     zero(P.count, s);
     launch_pairs_all(s, n, idx->X.as<double>(), idx->nrm.as<double>(), n, idx->X.as<double>(), idx->nrm.as<double>(),
-                     idx->dp, true, P.view(), idx->counters.as<uint64_t>());
+                     idx->dp, true, idx->opt.metric, P.view(), idx->counters.as<uint64_t>());
     const int64_t np = n * (n - 1) / 2;
     DevBuf alive;
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
     launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), n, idx->dp, idx->X.as<double>(),
-                    idx->nrm.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0, alive.as<uint8_t>(),
-                    idx->counters.as<uint64_t>());
+                    idx->nrm.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0, idx->opt.metric,
+                    idx->opt.graph, alive.as<uint8_t>(), idx->counters.as<uint64_t>());
     ms_lune = lt.stop();
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), nullptr, edges, ne);
 }
@@ -905,12 +911,12 @@ void do_query(grng_index *idx, const float *q, int64_t nq, int64_t *offsets, int
         P.reserve(np);
         zero(P.count, s);
         launch_pairs_all(s, nq, Xq.as<double>(), nq2.as<double>(), idx->n, idx->X.as<double>(), idx->nrm.as<double>(),
-                         idx->dp, false, P.view(), idx->counters.as<uint64_t>());
+                         idx->dp, false, idx->opt.metric, P.view(), idx->counters.as<uint64_t>());
         alive.alloc((size_t)std::max<int64_t>(np, 8));
         EventTimer lt(s);
         launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->n, idx->dp,
                         Xq.as<double>(), nq2.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0,
-                        alive.as<uint8_t>(), idx->counters.as<uint64_t>());
+                        idx->opt.metric, idx->opt.graph, alive.as<uint8_t>(), idx->counters.as<uint64_t>());
         bt.lune = lt.stop();
     } else {
         const Layer &L = idx->layers.back();

@@ -673,19 +673,41 @@ __global__ __launch_bounds__(256) void k_pivot_knn_sorted(int64_t m, int32_t cap
     for (int t = threadIdx.x; t < K; t += blockDim.x) pknn[a * K + t] = t < m ? kid[t] : (int32_t)a;
 }
 
+// Distance key of two rows under a metric (GRNG_METRIC_*): the squared
+// Euclidean distance, the L1 or the L-infinity distance, all exact in float64
+// on the grid (every difference, square and partial sum is an integer number
+// of grid units below 2^53).
+__device__ inline double metric_key(const double *__restrict__ a, const double *__restrict__ b, int dp, int metric) {
+    double acc = 0.0;
+    for (int t = 0; t < dp; ++t) {
+        const double e = a[t] - b[t];
+        if (metric == GRNG_METRIC_L2)
+            acc = fma(e, e, acc);
+        else if (metric == GRNG_METRIC_L1)
+            acc += fabs(e);
+        else
+            acc = fmax(acc, fabs(e));
+    }
+    return acc;
+}
+
 // All pairs (no pivot layer): i < j within one set, or every (i, j) across
-// two sets.  Thread per pair, one block row per i.
+// two sets, with their distance keys.  Thread per pair, one block row per i.
 __global__ void k_pairs_all(int64_t nA, const double *__restrict__ XA, const double *__restrict__ nrmA, int64_t nB,
                             const double *__restrict__ XB, const double *__restrict__ nrmB, int dp, int self,
-                            PairList out, unsigned long long *counters) {
+                            int metric, PairList out, unsigned long long *counters) {
     const int64_t i = blockIdx.y;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool keep = j < nB && (!self || j > i);
     double d2 = 0.0;
     if (keep) {
-        double acc = 0.0;
-        for (int t = 0; t < dp; ++t) acc = fma(XA[i * dp + t], XB[j * dp + t], acc);
-        d2 = nrmA[i] + nrmB[j] - 2.0 * acc;
+        if (metric == GRNG_METRIC_L2) {
+            double acc = 0.0;
+            for (int t = 0; t < dp; ++t) acc = fma(XA[i * dp + t], XB[j * dp + t], acc);
+            d2 = nrmA[i] + nrmB[j] - 2.0 * acc;
+        } else {
+            d2 = metric_key(XA + i * dp, XB + j * dp, dp, metric);
+        }
     }
     wave_append(out, keep, (int32_t)i, (int32_t)j, d2);
     const uint32_t c = wave_sum(keep ? 1u : 0u);
@@ -1135,16 +1157,26 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     }
 }
 
-// Lune test against every point (no pivot layer).  One wave per pair.
+// Empty-region test against every point (no pivot layer).  One wave per
+// pair, 64 witnesses per step, a ballot ends the pair at the first point in
+// its region:
+//   RNG      max(d(x,z), d(y,z)) < d(x,y) under the index's metric (distance
+//            keys: squared Euclidean, L1, L-infinity);
+//   Gabriel  d^2(x,z) + d^2(y,z) < d^2(x,y), tested as d^2(x,z) < d^2(x,y) -
+//            d^2(y,z) (exact: a difference of integers below 2^53).
+// Partial sums (or maxima) of non-negative terms only grow, so a partial key
+// at or above the threshold ends a test early.
 __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t *__restrict__ px,
                                                   const int32_t *__restrict__ py, const double *__restrict__ pd2,
                                                   int64_t n, int dp, const double *__restrict__ Xx,
                                                   const double *__restrict__ nrmx, const double *__restrict__ X,
-                                                  const double *__restrict__ nrm, int64_t z_from,
-                                                  uint8_t *__restrict__ alive, unsigned long long *counters) {
+                                                  const double *__restrict__ nrm, int64_t z_from, int metric,
+                                                  int graph, uint8_t *__restrict__ alive,
+                                                  unsigned long long *counters) {
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const bool gabriel = graph == GRNG_GRAPH_GABRIEL;
     uint32_t ntests = 0;
     for (int64_t p = wave0; p < npairs; p += nwaves) {
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
@@ -1157,16 +1189,25 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
             const int64_t z = zb + lane;
             bool wit = false;
             if (z < n) {
-                // exact direct form; partial sums are exact lower bounds
                 const double *zr = X + z * dp;
                 double sx = 0.0, sy = 0.0;
                 for (int c = 0; c < dp; ++c) {
-                    if (c >= 8 && (c & 7) == 0 && !(sx < d2 && sy < d2)) break;
+                    if (c >= 8 && (c & 7) == 0) {
+                        if (gabriel ? !(sx + sy < d2) : !(sx < d2 && sy < d2)) break;
+                    }
                     const double ex = xs[c] - zr[c], ey = ys[c] - zr[c];
-                    sx = fma(ex, ex, sx);
-                    sy = fma(ey, ey, sy);
+                    if (metric == GRNG_METRIC_L2) {
+                        sx = fma(ex, ex, sx);
+                        sy = fma(ey, ey, sy);
+                    } else if (metric == GRNG_METRIC_L1) {
+                        sx += fabs(ex);
+                        sy += fabs(ey);
+                    } else {
+                        sx = fmax(sx, fabs(ex));
+                        sy = fmax(sy, fabs(ey));
+                    }
                 }
-                wit = sx < d2 && sy < d2;
+                wit = gabriel ? (sx < d2 - sy) : (sx < d2 && sy < d2);
                 ++ntests;
             }
             if (__ballot(wit)) { dead = true; break; }
@@ -1250,11 +1291,12 @@ void launch_pairs_tiled(hipStream_t s, int64_t ntp, const uint64_t *rec, const d
 }
 
 void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double *nrmA, int64_t nB, const double *XB,
-                      const double *nrmB, int dp, bool self, PairList out, uint64_t *counters) {
+                      const double *nrmB, int dp, bool self, int metric, PairList out, uint64_t *counters) {
     if (nA == 0 || nB == 0) return;
     require(nA <= 65535, GRNG_EINVAL, "brute-force pair enumeration limited to 65535 row points");
     dim3 g((unsigned)div_up(nB, 256), (unsigned)nA);
-    k_pairs_all<<<g, 256, 0, s>>>(nA, XA, nrmA, nB, XB, nrmB, dp, self ? 1 : 0, out, (unsigned long long *)counters);
+    k_pairs_all<<<g, 256, 0, s>>>(nA, XA, nrmA, nB, XB, nrmB, dp, self ? 1 : 0, metric, out,
+                                  (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
@@ -1325,12 +1367,12 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
 
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
-                     int64_t z_from, uint8_t *alive, uint64_t *counters) {
+                     int64_t z_from, int metric, int graph, uint8_t *alive, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
-    k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, Xx, nrmx, X, nrm, z_from, alive,
-                                                           (unsigned long long *)counters);
+    k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, Xx, nrmx, X, nrm, z_from, metric, graph,
+                                              alive, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 

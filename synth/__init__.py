@@ -34,7 +34,7 @@ import numpy as np
 ROOT_SEED = 2208_10022
 # One child stream per workload family; spawn keys are fixed so that adding a
 # family never changes the inputs of another.
-_FAMILY = {"uniform2d": 0, "clustered": 1, "subspace3": 2, "insert": 3, "mlp": 4}
+_FAMILY = {"uniform2d": 0, "clustered": 1, "subspace3": 2, "insert": 3, "mlp": 4, "subspace_layers": 5}
 
 
 def _stream(family: str, *sub: int) -> np.random.Generator:
@@ -187,6 +187,44 @@ def subspace3(n: int = 1_000_000, d: int = 32, latent: int = 8, noise: float = 0
         r_coarse[i] = np.float32(int(np.partition(tot, kc - 1)[kc - 1]) * 2.0 ** -q)
     layers = [PivotLayer(coarse, r_coarse), PivotLayer(fine, r_fine)]
     return Workload(name=f"subspace_n{n}_d{d}_m{m_coarse}-{m_fine}", X=X, q=q, layers=layers)
+
+
+def subspace_layers(n: int, d: int = 32, latent: int = 8, noise: float = 0.01, ms=(30, 300, 3000),
+                    q: int = 21, sub: int = 0) -> Workload:
+    """The subspace law of ``subspace3`` with any number of nested pivot layers.
+
+    ``ms`` lists the layer sizes coarsest first.  The finest layer is drawn
+    from the points, each coarser layer from the next finer one.  Radii: the
+    finest layer's is the distance to the ceil(n/M)-th nearest other point;
+    a coarser layer's the ceil(M_finer/M)-th smallest of d(p, p') + r(p')
+    over the next finer layer's pivots p' (so its ball wholly holds that many
+    finer balls).  The points depend on (n, d, latent, sub) only, so
+    hierarchies of the same points can be compared; a separate seed stream
+    from ``subspace3``.
+    """
+    ms = [int(m) for m in ms]
+    assert all(a < b for a, b in zip(ms, ms[1:])) and ms[-1] <= n
+    g = _stream("subspace_layers", n, d, latent, sub)   # the points do not depend on the layers
+    B, _ = np.linalg.qr(g.standard_normal((d, latent)))
+    U = g.uniform(0.0, 1.0, size=(n, latent))
+    X = quantize(U @ B.T + noise * g.standard_normal((n, d)), q)
+    Xi = grid_ints(X, q)
+    g = _stream("subspace_layers", n, d, latent, sub, *ms)
+    fine = np.sort(g.choice(n, size=ms[-1], replace=False)).astype(np.int32)
+    r_fine = knn_radii(X, q, fine, min(-(-n // ms[-1]), n - 1))
+    layers = [PivotLayer(fine, r_fine)]
+    for m in reversed(ms[:-1]):
+        finer = layers[0]
+        ids = np.sort(g.choice(finer.pivot_ids, size=m, replace=False)).astype(np.int32)
+        D2 = _sq_dists_to(Xi[finer.pivot_ids], np.searchsorted(finer.pivot_ids, ids))
+        rf = np.rint(finer.radii.astype(np.float64) * 2.0 ** q).astype(np.int64)
+        k = min(-(-len(finer.pivot_ids) // m), len(finer.pivot_ids))
+        rad = np.empty(m, dtype=np.float32)
+        for i in range(m):
+            tot = np.array([_isqrt_ceil(int(v)) for v in D2[i]], dtype=np.int64) + rf
+            rad[i] = np.float32(int(np.partition(tot, k - 1)[k - 1]) * 2.0 ** -q)
+        layers.insert(0, PivotLayer(ids, rad))
+    return Workload(name="subspace_n%d_d%d_m%s" % (n, d, "-".join(map(str, ms))), X=X, q=q, layers=layers)
 
 
 def queries_like(base: Workload, nq: int, sub: int = 0) -> np.ndarray:

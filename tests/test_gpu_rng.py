@@ -329,3 +329,24 @@ def test_failed_allocation_leaves_the_index_unchanged(G, monkeypatch):
     idx.insert_batch(to_dev(B))
     assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), native.rng_edges(np.vstack([W.X, B]), W.q))
     idx.close()
+
+
+_FOUR_LAYER_ORACLE = {}
+
+
+@pytest.mark.parametrize("ms,prec", [((10, 60, 400), 1), ((10, 60, 400), 2), ((6, 40, 200), 0)])
+def test_four_layer_hierarchy_matches_oracle(G, ms, prec):
+    """Three nested pivot layers over the exemplars (a four-layer hierarchy):
+    each finer layer guided by the one above it (Section 3, Theorem 2), the
+    RNG guided by the finest; every layer and the RNG equal the oracle's."""
+    say("four-layer hierarchy n=12000 d=32 layers", ms, "precision", prec)
+    W = synth.subspace_layers(12000, ms=ms)
+    for coarse, fine in zip(W.layers, W.layers[1:]):
+        assert set(coarse.pivot_ids) <= set(fine.pivot_ids)
+    E, lay, st = gpu_edges(G, W.X, W.q, [(L.pivot_ids, L.radii) for L in W.layers], precision=prec)
+    assert st["n_layers"] == 3
+    for l, L in enumerate(W.layers):
+        assert np.array_equal(lay[l], L.pivot_ids[native.grng_edges(W.X[L.pivot_ids], L.radii, W.q)]), l
+    if ms not in _FOUR_LAYER_ORACLE:
+        _FOUR_LAYER_ORACLE[ms] = native.rng_edges(W.X, W.q)
+    assert np.array_equal(E, _FOUR_LAYER_ORACLE[ms])

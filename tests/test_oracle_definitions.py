@@ -203,3 +203,38 @@ def test_to_grid_enforces_the_contract():
     assert exact.to_grid(ok, 0).shape == (1, 31)
     with pytest.raises(ValueError):
         exact.to_grid(np.full((1, 32), 2.0 ** 23), 0)
+
+
+# --- other metrics (RNG under L1 and L-infinity) -------------------------------
+
+def test_metric_rng_hand_computed_case():
+    # u=(0,0), v=(4,0), z=(2,2): d_1(u,z) = 4 is not below d_1(u,v) = 4, so
+    # under L1 all three pairs are linked; under L-infinity d(u,z) = 2 < 4 and
+    # z removes (u,v); Euclidean: sqrt(8) < 4, the same as L-infinity.
+    K = np.array([[0, 0], [4, 0], [2, 2]], np.int64)
+    assert edge_set(rng.rng_edges_metric(K, "l1")) == {(0, 1), (0, 2), (1, 2)}
+    assert edge_set(rng.rng_edges_metric(K, "linf")) == {(0, 2), (1, 2)}
+    assert edge_set(rng.rng_edges_metric(K, "l2sq")) == edge_set(rng.rng_edges(K))
+
+
+@pytest.mark.parametrize("metric", ["l1", "linf"])
+def test_metric_rng_pins(metric):
+    g = np.random.default_rng(41)
+    # 1-D: every metric is |a - b|, so the RNG is the sorted path
+    x = g.permutation(40)[:25].astype(np.int64).reshape(-1, 1)
+    order = np.argsort(x[:, 0])
+    path = {tuple(sorted((int(order[i]), int(order[i + 1])))) for i in range(len(order) - 1)}
+    assert edge_set(rng.rng_edges_metric(x, metric)) == path
+    # loop-only implementation agrees on tiny inputs with many ties
+    for t in range(120):
+        n = int(g.integers(1, 8))
+        K = g.integers(0, 4 if t % 2 else 500, size=(n, int(g.integers(1, 4)))).astype(np.int64)
+        assert edge_set(rng.rng_edges_metric(K, metric)) == set(rng.rng_edges_metric_loops(K, metric))
+    # the metric's minimum spanning tree (scipy, an independent routine) lies in the RNG
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import minimum_spanning_tree
+    K = g.integers(0, 2 ** 20, size=(120, 3)).astype(np.int64)
+    D = rng.metric_dists(K, metric).astype(np.float64)
+    T = minimum_spanning_tree(csr_matrix(D + 1e-300 * (D == 0)))
+    r, c = T.nonzero()
+    assert {tuple(sorted((int(a), int(b)))) for a, b in zip(r, c)} <= edge_set(rng.rng_edges_metric(K, metric))
