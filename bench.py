@@ -264,6 +264,7 @@ def parse():
                     "else 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the comparison builds of the other forms")
+    ap.add_argument("--form-warmup", type=int, default=1, help="untimed builds before each form's timed one")
     ap.add_argument("--autotune", type=int, default=1, help="1: the index autotunes its witness-pivot counts on "
                     "the first (warmup) build")
     ap.add_argument("--vgrng-pivots", type=int, default=0, help="Proposition 1 witness pivots per block (autotune 0)")
@@ -320,15 +321,23 @@ class Builder:
         return e0.elapsed_time(e1)
 
 
-def other_form(P, W, precision, st, witness_order=0, scorer=None):
-    """One warmed-up build of another form with the witness-pivot counts the
-    timed index settled on: (ms, edges as a host array, stats)."""
+def progress(what, **kw):
+    """A progress line on stderr (a C5 build runs for about 100 s)."""
+    print(json.dumps(dict({"progress": what}, **kw)), file=sys.stderr, flush=True)
+
+
+def other_form(P, W, precision, st, witness_order=0, scorer=None, warmup=1):
+    """One build (after `warmup` untimed ones) of another form with the
+    witness-pivot counts the timed index settled on: (ms, edges as a host
+    array, stats)."""
     b = Builder(P, W, precision=precision, autotune=0, witness_order=witness_order,
                 vgrng_pivots=int(st["vgrng_pivots"]), stage4_pivots=int(st["stage4_pivots"]))
     if scorer is not None:
         b.idx.set_scorer(scorer)
-    b.step()
+    for _ in range(warmup):
+        b.step()
     ms = b.timed()
+    progress("form", precision=precision, witness_order=witness_order, ms=ms)
     E = b.idx.edges().cpu().numpy()
     s2 = b.idx.stats()
     b.idx.close()
@@ -361,6 +370,7 @@ def train_scorer(P):
                              .astype(np.float32)).cuda()
     t0 = time.perf_counter()
     loss = P.mlp_train(theta, feats, labels, steps=400, lr=3e-3)
+    progress("scorer trained", loss=loss)
     return theta, {"samples": int(feats.shape[0]), "loss": loss, "train_s": time.perf_counter() - t0}
 
 
@@ -403,11 +413,13 @@ def main():
         sys.exit(2)
     for _ in range(args.warmup):
         b.step()
+        progress("warmup step")
     torch.cuda.synchronize()
     times = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
         times.append(b.timed())
+        progress("timed step", ms=times[-1])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms = float(np.median(times))
@@ -422,19 +434,20 @@ def main():
         if prec == 1:
             base_ms, base_st = ms, st
         else:
-            base_ms, E1, base_st = other_form(P, W, 1, st)
+            base_ms, E1, base_st = other_form(P, W, 1, st, warmup=args.form_warmup)
             forms["plain_float32"] = form_entry(base_ms, base_st, np.array_equal(E1, E), base_ms)
         if prec == 2:
             forms["bf16"] = form_entry(ms, st, forms["plain_float32"]["identical_edges"], base_ms)
         elif args.workload == "clustered":
-            ms2, E2, st2 = other_form(P, W, 2, st)
+            ms2, E2, st2 = other_form(P, W, 2, st, warmup=args.form_warmup)
             forms["bf16"] = form_entry(ms2, st2, np.array_equal(E2, E), base_ms)
         if args.workload == "clustered96":
             forms["plain_float32"] = form_entry(ms, st, True, ms)
-            ms_l, E_l, st_l = other_form(P, W, 1, st, witness_order=P.ORDER_LEARNED, scorer=scorer)
+            ms_l, E_l, st_l = other_form(P, W, 1, st, witness_order=P.ORDER_LEARNED, scorer=scorer,
+                                         warmup=args.form_warmup)
             forms["learned"] = form_entry(ms_l, st_l, np.array_equal(E_l, E), ms)
             forms["learned"]["scorer"] = train
-            ms_u, E_u, st_u = other_form(P, W, 1, st, witness_order=P.ORDER_LUNE)
+            ms_u, E_u, st_u = other_form(P, W, 1, st, witness_order=P.ORDER_LUNE, warmup=args.form_warmup)
             forms["lune_order"] = form_entry(ms_u, st_u, np.array_equal(E_u, E), ms)
         if forms["plain_float32"] is None:
             forms["plain_float32"] = form_entry(base_ms, base_st, True, base_ms)
@@ -526,6 +539,7 @@ def bench_insert(args):
         reb_ms.append(r.timed())
         same = same and np.array_equal(r.idx.edges().cpu().numpy(), b.idx.edges().cpu().numpy())
         r.idx.close()
+        progress("batch", n=len(allX) - 1, insert_ms=ins_ms[-1], rebuild_ms=reb_ms[-1])
     n_final = b.idx.stats()["n_points"]
     b.idx.close()
     total = sum(ins_ms)

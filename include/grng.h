@@ -256,19 +256,19 @@ void grng_destroy(grng_index *idx);
  * found); it changes only how many witness tests are spent.  A small MLP,
  *     h = relu(f W1 + b1),  s = h . w2 + b2,
  * scores each candidate domain from GRNG_MLP_FEATURES scale-free features
- * (distances of x and y to the domain's pivot, the domain's covering radius
- * and pivot radius, its Proposition 3 margin and size, all relative to
- * d(x,y)).  Parameters are one float32 device vector of grng_mlp_params()
+ * (distances of x and y to the domain's pivot, their smaller and larger
+ * value (the larger is the lune-order key), the domain's covering radius and
+ * pivot radius, its Proposition 3 margin and size, all relative to d(x,y)).  Parameters are one float32 device vector of grng_mlp_params()
  * values laid out [W1 (features x hidden, row-major), b1, w2, b2].  The loss
  * is the mean binary cross-entropy with logits against "the domain holds a
  * witness".  Training samples come from the last grng_build_rng. */
-#define GRNG_MLP_FEATURES 8
+#define GRNG_MLP_FEATURES 9
 #define GRNG_MLP_HIDDEN 64
 
-/* Number of parameters: F*H + 2H + 1 = 641. */
+/* Number of parameters: F*H + 2H + 1 = 705. */
 int32_t grng_mlp_params(void);
 
-/* Loss and its gradient on n samples.  feats_dev: float32 [n][8] (device),
+/* Loss and its gradient on n samples.  feats_dev: float32 [n][9] (device),
  * labels_dev: uint8 [n] in {0,1} (device), grad_dev: float32 [params]
  * (device, written), *loss: host float.  Blocks of samples are reduced in a
  * fixed order, so the result is deterministic.  stream: hipStream_t or NULL. */
@@ -279,7 +279,7 @@ grng_status grng_mlp_grad(const float *theta_dev, const float *feats_dev, const 
  * capture, tight training or serving loops, harnesses that forbid
  * hipMalloc): the same loss and gradient as grng_mlp_grad, bit for bit, but
  * with no allocation.  The per-block partial gradients go to a fixed scratch
- * array in the library's device memory (10.5 MB on each device the library
+ * array in the library's device memory (11.6 MB on each device the library
  * runs on, held until the process ends), so n is limited to
  * GRNG_MLP_NOALLOC_MAX_SAMPLES; larger n returns GRNG_EINVAL.  The loss is
  * written to loss_dev (float32, device) instead of a host float, and the call

@@ -27,7 +27,7 @@ ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_bui
                  "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy",
                  "grng_mlp_params", "grng_mlp_grad", "grng_mlp_grad_noalloc", "grng_mlp_train", "grng_mlp_score", "grng_log_witness_cells",
                  "grng_set_scorer")
-MLP_FEATURES, MLP_HIDDEN = 8, 64
+MLP_FEATURES, MLP_HIDDEN = 9, 64
 
 
 class GrngError(RuntimeError):

@@ -190,7 +190,7 @@ enum Counter {
 constexpr int kWorkStride = 16;   // uint64 slots between two XCDs' work counters
 
 // Learned witness-cell ranking (scan order only).
-constexpr int kMlpFeatures = 8;
+constexpr int kMlpFeatures = 9;
 constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = kMlpFeatures * kMlpHidden + 2 * kMlpHidden + 1;
 
@@ -208,7 +208,8 @@ __device__ inline void mlp_features(double dx, double dy, double dcell, double r
                                     (fmax(dx, dy) - dcell) * inv,
                                     log2(1.0 + (double)size) * 0.1,
                                     (dx * dx + dy * dy) * inv * inv - 1.0,
-                                    fmin(dx, dy) * inv};
+                                    fmin(dx, dy) * inv,
+                                    fmax(dx, dy) * inv};   // the lune-order key
     for (int k = 0; k < kMlpFeatures; ++k) f[k] = (float)fmin(64.0, fmax(-64.0, v[k]));
 }
 
@@ -298,6 +299,16 @@ void launch_to_f32(hipStream_t s, const double *src, int64_t count, float *dst);
 void launch_iota_inverse(hipStream_t s, const int32_t *perm, int64_t n, int32_t *inv);
 void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out_excl);  // out has n+1
 void launch_scan_i32_to_i64(hipStream_t s, const int32_t *in, int64_t n, int64_t *out_excl);
+// Insertion merge of per-point state (old rows of each cell, then its batch rows).
+void launch_merge_positions(hipStream_t s, int64_t n1, int64_t m, const int32_t *new_off, const int32_t *old_off,
+                            const int32_t *bat_off, int32_t *src);
+void launch_merge_rows(hipStream_t s, int64_t n1, size_t row_bytes, const int32_t *src, const void *old,
+                       const void *bat, uint32_t bias, void *out);
+void launch_merge_csr_len(hipStream_t s, int64_t n1, const int32_t *src, const int64_t *old_off,
+                          const int64_t *bat_off, int32_t *len);
+void launch_merge_csr_copy(hipStream_t s, int64_t n1, const int32_t *src, const int64_t *old_off,
+                           const int32_t *old_idx, const int64_t *bat_off, const int32_t *bat_idx,
+                           const int64_t *new_off, int32_t *new_idx);
 void launch_bits_transpose(hipStream_t s, const uint64_t *rows, int64_t n, int32_t words, int64_t m,
                            uint64_t *cols);
 void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t count, uint64_t v);
@@ -319,10 +330,13 @@ void launch_parents(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, co
                     const int64_t *par_off, int32_t *par_idx);
 void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, const double *rad, const double *dvor,
                                 float *bd, float *bv);
+// Virtual-pivot bit rows of every point (Propositions 1-2).  cols: only the
+// cell-radius bits of the listed pivots, OR-ed into v_rows (g_rows untouched).
 void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
                   const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
                   const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, const int32_t *home,
-                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters);
+                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters,
+                  const int32_t *cols = nullptr, int32_t ncols = 0);
 
 // k_rng.hip
 struct PairList {
@@ -394,7 +408,7 @@ void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double 
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
-                            uint64_t *counters);
+                            uint64_t *counters, bool sort = true);
 void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2);
 void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,

@@ -389,9 +389,10 @@ void prepare_aux(grng_index *idx, const Layer &L, LayerAux &aux) {
 // is_new (host, optional): per input index, 1 for points inserted in this batch.
 // locality: inside a home cell, group the points by their second-nearest
 // pivot (a full build only: insertion needs each cell's old points first).
+// dxp_ready: P.dxp already holds the point-pivot distances.
 void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double *X, const double *nrm, int64_t n,
                     const PointState *cells, const std::vector<uint8_t> *is_new, PointState &P, BuildTimes &bt,
-                    bool locality = false) {
+                    bool locality = false, bool dxp_ready = false) {
     hipStream_t s = idx->stream;
     const int64_t m = L.m;
     const int dp = idx->dp;
@@ -400,9 +401,11 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     const bool indexed = cells == nullptr;
     P.n = n;
     // A1: exact point-pivot distances (MFMA f64 tiles), input order [n][m].
-    P.dxp.alloc(sizeof(double) * (size_t)(n * m));
-    launch_dist2(s, X, nrm, n, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, P.dxp.as<double>(), m, true);
-    bt.host_dist += (double)n * (double)m;
+    if (!dxp_ready) {
+        P.dxp.alloc(sizeof(double) * (size_t)(n * m));
+        launch_dist2(s, X, nrm, n, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, P.dxp.as<double>(), m, true);
+        bt.host_dist += (double)n * (double)m;
+    }
     // A2: parent counts, home cell, cell radius.
     DevBuf home, d2home, npar, d2vor, gcount, second;
     home.alloc(4 * (size_t)n);
@@ -578,6 +581,200 @@ void prepare_points(grng_index *idx, const Layer &L, LayerAux &aux, const double
     }
 }
 
+// Insertion state (Section 2, Stage VII; Proposition 5).  The indexed points
+// S keep their point-pivot distances, home cells, parents and bit rows from
+// one insertion to the next.  The batch is prepared on its own against the
+// cells as they are after the insertion (B: also the row side of a sparse
+// insertion) and merged into each home cell after the cell's old points (N).
+// An old point's bit rows depend on the cells only through their radius
+// bounds and sizes, so they stay valid except in the 64-cell words of cells
+// whose bound grew or that were empty: those words are recomputed for every
+// point.  The batch's distance rows are appended to S.dxp when it has room
+// (rows past S.n are unused, so S stays valid) and N then takes the buffer
+// over (dxp_moved: the caller gives it back if the insertion fails); else N
+// gets a larger copy.  bd_new, bv_new: the shifted pivot tables for the new
+// cell bounds, swapped into aux on success.  newrad: radius bound of each
+// cell's batch points (0 where there are none).
+void merge_batch(grng_index *idx, const Layer &L, LayerAux &aux, PointState &S, const double *Xb, const double *nrmb,
+                 int64_t nb, bool dense, PointState &N, PointState &B, DevBuf &bd_new, DevBuf &bv_new,
+                 std::vector<double> &newrad, bool &dxp_moved, BuildTimes &bt) {
+    hipStream_t s = idx->stream;
+    const int64_t m = L.m, n0 = S.n, n1 = n0 + nb;
+    const int dp = idx->dp;
+    const int32_t words = L.words;
+    uint64_t *ctr = idx->counters.as<uint64_t>();
+    require(S.dxp.p != nullptr && S.dxp.bytes >= sizeof(double) * (size_t)(n0 * m), GRNG_ESTATE,
+            "point-pivot distances of the indexed points are missing");
+    EventTimer timer(s);
+    // Batch home cells and their squared distances.
+    B.dxp.alloc(sizeof(double) * (size_t)(nb * m));
+    launch_dist2(s, Xb, nrmb, nb, aux.Xp.as<double>(), aux.nrmp.as<double>(), m, dp, B.dxp.as<double>(), m, true);
+    bt.host_dist += (double)nb * (double)m;
+    DevBuf hb, d2b, npb;
+    hb.alloc(4 * (size_t)nb);
+    d2b.alloc(8 * (size_t)nb);
+    npb.alloc(4 * (size_t)nb);
+    launch_point_pass1(s, nb, m, B.dxp.as<double>(), L.rad.as<double>(), hb.as<int32_t>(), d2b.as<double>(),
+                       npb.as<int32_t>(), nullptr);
+    std::vector<int32_t> h_hb;
+    std::vector<double> h_d2b, dv_old;
+    d2h(h_hb, hb.p, (size_t)nb, s);
+    d2h(h_d2b, d2b.p, (size_t)nb, s);
+    d2h(dv_old, S.dvor.p, (size_t)m, s);
+    // Cells after the insertion: sizes, radius bounds (the same values a
+    // rebuild computes: the bound is monotone in the squared radius), offsets.
+    std::vector<int32_t> bcnt((size_t)m, 0), gcount((size_t)m);
+    std::vector<double> dvor(dv_old);
+    newrad.assign((size_t)m, 0.0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t c = h_hb[b];
+        ++bcnt[c];
+        newrad[c] = std::max(newrad[c], std::sqrt(h_d2b[b]) * (1.0 + 1e-15));
+        dvor[c] = std::max(dvor[c], newrad[c]);
+    }
+    std::vector<int32_t> grown;   // cells whose bound grew or that were empty
+    N.n = n1;
+    N.h_off.assign((size_t)m + 1, 0);
+    for (int64_t c = 0; c < m; ++c) {
+        const int32_t old = S.h_off[c + 1] - S.h_off[c];
+        gcount[c] = old + bcnt[c];
+        N.h_off[c + 1] = N.h_off[c] + gcount[c];
+        if (bcnt[c] > 0 && (old == 0 || dvor[c] > dv_old[c])) grown.push_back((int32_t)c);
+    }
+    h2d(N.grp_off, N.h_off, s);
+    h2d(N.dvor, dvor, s);
+    h2d(N.gcount, gcount, s);
+    bd_new.alloc(4 * (size_t)(m * m));
+    bv_new.alloc(4 * (size_t)(m * m));
+    launch_shifted_pivot_dists(s, m, L.dpp.as<double>(), L.rad.as<double>(), N.dvor.as<double>(),
+                               bd_new.as<float>(), bv_new.as<float>());
+    // The new tables stand in aux while the bit rows are computed.
+    struct TablesIn {
+        LayerAux &a;
+        DevBuf &bd, &bv;
+        TablesIn(LayerAux &a_, DevBuf &bd_, DevBuf &bv_) : a(a_), bd(bd_), bv(bv_) { swap(); }
+        ~TablesIn() { swap(); }
+        void swap() {
+            std::swap(a.bd, bd);
+            std::swap(a.bv, bv);
+        }
+    };
+    {
+        TablesIn in(aux, bd_new, bv_new);
+        prepare_points(idx, L, aux, Xb, nrmb, nb, &N, nullptr, B, bt, false, true);
+    }
+    {
+        std::vector<double> dh((size_t)nb);
+        std::vector<float> dhf((size_t)nb);
+        for (int64_t r = 0; r < nb; ++r) {
+            dh[r] = std::sqrt(h_d2b[B.h_perm[r]]) * (1.0 + 1e-15);   // upper bound of d(x, p_home)
+            float f = (float)dh[r];
+            if ((double)f < dh[r]) f = std::nextafter(f, INFINITY);
+            dhf[r] = f;
+        }
+        h2d(B.dhome, dh, s);
+        h2d(B.dhomef, dhf, s);
+    }
+    // Merged home order and per-point rows.
+    DevBuf src, boff;
+    src.alloc(4 * (size_t)n1);
+    h2d(boff, B.h_off, s);
+    launch_merge_positions(s, n1, m, N.grp_off.as<int32_t>(), S.grp_off.as<int32_t>(), boff.as<int32_t>(),
+                           src.as<int32_t>());
+    auto merge = [&](DevBuf &dst, const DevBuf &a, const DevBuf &b, size_t row_bytes, uint32_t bias) {
+        dst.alloc(row_bytes * (size_t)std::max<int64_t>(n1, 1));
+        launch_merge_rows(s, n1, row_bytes, src.as<int32_t>(), a.p, b.p, bias, dst.p);
+    };
+    merge(N.perm, S.perm, B.perm, 4, (uint32_t)n0);
+    merge(N.home, S.home, B.home, 4, 0);
+    merge(N.Xh, S.Xh, B.Xh, 8 * (size_t)dp, 0);
+    merge(N.nrmh, S.nrmh, B.nrmh, 8, 0);
+    merge(N.Xf, S.Xf, B.Xf, 4 * (size_t)dp, 0);
+    merge(N.dhome, S.dhome, B.dhome, 8, 0);
+    merge(N.dhomef, S.dhomef, B.dhomef, 4, 0);
+    merge(N.g_rows, S.g_rows, B.g_rows, 8 * (size_t)words, 0);
+    merge(N.v_rows, S.v_rows, B.v_rows, 8 * (size_t)words, 0);
+    {
+        DevBuf plen;
+        plen.alloc(4 * (size_t)n1);
+        N.par_off.alloc(8 * (size_t)(n1 + 1));
+        launch_merge_csr_len(s, n1, src.as<int32_t>(), S.par_off.as<int64_t>(), B.par_off.as<int64_t>(),
+                             plen.as<int32_t>());
+        launch_scan_i32_to_i64(s, plen.as<int32_t>(), n1, N.par_off.as<int64_t>());
+        std::vector<int64_t> tot;
+        d2h(tot, N.par_off.as<int64_t>() + n1, 1, s);
+        N.par_idx.alloc(4 * (size_t)std::max<int64_t>(tot[0], 1));
+        launch_merge_csr_copy(s, n1, src.as<int32_t>(), S.par_off.as<int64_t>(), S.par_idx.as<int32_t>(),
+                              B.par_off.as<int64_t>(), B.par_idx.as<int32_t>(), N.par_off.as<int64_t>(),
+                              N.par_idx.as<int32_t>());
+    }
+    N.orphans = S.orphans + B.orphans;
+    N.inv.alloc(4 * (size_t)n1);
+    launch_iota_inverse(s, N.perm.as<int32_t>(), n1, N.inv.as<int32_t>());
+    // Point-pivot distances, input order: the batch rows follow the old ones.
+    const size_t row = sizeof(double) * (size_t)m;
+    if (S.dxp.bytes >= row * (size_t)n1) {
+        N.dxp = std::move(S.dxp);
+        dxp_moved = true;
+    } else {
+        N.dxp.alloc(row * (size_t)(n1 + n1 / 4));   // room for later batches
+        GRNG_HIP(hipMemcpyAsync(N.dxp.p, S.dxp.p, row * (size_t)n0, hipMemcpyDeviceToDevice, s));
+    }
+    GRNG_HIP(hipMemcpyAsync(N.dxp.as<double>() + n0 * m, B.dxp.p, row * (size_t)nb, hipMemcpyDeviceToDevice, s));
+    const double ms_merge = timer.stop();
+    trace("insertion merge", ms_merge, n1);
+    // Cell-radius bits of the grown cells, for every point.
+    if (!grown.empty()) {
+        DevBuf dcols;
+        h2d(dcols, grown, s);
+        TablesIn in(aux, bd_new, bv_new);
+        EventTimer vt(s);
+        launch_vgrng(s, n1, m, N.perm.as<int32_t>(), N.dxp.as<double>(), aux.bd.as<float>(), aux.bv.as<float>(),
+                     L.rad.as<double>(), N.dvor.as<double>(), N.gcount.as<int32_t>(), N.par_off.as<int64_t>(),
+                     N.par_idx.as<int32_t>(), L.bits.as<uint64_t>(), words, N.home.as<int32_t>(),
+                     aux.wknn.as<int32_t>(), aux.kw, N.g_rows.as<uint64_t>(), N.v_rows.as<uint64_t>(), ctr,
+                     dcols.as<int32_t>(), (int32_t)grown.size());
+        const double ms = vt.stop();
+        bt.vgrng += ms;
+        trace("cell-radius bits of grown cells", ms, (int64_t)grown.size());
+    }
+    N.nw = div_up(n1, 64);
+    N.g_cols.alloc(8 * (size_t)(m * N.nw));
+    launch_bits_transpose(s, N.g_rows.as<uint64_t>(), n1, words, m, N.g_cols.as<uint64_t>());
+    // Tiles: chunks of <= 64 points of one cell; with a dense batch, a cell's
+    // old and batch points get tiles of their own.
+    std::vector<int32_t> tiles;
+    std::vector<uint8_t> tnew, newh;
+    if (dense) newh.assign((size_t)n1, 0);
+    auto add_tiles = [&](int32_t b, int32_t e, int64_t c, uint8_t fresh) {
+        for (int32_t st = b; st < e; st += 64) {
+            tiles.push_back(st);
+            tiles.push_back(std::min<int32_t>(64, e - st));
+            tiles.push_back((int32_t)c);
+            if (dense) tnew.push_back(fresh);
+        }
+    };
+    for (int64_t c = 0; c < m; ++c) {
+        const int32_t b = N.h_off[c], e = N.h_off[c + 1];
+        if (!dense) {
+            add_tiles(b, e, c, 0);
+            continue;
+        }
+        const int32_t split = b + (S.h_off[c + 1] - S.h_off[c]);
+        add_tiles(b, split, c, 0);
+        add_tiles(split, e, c, 1);
+        for (int32_t r = split; r < e; ++r) newh[r] = 1;
+    }
+    N.ntiles = (int64_t)tiles.size() / 3;
+    h2d(N.tiles, tiles, s);
+    N.tv.alloc(8 * (size_t)std::max<int64_t>(N.ntiles * words, 1));
+    launch_tile_vmask(s, N.ntiles, N.tiles.as<int32_t>(), N.v_rows.as<uint64_t>(), words, N.tv.as<uint64_t>());
+    if (dense) {
+        h2d(N.is_new, newh, s);
+        h2d(N.tnew, tnew, s);
+    }
+}
+
 // gid: global point ids of the set (PM_INSERT), or null; new_from: first id
 // of the batch being inserted; with_new: pass the batch flags (PM_NEW_ONLY).
 PointsView view_of(const PointState &P, const int32_t *gid, int32_t new_from, bool with_new) {
@@ -613,11 +810,14 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
                       B.tv.as<uint64_t>(), nb, words, mode, toff.as<int64_t>(), tcnt.as<int32_t>(), tpT.as<int32_t>(),
                       tpU.as<int32_t>());
     dmax.alloc(8 * (size_t)std::max<int64_t>(A.n, 1));
-    // Survivor capacity: 64 per point.  A pass that overflows is run again
-    // with the exact size; at a million points a pass takes tens of seconds
-    // where pruning is weak, so there the first capacity is 256 per point
-    // when a quarter of the free device memory holds it.
+    // Survivor capacity: 64 per point, and up to 8,192 per point for small
+    // row sets (an insertion batch: few rows, each facing the whole index),
+    // at most 2^25 pairs.  A pass that overflows is run again with the exact
+    // size; at a million points a pass takes tens of seconds where pruning
+    // is weak, so there the first capacity is 256 per point when a quarter
+    // of the free device memory holds it.
     int64_t cap = std::max<int64_t>(1 << 22, 64 * A.n);
+    cap = std::max<int64_t>(cap, std::min<int64_t>(8192 * A.n, 1 << 25));
     if (A.n >= 500000) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess)
@@ -685,9 +885,13 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
 //   X: row side (indexed set or query set), S: indexed set (witnesses).
 //   cell_filter: cells that may hold witnesses (S.gcount, or new-point counts).
 //   zstart: first witness position per cell (Stage VII: the inserted points), or null.
+//   cell_rad: radius bound of each cell's witnesses (S.dvor when null; Stage
+//     VII passes the bound of the inserted points alone).
 void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const PointState &X, const PointState &S,
                     Pairs &P, int64_t np, const DevBuf &dmax, const int32_t *cell_filter, const int32_t *zstart,
-                    DevBuf &alive, BuildTimes &bt, ExhaustiveState *keep = nullptr) {
+                    DevBuf &alive, BuildTimes &bt, ExhaustiveState *keep = nullptr,
+                    const double *cell_rad = nullptr) {
+    const double *crad = cell_rad ? cell_rad : S.dvor.as<double>();
     hipStream_t s = idx->stream;
     const int64_t n = X.n, m = L.m;
     uint64_t *ctr = idx->counters.as<uint64_t>();
@@ -708,16 +912,19 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     DevBuf rel_cnt, rel_off, rel_grp, rel_d2x;
     rel_cnt.alloc(4 * (size_t)n);
     rel_off.alloc(8 * (size_t)(n + 1));
-    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
-                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr, ctr);
+    // Nearest witness cells first, except in Stage VII, whose cells hold only
+    // the inserted points (a few each): there the order is pivot order.
+    const bool sort = zstart == nullptr;
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter,
+                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr, ctr, sort);
     launch_scan_i32_to_i64(s, rel_cnt.as<int32_t>(), n, rel_off.as<int64_t>());
     std::vector<int64_t> tot;
     d2h(tot, rel_off.as<int64_t>() + n, 1, s);
     rel_grp.alloc(4 * (size_t)std::max<int64_t>(tot[0], 1));
     rel_d2x.alloc(8 * (size_t)std::max<int64_t>(tot[0], 1));
-    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), S.dvor.as<double>(), cell_filter,
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter,
                            dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(),
-                           rel_d2x.as<double>(), ctr);
+                           rel_d2x.as<double>(), ctr, sort);
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
     const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
@@ -725,7 +932,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                        X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.n, S.dhome.as<double>(),
                        f32 ? X.Xf.as<float>() : nullptr, f32 ? S.Xf.as<float>() : nullptr,
                        f32 ? S.dhomef.as<float>() : nullptr, zstart,
-                       S.grp_off.as<int32_t>(), S.dvor.as<double>(), aux.Xp.as<double>(), aux.nrmp.as<double>(),
+                       S.grp_off.as<int32_t>(), crad, aux.Xp.as<double>(), aux.nrmp.as<double>(),
                        rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
                        idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,
                        idx->opt.witness_order == GRNG_ORDER_LUNE,
@@ -758,7 +965,6 @@ void build_rng_guided(grng_index *idx, PointState &ps, LayerAux &aux, DevBuf &ed
     run_exhaustive(idx, L, aux, ps, ps, P, np, dmax, ps.gcount.as<int32_t>(), nullptr, alive, bt, &ex);
     pairs_to_edges(idx->stream, idx->n, np, ex.x.as<int32_t>(), ex.y.as<int32_t>(), alive.as<uint8_t>(),
                    ps.perm.as<int32_t>(), edges, ne);
-    ps.dxp.release();   // only needed while building
 }
 
 void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
@@ -997,85 +1203,95 @@ void do_insert(grng_index *idx, const float *pts, int64_t nb) {
     } else {
         const Layer &L = idx->layers.back();
         LayerAux &aux = idx->aux;
+        PointState &S = idx->ps;
+        const int64_t m = L.m;
         // Localization of the new points (Stages I-VI) against S u B.  A dense
         // batch (at least kDenseBatch points per pivot cell on average) keeps
         // the batch points in their cells' tiles and scans the tile pairs with
         // a batch tile; a sparse one is the row side of its own, with tiles
         // packed across cells.
         constexpr int64_t kDenseBatch = 8;
-        const bool dense = nb >= kDenseBatch * L.m;
-        std::vector<uint8_t> is_new;
-        if (dense) {
-            is_new.assign((size_t)n1, 0);
-            for (int64_t x = n0; x < n1; ++x) is_new[x] = 1;
-        }
-        prepare_points(idx, L, aux, X1.as<double>(), nrm1.as<double>(), n1, nullptr, dense ? &is_new : nullptr, ps,
-                       bt);
-        Pairs Pn;
-        DevBuf dmax_n, alive_n;
-        int64_t np_n = 0;
-        if (dense) {
-            run_pairs(idx, L, aux, ps, ps, PM_SELF | PM_NEW_ONLY, Pn, dmax_n, np_n, bt);
-            run_exhaustive(idx, L, aux, ps, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
-            launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), ps.perm.as<int32_t>(),
+        const bool dense = nb >= kDenseBatch * m;
+        PointState qs;
+        DevBuf bd_new, bv_new;
+        std::vector<double> newrad;
+        bool dxp_moved = false;
+        try {
+            merge_batch(idx, L, aux, S, Xb.as<double>(), nrmb.as<double>(), nb, dense, ps, qs, bd_new, bv_new,
+                        newrad, dxp_moved, bt);
+            Pairs Pn;
+            DevBuf dmax_n, alive_n;
+            int64_t np_n = 0;
+            if (dense) {
+                run_pairs(idx, L, aux, ps, ps, PM_SELF | PM_NEW_ONLY, Pn, dmax_n, np_n, bt);
+                run_exhaustive(idx, L, aux, ps, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n,
+                               bt);
+                launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), ps.perm.as<int32_t>(),
+                                    ps.perm.as<int32_t>());
+            } else {
+                std::vector<int32_t> g(qs.h_perm.size());
+                for (size_t r = 0; r < g.size(); ++r) g[r] = (int32_t)(n0 + qs.h_perm[r]);
+                h2d(qs.gid, g, s);
+                run_pairs(idx, L, aux, qs, ps, PM_INSERT, Pn, dmax_n, np_n, bt);
+                run_exhaustive(idx, L, aux, qs, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n,
+                               bt);
+                launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), qs.gid.as<int32_t>(),
+                                    ps.perm.as<int32_t>());
+            }
+            // Stage VII (Proposition 5): an existing edge survives iff no
+            // inserted point lies in its lune; only the inserted points are
+            // witnesses (each cell's batch points follow its old ones), so a
+            // cell's witness ball is that of its inserted points.
+            EventTimer t7(s);
+            std::vector<int32_t> newcount((size_t)m), zst((size_t)m);
+            for (int64_t c = 0; c < m; ++c) {
+                zst[c] = ps.h_off[c] + (S.h_off[c + 1] - S.h_off[c]);
+                newcount[c] = ps.h_off[c + 1] - zst[c];
+            }
+            DevBuf d_newcount, d_zst, d_newrad;
+            h2d(d_newcount, newcount, s);
+            h2d(d_zst, zst, s);
+            h2d(d_newrad, newrad, s);
+            const int64_t ne0 = idx->nedges;
+            Pairs Po;
+            Po.reserve(ne0);
+            DevBuf dmax_o, alive_o;
+            dmax_o.alloc(8 * (size_t)n1);
+            zero(dmax_o, s);
+            launch_edges_to_pairs(s, ne0, idx->edges.as<int32_t>(), ps.inv.as<int32_t>(), Po.x.as<int32_t>(),
+                                  Po.y.as<int32_t>());
+            launch_pair_d2(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), dp, ps.Xh.as<double>(),
+                           ps.nrmh.as<double>(), Po.d2.as<double>(), dmax_o.as<uint64_t>());
+            run_exhaustive(idx, L, aux, ps, ps, Po, ne0, dmax_o, d_newcount.as<int32_t>(), d_zst.as<int32_t>(),
+                           alive_o, bt, nullptr, d_newrad.as<double>());
+            trace("Stage VII on the old edges", t7.stop(), ne0);
+            // Merge: surviving old edges and new edges.
+            EventTimer te(s);
+            Pairs Pm;
+            Pm.reserve(ne0 + np_n);
+            DevBuf alive_m;
+            alive_m.alloc((size_t)std::max<int64_t>(ne0 + np_n, 8));
+            auto cat = [&](DevBuf &dst, const DevBuf &a, const DevBuf &b, size_t el, int64_t na, int64_t nb2) {
+                if (na) GRNG_HIP(hipMemcpyAsync(dst.p, a.p, el * (size_t)na, hipMemcpyDeviceToDevice, s));
+                if (nb2)
+                    GRNG_HIP(hipMemcpyAsync(static_cast<char *>(dst.p) + el * (size_t)na, b.p, el * (size_t)nb2,
+                                            hipMemcpyDeviceToDevice, s));
+            };
+            launch_pairs_to_ids(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), ps.perm.as<int32_t>(),
                                 ps.perm.as<int32_t>());
-        } else {
-            PointState qs;
-            prepare_points(idx, L, aux, Xb.as<double>(), nrmb.as<double>(), nb, &ps, nullptr, qs, bt);
-            std::vector<int32_t> g(qs.h_perm.size());
-            for (size_t r = 0; r < g.size(); ++r) g[r] = (int32_t)(n0 + qs.h_perm[r]);
-            h2d(qs.gid, g, s);
-            run_pairs(idx, L, aux, qs, ps, PM_INSERT, Pn, dmax_n, np_n, bt);
-            run_exhaustive(idx, L, aux, qs, ps, Pn, np_n, dmax_n, ps.gcount.as<int32_t>(), nullptr, alive_n, bt);
-            launch_pairs_to_ids(s, np_n, Pn.x.as<int32_t>(), Pn.y.as<int32_t>(), qs.gid.as<int32_t>(),
-                                ps.perm.as<int32_t>());
+            cat(Pm.x, Po.x, Pn.x, 4, ne0, np_n);
+            cat(Pm.y, Po.y, Pn.y, 4, ne0, np_n);
+            cat(alive_m, alive_o, alive_n, 1, ne0, np_n);
+            pairs_to_edges(s, n1, ne0 + np_n, Pm.x.as<int32_t>(), Pm.y.as<int32_t>(), alive_m.as<uint8_t>(),
+                           nullptr, edges, ne);
+            trace("edge list of the union", te.stop(), ne);
+        } catch (...) {
+            if (dxp_moved) S.dxp = std::move(ps.dxp);   // its first n0 rows are as they were
+            throw;
         }
-        // Stage VII (Proposition 5): an existing edge survives iff no inserted
-        // point lies in its lune; only the inserted points are witnesses (home
-        // cells keep old points first, so they are a suffix of each cell).
-        const int64_t m = L.m;
-        std::vector<int32_t> newcount((size_t)m, 0), zst((size_t)m);
-        for (int64_t c = 0; c < m; ++c) {
-            int32_t old = 0;
-            for (int32_t r = ps.h_off[c]; r < ps.h_off[c + 1]; ++r) old += ps.h_perm[r] < n0;
-            zst[c] = ps.h_off[c] + old;
-            newcount[c] = ps.h_off[c + 1] - zst[c];
-        }
-        DevBuf d_newcount, d_zst;
-        h2d(d_newcount, newcount, s);
-        h2d(d_zst, zst, s);
-        const int64_t ne0 = idx->nedges;
-        Pairs Po;
-        Po.reserve(ne0);
-        DevBuf dmax_o, alive_o;
-        dmax_o.alloc(8 * (size_t)n1);
-        zero(dmax_o, s);
-        launch_edges_to_pairs(s, ne0, idx->edges.as<int32_t>(), ps.inv.as<int32_t>(), Po.x.as<int32_t>(),
-                              Po.y.as<int32_t>());
-        launch_pair_d2(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), dp, ps.Xh.as<double>(), ps.nrmh.as<double>(),
-                       Po.d2.as<double>(), dmax_o.as<uint64_t>());
-        run_exhaustive(idx, L, aux, ps, ps, Po, ne0, dmax_o, d_newcount.as<int32_t>(), d_zst.as<int32_t>(), alive_o,
-                       bt);
-        // Merge: surviving old edges and new edges.
-        Pairs Pm;
-        Pm.reserve(ne0 + np_n);
-        DevBuf alive_m;
-        alive_m.alloc((size_t)std::max<int64_t>(ne0 + np_n, 8));
-        auto cat = [&](DevBuf &dst, const DevBuf &a, const DevBuf &b, size_t el, int64_t na, int64_t nb2) {
-            if (na) GRNG_HIP(hipMemcpyAsync(dst.p, a.p, el * (size_t)na, hipMemcpyDeviceToDevice, s));
-            if (nb2)
-                GRNG_HIP(hipMemcpyAsync(static_cast<char *>(dst.p) + el * (size_t)na, b.p, el * (size_t)nb2,
-                                        hipMemcpyDeviceToDevice, s));
-        };
-        launch_pairs_to_ids(s, ne0, Po.x.as<int32_t>(), Po.y.as<int32_t>(), ps.perm.as<int32_t>(),
-                            ps.perm.as<int32_t>());
-        cat(Pm.x, Po.x, Pn.x, 4, ne0, np_n);
-        cat(Pm.y, Po.y, Pn.y, 4, ne0, np_n);
-        cat(alive_m, alive_o, alive_n, 1, ne0, np_n);
-        pairs_to_edges(s, n1, ne0 + np_n, Pm.x.as<int32_t>(), Pm.y.as<int32_t>(), alive_m.as<uint8_t>(), nullptr,
-                       edges, ne);
-        ps.dxp.release();
         idx->ps = std::move(ps);
+        std::swap(aux.bd, bd_new);
+        std::swap(aux.bv, bv_new);
         idx->ex = ExhaustiveState();   // training samples come from full builds only
         std::swap(idx->X, X1);
         std::swap(idx->nrm, nrm1);

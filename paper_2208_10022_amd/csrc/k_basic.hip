@@ -177,18 +177,22 @@ __global__ void k_inverse(const int32_t *perm, int64_t n, int32_t *inv) {
 // takes 4 consecutive entries (coalesced loads and stores across the wave),
 // waves scan their sums with shuffles, and the 16 wave totals carry the
 // running offset from pass to pass.
+// Workgroup b scans entries [b * chunk, min(n, (b + 1) * chunk)) starting
+// from base[b] (0 without base); the last workgroup writes the total out[n].
 template <class TI>
-__global__ __launch_bounds__(1024) void k_scan(const TI *in, int64_t n, int64_t *out) {
+__global__ __launch_bounds__(1024) void k_scan(const TI *in, int64_t n, int64_t chunk, const int64_t *base,
+                                               int64_t *out) {
     constexpr int kPer = 4;
     __shared__ int64_t wsum[16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    int64_t carry = 0;
-    for (int64_t b0 = 0; b0 < n; b0 += 1024 * kPer) {
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    int64_t carry = base ? base[blockIdx.x] : 0;
+    for (int64_t b0 = lo; b0 < hi; b0 += 1024 * kPer) {
         const int64_t i0 = b0 + (int64_t)t * kPer;
         int64_t v[kPer], sum = 0;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            v[u] = i0 + u < n ? (int64_t)in[i0 + u] : 0;
+            v[u] = i0 + u < hi ? (int64_t)in[i0 + u] : 0;
             sum += v[u];
         }
         int64_t inc = sum;
@@ -208,13 +212,31 @@ __global__ __launch_bounds__(1024) void k_scan(const TI *in, int64_t n, int64_t 
         int64_t run = carry + before + inc - sum;
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            if (i0 + u < n) out[i0 + u] = run;
+            if (i0 + u < hi) out[i0 + u] = run;
             run += v[u];
         }
         carry += total;
         __syncthreads();   // wsum is rewritten by the next pass
     }
-    if (t == 0) out[n] = carry;
+    if (t == 0 && blockIdx.x == gridDim.x - 1) out[n] = carry;
+}
+
+// Sum of each workgroup's chunk (the first step of a scan over many workgroups).
+template <class TI>
+__global__ __launch_bounds__(1024) void k_chunk_sums(const TI *in, int64_t n, int64_t chunk, int64_t *sums) {
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    int64_t acc = 0;
+    for (int64_t i = lo + t; i < hi; i += 1024) acc += (int64_t)in[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (t == 0) {
+        int64_t tot = 0;
+        for (int j = 0; j < 16; ++j) tot += wsum[j];
+        sums[blockIdx.x] = tot;
+    }
 }
 
 __global__ void k_bits_transpose(const uint64_t *rows, int64_t n, int32_t words, int64_t m, uint64_t *cols,
@@ -247,6 +269,60 @@ inline unsigned grid1(int64_t work, int block) {
 __global__ void k_to_f32(const double *src, int64_t count, float *dst) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < count) dst[i] = (float)src[i];
+}
+
+
+// Insertion merge.  The merged home order keeps each cell's old points first
+// and appends the cell's batch points after them.  src[r] >= 0 names the old
+// position that position r takes its row from, src[r] < 0 the batch
+// position -1 - src[r].  The offsets arrays have m + 1 entries.
+__global__ void k_merge_positions(int64_t n1, int64_t m, const int32_t *__restrict__ new_off,
+                                  const int32_t *__restrict__ old_off, const int32_t *__restrict__ bat_off,
+                                  int32_t *__restrict__ src) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    int64_t lo = 0, hi = m;   // the cell c with new_off[c] <= r < new_off[c + 1]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (new_off[mid] <= r) lo = mid; else hi = mid;
+    }
+    const int32_t k = (int32_t)r - new_off[lo], old = old_off[lo + 1] - old_off[lo];
+    src[r] = k < old ? old_off[lo] + k : -1 - (bat_off[lo] + k - old);
+}
+
+// Rows of rw 32-bit words from the old or the batch side; bias is added to
+// batch-side words (batch-local point ids becoming global ids), else 0.
+__global__ void k_merge_rows32(int64_t n1, int32_t rw, const int32_t *__restrict__ src,
+                               const uint32_t *__restrict__ old, const uint32_t *__restrict__ bat, uint32_t bias,
+                               uint32_t *__restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n1 * rw) return;
+    const int64_t r = e / rw;
+    const int32_t t = (int32_t)(e - r * rw), sr = src[r];
+    out[e] = sr >= 0 ? old[(int64_t)sr * rw + t] : bat[(int64_t)(-1 - sr) * rw + t] + bias;
+}
+
+// Ragged rows (CSR): first the length of each merged row, then the copy.
+__global__ void k_merge_csr_len(int64_t n1, const int32_t *__restrict__ src, const int64_t *__restrict__ old_off,
+                                const int64_t *__restrict__ bat_off, int32_t *__restrict__ len) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    const int32_t sr = src[r];
+    len[r] = (int32_t)(sr >= 0 ? old_off[sr + 1] - old_off[sr] : bat_off[-sr] - bat_off[-1 - sr]);
+}
+
+__global__ void k_merge_csr_copy(int64_t n1, const int32_t *__restrict__ src, const int64_t *__restrict__ old_off,
+                                 const int32_t *__restrict__ old_idx, const int64_t *__restrict__ bat_off,
+                                 const int32_t *__restrict__ bat_idx, const int64_t *__restrict__ new_off,
+                                 int32_t *__restrict__ out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    const int32_t sr = src[r];
+    const int64_t *off = sr >= 0 ? old_off : bat_off;
+    const int32_t *idx = sr >= 0 ? old_idx : bat_idx;
+    const int64_t b = sr >= 0 ? sr : -1 - sr;
+    int64_t o = new_off[r];
+    for (int64_t t = off[b]; t < off[b + 1]; ++t) out[o++] = idx[t];
 }
 
 }  // namespace
@@ -319,14 +395,35 @@ void launch_iota_inverse(hipStream_t s, const int32_t *perm, int64_t n, int32_t 
     GRNG_LAUNCHED();
 }
 
-void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out_excl) {
-    k_scan<int64_t><<<1, 1024, 0, s>>>(in, n, out_excl);
+// Exclusive scan with the total in out[n]: one workgroup up to 2^16
+// entries, else chunk sums, their scan, and one workgroup per 4,096-entry
+// chunk.
+template <class TI>
+void scan_to_i64(hipStream_t s, const TI *in, int64_t n, int64_t *out) {
+    constexpr int64_t kChunk = 4096;
+    if (n <= (int64_t)1 << 16) {
+        k_scan<TI><<<1, 1024, 0, s>>>(in, n, n > 0 ? n : 1, nullptr, out);
+        GRNG_LAUNCHED();
+        return;
+    }
+    const int64_t nc = div_up(n, kChunk);
+    DevBuf sums, base;
+    sums.alloc(8 * (size_t)nc);
+    base.alloc(8 * (size_t)(nc + 1));
+    k_chunk_sums<TI><<<(unsigned)nc, 1024, 0, s>>>(in, n, kChunk, sums.as<int64_t>());
+    GRNG_LAUNCHED();
+    k_scan<int64_t><<<1, 1024, 0, s>>>(sums.as<int64_t>(), nc, nc, nullptr, base.as<int64_t>());
+    GRNG_LAUNCHED();
+    k_scan<TI><<<(unsigned)nc, 1024, 0, s>>>(in, n, kChunk, base.as<int64_t>(), out);
     GRNG_LAUNCHED();
 }
 
+void launch_scan_i64(hipStream_t s, const int64_t *in, int64_t n, int64_t *out_excl) {
+    scan_to_i64<int64_t>(s, in, n, out_excl);
+}
+
 void launch_scan_i32_to_i64(hipStream_t s, const int32_t *in, int64_t n, int64_t *out_excl) {
-    k_scan<int32_t><<<1, 1024, 0, s>>>(in, n, out_excl);
-    GRNG_LAUNCHED();
+    scan_to_i64<int32_t>(s, in, n, out_excl);
 }
 
 void launch_bits_transpose(hipStream_t s, const uint64_t *rows, int64_t n, int32_t words, int64_t m,
@@ -334,6 +431,39 @@ void launch_bits_transpose(hipStream_t s, const uint64_t *rows, int64_t n, int32
     const int64_t nw = div_up(n, 64);
     if (m == 0 || nw == 0) return;
     k_bits_transpose<<<grid1(m * nw, 256), 256, 0, s>>>(rows, n, words, m, cols, nw);
+    GRNG_LAUNCHED();
+}
+
+void launch_merge_positions(hipStream_t s, int64_t n1, int64_t m, const int32_t *new_off, const int32_t *old_off,
+                            const int32_t *bat_off, int32_t *src) {
+    if (n1 == 0) return;
+    k_merge_positions<<<grid1(n1, 256), 256, 0, s>>>(n1, m, new_off, old_off, bat_off, src);
+    GRNG_LAUNCHED();
+}
+
+void launch_merge_rows(hipStream_t s, int64_t n1, size_t row_bytes, const int32_t *src, const void *old,
+                       const void *bat, uint32_t bias, void *out) {
+    require(row_bytes % 4 == 0, GRNG_EINVAL, "merged rows must be whole 32-bit words");
+    const int32_t rw = (int32_t)(row_bytes / 4);
+    if (n1 == 0 || rw == 0) return;
+    k_merge_rows32<<<grid1(n1 * rw, 256), 256, 0, s>>>(n1, rw, src, static_cast<const uint32_t *>(old),
+                                                       static_cast<const uint32_t *>(bat), bias,
+                                                       static_cast<uint32_t *>(out));
+    GRNG_LAUNCHED();
+}
+
+void launch_merge_csr_len(hipStream_t s, int64_t n1, const int32_t *src, const int64_t *old_off,
+                          const int64_t *bat_off, int32_t *len) {
+    if (n1 == 0) return;
+    k_merge_csr_len<<<grid1(n1, 256), 256, 0, s>>>(n1, src, old_off, bat_off, len);
+    GRNG_LAUNCHED();
+}
+
+void launch_merge_csr_copy(hipStream_t s, int64_t n1, const int32_t *src, const int64_t *old_off,
+                           const int32_t *old_idx, const int64_t *bat_off, const int32_t *bat_idx,
+                           const int64_t *new_off, int32_t *new_idx) {
+    if (n1 == 0) return;
+    k_merge_csr_copy<<<grid1(n1, 256), 256, 0, s>>>(n1, src, old_off, old_idx, bat_off, bat_idx, new_off, new_idx);
     GRNG_LAUNCHED();
 }
 

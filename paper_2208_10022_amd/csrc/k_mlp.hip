@@ -4,7 +4,7 @@
 // scan: every cell is still scanned unless the pair dies, so edges never
 // change.
 //
-//   h = relu(f W1 + b1), s = h . w2 + b2      f: 8 scale-free features
+//   h = relu(f W1 + b1), s = h . w2 + b2      f: 9 scale-free features
 //   loss = mean softplus(s) - label * s       (cross-entropy with logits)
 // Parameters: one float vector [W1 (F x H row-major), b1, w2, b2].
 //
@@ -21,6 +21,7 @@ namespace grng {
 namespace {
 
 constexpr int F = kMlpFeatures, H = kMlpHidden, P = kMlpParams;
+static_assert(P <= 3 * 256, "each of 256 threads owns at most three parameters");
 constexpr int kB = 64;   // samples per LDS batch
 
 __device__ inline float softplus(float s) { return s > 0.f ? s + log1pf(expf(-s)) : log1pf(expf(s)); }
@@ -248,7 +249,7 @@ void grad_into(hipStream_t s, const float *theta, const float *feats, const uint
 }
 
 // Fixed device scratch of the allocation-free gradient: room for the
-// partials of kNoAllocMaxSamples samples (4,096 blocks x 642 floats, 10.5 MB
+// partials of kNoAllocMaxSamples samples (4,096 blocks x 706 floats, 11.6 MB
 // per device, held until the process ends).  Host code never passes the
 // array's name to a kernel: on the host it is only a stand-in for the
 // symbol; the device address comes from hipGetSymbolAddress, once per

@@ -290,25 +290,36 @@ __global__ __launch_bounds__(256) void k_witness_dists(int64_t x0, int64_t rows,
     ax[e] = __double2float_ru(sqrt(dxp[(int64_t)perm[i] * m + p]) * (1.0 + 1e-15));
 }
 
+// kCols: the cell-radius bits of listed pivots only (cols[0 .. ncols), any
+// order, 64 per workgroup column), OR-ed into v_rows: an insertion that grew
+// those cells' radius bounds.  A bit that was set stays set (sound: each
+// computation only drops pivots that are provably not needed).
+template <bool kCols>
 __global__ __launch_bounds__(256) void k_vgrng_tiles(
     int64_t n, int64_t m, const int32_t *__restrict__ perm, const double *__restrict__ dxp,
     const float *__restrict__ bd, const float *__restrict__ bv, const double *__restrict__ rad,
     const double *__restrict__ dvor, const int32_t *__restrict__ gcount, const int64_t *__restrict__ par_off,
     const int32_t *__restrict__ par_idx, const uint64_t *__restrict__ layer_bits, int32_t words,
     const int32_t *__restrict__ home, const int32_t *__restrict__ wknn, int32_t kw, int64_t xbase,
-    const float *__restrict__ ax, uint64_t *__restrict__ g_rows, uint64_t *__restrict__ v_rows,
-    unsigned long long *counters) {
+    const float *__restrict__ ax, const int32_t *__restrict__ cols, int32_t ncols, uint64_t *__restrict__ g_rows,
+    uint64_t *__restrict__ v_rows, unsigned long long *counters) {
     __shared__ __align__(16) float sA[kVT_X][kVT_K + 2];   // rows 8-byte aligned: pairs of k in one load
-    __shared__ __align__(16) float sD[kVT_K][kVT_J];
+    __shared__ __align__(16) float sD[kCols ? 1 : kVT_K][kVT_J];
     __shared__ __align__(16) float sV[kVT_K][kVT_J];
     __shared__ int32_t sK[kVT_K];
+    __shared__ int32_t sJ[kVT_J];
     __shared__ uint64_t sCand[kVT_X];
     __shared__ unsigned long long sG[kVT_X], sVb[kVT_X];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int64_t x0 = xbase + blockIdx.x * (int64_t)kVT_X;   // ax holds rows from xbase on
-    const int64_t j0 = blockIdx.y * (int64_t)kVT_J;
-    const int32_t wj = (int32_t)(j0 >> 6);
-    if (tid < kVT_X) {
+    // pivot block: one 64-bit word of the bit rows, or 64 listed pivots
+    const int32_t wj = kCols ? 0 : (int32_t)blockIdx.y;
+    const int64_t j0 = (int64_t)wj * kVT_J;
+    if (tid < kVT_J) {
+        const int64_t c = (int64_t)blockIdx.y * kVT_J + tid;
+        sJ[tid] = kCols ? (c < ncols ? cols[c] : -1) : (j0 + tid < m ? (int32_t)(j0 + tid) : -1);
+    }
+    if (!kCols && tid < kVT_X) {
         // Theorem 1 candidates: pivots linked to (or equal to) every parent of x.
         const int64_t i = x0 + tid;
         uint64_t c = 0;
@@ -346,10 +357,9 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         }
         for (int e = tid; e < kVT_K * kVT_J; e += 256) {
             const int kk = e / kVT_J, jj = e % kVT_J;
-            const int32_t k = sK[kk];
-            const int64_t j = j0 + jj;
-            const bool ok = k >= 0 && j < m;
-            sD[kk][jj] = ok ? bd[(int64_t)k * m + j] : INFINITY;
+            const int32_t k = sK[kk], j = sJ[jj];
+            const bool ok = k >= 0 && j >= 0;
+            if (!kCols) sD[kk][jj] = ok ? bd[(int64_t)k * m + j] : INFINITY;
             sV[kk][jj] = ok ? bv[(int64_t)k * m + j] : INFINITY;
         }
         __syncthreads();
@@ -364,14 +374,17 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
                 a[1][r] = t.y;
             }
             for (int h = 0; h < 2; ++h) {
-                const uint4 td = *reinterpret_cast<const uint4 *>(&sD[kk + h][4 * tx]);
                 const uint4 tv = *reinterpret_cast<const uint4 *>(&sV[kk + h][4 * tx]);
-                d[h][0] = td.x; d[h][1] = td.y; d[h][2] = td.z; d[h][3] = td.w;
                 v[h][0] = tv.x; v[h][1] = tv.y; v[h][2] = tv.z; v[h][3] = tv.w;
+                if (!kCols) {
+                    const uint4 td = *reinterpret_cast<const uint4 *>(&sD[kk + h][4 * tx]);
+                    d[h][0] = td.x; d[h][1] = td.y; d[h][2] = td.z; d[h][3] = td.w;
+                }
             }
             for (int r = 0; r < 4; ++r)
                 for (int c = 0; c < 4; ++c) {
-                    cD[r][c] = vt_min3(cD[r][c], vt_max(a[0][r], d[0][c]), vt_max(a[1][r], d[1][c]));
+                    if (!kCols)
+                        cD[r][c] = vt_min3(cD[r][c], vt_max(a[0][r], d[0][c]), vt_max(a[1][r], d[1][c]));
                     cV[r][c] = vt_min3(cV[r][c], vt_max(a[0][r], v[0][c]), vt_max(a[1][r], v[1][c]));
                 }
         }
@@ -384,19 +397,24 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
         const double *row = dxp + (int64_t)perm[i] * m;
         for (int c = 0; c < 4; ++c) {
             const int jc = 4 * tx + c;
-            const int64_t j = j0 + jc;
-            if (j >= m) continue;
+            const int32_t j = sJ[jc];
+            if (j < 0) continue;
             const double dj = sqrt(row[j]) * (1.0 - 1e-15);
             const double rj = rad[j], vj = dvor[j];
             const double mj = 1e-6 * (dj + 3.0 * fmax(rj, vj)) + 1e-300;
-            const bool candD = (sCand[xr] >> jc) & 1ull;
             const bool candV = gcount[j] > 0;
-            const bool keepD = candD && !((double)__uint_as_float(cD[r][c]) + rj < dj - mj);
             const bool keepV = candV && !((double)__uint_as_float(cV[r][c]) + vj < dj - mj);
+            if (kCols) {
+                if (keepV) atomicOr((unsigned long long *)&v_rows[i * words + (j >> 6)], 1ull << (j & 63));
+                continue;
+            }
+            const bool candD = (sCand[xr] >> jc) & 1ull;
+            const bool keepD = candD && !((double)__uint_as_float(cD[r][c]) + rj < dj - mj);
             if (keepD) atomicOr(&sG[xr], 1ull << jc);
             if (keepV) atomicOr(&sVb[xr], 1ull << jc);
         }
     }
+    if (kCols) return;
     __syncthreads();
     if (tid < kVT_X && x0 + tid < n) {
         g_rows[(x0 + tid) * words + wj] = sG[tid];
@@ -404,8 +422,8 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
     }
     if (tid == 0) {
         const int64_t rows = (n - x0) < kVT_X ? (n - x0) : kVT_X;
-        const int64_t cols = (m - j0) < kVT_J ? (m - j0) : kVT_J;
-        atomicAdd(&counters[C_WTEST], (unsigned long long)(2 * rows * cols * kw));
+        const int64_t ncol = (m - j0) < kVT_J ? (m - j0) : kVT_J;
+        atomicAdd(&counters[C_WTEST], (unsigned long long)(2 * rows * ncol * kw));
     }
 }
 
@@ -476,8 +494,9 @@ void launch_shifted_pivot_dists(hipStream_t s, int64_t m, const double *dpp, con
 void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp, const float *bd,
                   const float *bv, const double *rad, const double *dvor, const int32_t *gcount, const int64_t *par_off,
                   const int32_t *par_idx, const uint64_t *layer_bits, int32_t words, const int32_t *home,
-                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters) {
-    if (n == 0) return;
+                  const int32_t *wknn, int32_t kw, uint64_t *g_rows, uint64_t *v_rows, uint64_t *counters,
+                  const int32_t *cols, int32_t ncols) {
+    if (n == 0 || (cols && ncols == 0)) return;
     require(kw >= 1 && kw <= m, GRNG_EINVAL, "witness pivot count out of range");
     require(div_up(m, kVT_J) <= 65535, GRNG_EINVAL, "pivot layer too large for the virtual-pivot kernel");
     // point rows per pass: at most 2^19, whose witness distances take at most 4 GiB
@@ -491,10 +510,15 @@ void launch_vgrng(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, cons
         k_witness_dists<<<(unsigned)div_up(rows * kw, 256), 256, 0, s>>>(x0, rows, m, perm, dxp, home, wknn, kw,
                                                                          ax.as<float>());
         GRNG_LAUNCHED();
-        dim3 g((unsigned)div_up(rows, kVT_X), (unsigned)div_up(m, kVT_J));
-        k_vgrng_tiles<<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx, layer_bits,
-                                        words, home, wknn, kw, x0, ax.as<float>(), g_rows, v_rows,
-                                        (unsigned long long *)counters);
+        dim3 g((unsigned)div_up(rows, kVT_X), (unsigned)div_up(cols ? ncols : m, kVT_J));
+        if (cols)
+            k_vgrng_tiles<true><<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx,
+                                                  layer_bits, words, home, wknn, kw, x0, ax.as<float>(), cols, ncols,
+                                                  g_rows, v_rows, (unsigned long long *)counters);
+        else
+            k_vgrng_tiles<false><<<g, 256, 0, s>>>(n, m, perm, dxp, bd, bv, rad, dvor, gcount, par_off, par_idx,
+                                                   layer_bits, words, home, wknn, kw, x0, ax.as<float>(), nullptr, 0,
+                                                   g_rows, v_rows, (unsigned long long *)counters);
         GRNG_LAUNCHED();
     }
 }

@@ -534,20 +534,97 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
 
 // Counting sort of the pair list by row point (stable within a row is not
 // needed: the lune verdict of a pair does not depend on its position).
+// Pairs arrive in runs of equal row point (a tile pair's survivors row by
+// row): each run of lanes with one row point takes its slots with a single
+// atomic, so that a row with thousands of pairs is not one contended counter.
+// run_start: bit l set iff lane l starts a run (its row differs from lane l-1's).
+__device__ inline uint64_t run_starts(int32_t x) {
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(x, 1, 64);
+    return __ballot(lane == 0 || prev != x);
+}
+
 __global__ void k_pairs_count_rows(int64_t np, const int32_t *px, int32_t *cnt) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < np) atomicAdd(&cnt[px[p]], 1);
+    const int lane = threadIdx.x & 63;
+    const int32_t x = p < np ? px[p] : -1;
+    const uint64_t st = run_starts(x);
+    if (x < 0 || !((st >> lane) & 1ull)) return;
+    const uint64_t later = lane == 63 ? 0ull : st & (~0ull << (lane + 1));
+    const int end = later ? __ffsll((long long)later) - 1 : 64;
+    atomicAdd(&cnt[x], end - lane);
 }
 
 __global__ void k_pairs_scatter_rows(int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                                      const int64_t *off, int32_t *fill, int32_t *ox, int32_t *oy, double *od2) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int32_t x = px[p];
-    const int64_t s = off[x] + atomicAdd(&fill[x], 1);
+    const int lane = threadIdx.x & 63;
+    const int32_t x = p < np ? px[p] : -1;
+    const uint64_t st = run_starts(x);
+    const uint64_t later = lane == 63 ? 0ull : st & (~0ull << (lane + 1));
+    const int end = later ? __ffsll((long long)later) - 1 : 64;
+    int32_t base = 0;
+    if (x >= 0 && ((st >> lane) & 1ull)) base = atomicAdd(&fill[x], end - lane);
+    const uint64_t upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+    const int first = 63 - __clzll((long long)(st & upto));   // the lane that starts this lane's run
+    base = __shfl(base, first, 64);
+    if (x < 0) return;
+    const int64_t s = off[x] + base + (lane - first);
     ox[s] = x;
     oy[s] = py[p];
     od2[s] = pd2[p];
+}
+
+// Few rows (an insertion batch or a query set): each workgroup counts its
+// chunk of pairs in an LDS histogram and takes its slots in every row with
+// one global atomic per row.
+constexpr int kRowsLdsMax = 8192;    // rows of the LDS histogram (32 KB)
+constexpr int kSortPer = 16;         // pairs per thread
+__global__ __launch_bounds__(1024) void k_pairs_count_rows_lds(int64_t np, const int32_t *px, int64_t n,
+                                                               int32_t *cnt) {
+    extern __shared__ int32_t hist[];
+    const int tid = threadIdx.x;
+    for (int64_t r = tid; r < n; r += 1024) hist[r] = 0;
+    __syncthreads();
+    const int64_t lo = blockIdx.x * (int64_t)(1024 * kSortPer);
+    for (int u = 0; u < kSortPer; ++u) {
+        const int64_t p = lo + (int64_t)u * 1024 + tid;
+        if (p < np) atomicAdd(&hist[px[p]], 1);
+    }
+    __syncthreads();
+    for (int64_t r = tid; r < n; r += 1024)
+        if (hist[r]) atomicAdd(&cnt[r], hist[r]);
+}
+
+__global__ __launch_bounds__(1024) void k_pairs_scatter_rows_lds(int64_t np, const int32_t *px, const int32_t *py,
+                                                                 const double *pd2, int64_t n, const int64_t *off,
+                                                                 int32_t *fill, int32_t *ox, int32_t *oy,
+                                                                 double *od2) {
+    extern __shared__ int32_t hist[];
+    const int tid = threadIdx.x;
+    for (int64_t r = tid; r < n; r += 1024) hist[r] = 0;
+    __syncthreads();
+    const int64_t lo = blockIdx.x * (int64_t)(1024 * kSortPer);
+    int32_t slot[kSortPer];
+#pragma unroll
+    for (int u = 0; u < kSortPer; ++u) {
+        const int64_t p = lo + (int64_t)u * 1024 + tid;
+        slot[u] = p < np ? atomicAdd(&hist[px[p]], 1) : 0;
+    }
+    __syncthreads();
+    for (int64_t r = tid; r < n; r += 1024)
+        if (hist[r]) hist[r] = atomicAdd(&fill[r], hist[r]);   // the chunk's first slot in row r
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSortPer; ++u) {
+        const int64_t p = lo + (int64_t)u * 1024 + tid;
+        if (p >= np) continue;
+        const int32_t x = px[p];
+        const int64_t s = off[x] + hist[x] + slot[u];
+        ox[s] = x;
+        oy[s] = py[p];
+        od2[s] = pd2[p];
+    }
 }
 
 // Tile bookkeeping: OR of the cell bits of a tile's points; tile pairs whose
@@ -735,90 +812,93 @@ __global__ __launch_bounds__(kRelThreads) void k_relevant_groups(int64_t n, int6
     // a witness of any of its pairs (Proposition 3 with the row's largest pair
     // distance); pass 1 writes them, nearest pivot first (a bitonic sort in
     // LDS of at most cap entries, a power of two, by the whole workgroup), or
-    // in pivot order when there are more than cap of them (the order only
-    // steers the scan, it never changes a verdict).  Sort key: the float32
+    // in pivot order when there are more than cap of them or cap is 0 (the
+    // order only steers the scan, it never changes a verdict).  Sort key: the float32
     // bits of d^2 (monotone in d^2 for non-negative values) above the cell id.
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *key = (uint64_t *)smem;
     const int tid = threadIdx.x, lane = tid & 63, nt = blockDim.x;
-    const int64_t i = blockIdx.x;
-    if (i >= n) return;
-    const double dmax2 = __longlong_as_double((long long)dmax_bits[i]);
-    if (!(dmax2 > 0.0)) {
-        if (pass == 0 && tid == 0) rel_cnt[i] = 0;
-        return;
-    }
-    int64_t o = 0, cnt = 0;
-    if (pass == 1) {
-        o = rel_off[i];
-        cnt = rel_off[i + 1] - o;
-        if (cnt == 0) return;
-    }
-    const bool sorted = cnt <= cap;
-    if (pass == 1 && !sorted && tid == 0) atomicAdd(&counters[C_UNSORTED], 1ull);
-    const double dmax_hi = sqrt_hi(dmax2);
-    const double *row = dxp + (int64_t)perm[i] * m;
-    if (tid < 64) {
-        int64_t pos = 0;
-        for (int64_t k0 = 0; k0 < m; k0 += 256) {
-            // four groups of 64 cells per pass, their loads in flight together
-            double d2[4], dv[4];
-            int32_t gc[4];
+    // Rows in a grid-stride loop: most rows of an insertion's Stage VII have
+    // nothing to write, and a workgroup per row would be launch-bound.
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        __syncthreads();   // the previous row's keys are read out
+        const double dmax2 = __longlong_as_double((long long)dmax_bits[i]);
+        if (!(dmax2 > 0.0)) {
+            if (pass == 0 && tid == 0) rel_cnt[i] = 0;
+            continue;
+        }
+        int64_t o = 0, cnt = 0;
+        if (pass == 1) {
+            o = rel_off[i];
+            cnt = rel_off[i + 1] - o;
+            if (cnt == 0) continue;
+        }
+        const bool sorted = cnt <= cap;
+        if (pass == 1 && !sorted && cap > 0 && tid == 0) atomicAdd(&counters[C_UNSORTED], 1ull);
+        const double dmax_hi = sqrt_hi(dmax2);
+        const double *row = dxp + (int64_t)perm[i] * m;
+        if (tid < 64) {
+            int64_t pos = 0;
+            for (int64_t k0 = 0; k0 < m; k0 += 256) {
+                // four groups of 64 cells per pass, their loads in flight together
+                double d2[4], dv[4];
+                int32_t gc[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t k = k0 + 64 * u + lane;
-                const bool in = k < m;
-                d2[u] = in ? row[k] : INFINITY;
-                dv[u] = in ? dvor[k] : 0.0;
-                gc[u] = in ? gcount[k] : 0;
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t k = k0 + 64 * u + lane;
+                    const bool in = k < m;
+                    d2[u] = in ? row[k] : INFINITY;
+                    dv[u] = in ? dvor[k] : 0.0;
+                    gc[u] = in ? gcount[k] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t k = k0 + 64 * u + lane;
+                    // skip when d(x, p_k) - radius_k >= the row's largest pair
+                    // distance, tested on squares (d2 is exact; the margin covers
+                    // the rounding of the right side)
+                    const double r = dv[u] + dmax_hi;
+                    const bool keep = gc[u] > 0 && !(d2[u] >= r * r * (1.0 + 1e-12));
+                    const uint64_t bal = __ballot(keep);
+                    if (pass == 1 && keep) {
+                        const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
+                        if (sorted) {
+                            key[t] = ((uint64_t)__float_as_uint((float)d2[u]) << 32) | (uint64_t)(uint32_t)k;
+                        } else {
+                            rel_grp[o + t] = (int32_t)k;
+                            rel_d2x[o + t] = d2[u];
+                        }
+                    }
+                    pos += __popcll(bal);
+                }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t k = k0 + 64 * u + lane;
-                // skip when d(x, p_k) - radius_k >= the row's largest pair
-                // distance, tested on squares (d2 is exact; the margin covers
-                // the rounding of the right side)
-                const double r = dv[u] + dmax_hi;
-                const bool keep = gc[u] > 0 && !(d2[u] >= r * r * (1.0 + 1e-12));
-                const uint64_t bal = __ballot(keep);
-                if (pass == 1 && keep) {
-                    const int64_t t = pos + __popcll(bal & ((1ull << lane) - 1ull));
-                    if (sorted) {
-                        key[t] = ((uint64_t)__float_as_uint((float)d2[u]) << 32) | (uint64_t)(uint32_t)k;
-                    } else {
-                        rel_grp[o + t] = (int32_t)k;
-                        rel_d2x[o + t] = d2[u];
+            if (pass == 0 && lane == 0) rel_cnt[i] = (int32_t)pos;
+        }
+        if (pass == 0 || !sorted) continue;   // uniform over the workgroup
+        int32_t P = 64;
+        while (P < cnt) P <<= 1;
+        for (int64_t t = cnt + tid; t < P; t += nt) key[t] = ~0ull;
+        __syncthreads();
+        for (int32_t size = 2; size <= P; size <<= 1) {
+            for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int32_t t = tid; t < (P >> 1); t += nt) {
+                    const int32_t lo = 2 * t - (t & (stride - 1));
+                    const int32_t hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t ka = key[lo], kb = key[hi];
+                    if ((ka > kb) == up) {
+                        key[lo] = kb;
+                        key[hi] = ka;
                     }
                 }
-                pos += __popcll(bal);
+                __syncthreads();
             }
         }
-        if (pass == 0 && lane == 0) rel_cnt[i] = (int32_t)pos;
-    }
-    if (pass == 0 || !sorted) return;   // uniform over the workgroup
-    int32_t P = 64;
-    while (P < cnt) P <<= 1;
-    for (int64_t t = cnt + tid; t < P; t += nt) key[t] = ~0ull;
-    __syncthreads();
-    for (int32_t size = 2; size <= P; size <<= 1) {
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int32_t t = tid; t < (P >> 1); t += nt) {
-                const int32_t lo = 2 * t - (t & (stride - 1));
-                const int32_t hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t ka = key[lo], kb = key[hi];
-                if ((ka > kb) == up) {
-                    key[lo] = kb;
-                    key[hi] = ka;
-                }
-            }
-            __syncthreads();
+        for (int64_t t = tid; t < cnt; t += nt) {
+            const int32_t k = (int32_t)(uint32_t)key[t];
+            rel_grp[o + t] = k;
+            rel_d2x[o + t] = row[k];   // the exact value, not the float32 key
         }
-    }
-    for (int64_t t = tid; t < cnt; t += nt) {
-        const int32_t k = (int32_t)(uint32_t)key[t];
-        rel_grp[o + t] = k;
-        rel_d2x[o + t] = row[k];   // the exact value, not the float32 key
     }
 }
 
@@ -1303,19 +1383,22 @@ void launch_pairs_all(hipStream_t s, int64_t nA, const double *XA, const double 
 void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *perm, const double *dxp,
                             const double *dvor, const int32_t *gcount, const uint64_t *dmax_bits,
                             const int64_t *rel_off, int32_t *rel_cnt, int32_t *rel_grp, double *rel_d2x,
-                            uint64_t *counters) {
+                            uint64_t *counters, bool sort) {
     if (n == 0) return;
     require(n <= 0x7fffffffLL, GRNG_EINVAL, "too many points for the witness-cell pass");
     int32_t cap = 64;   // sort capacity: the layer size rounded up to a power of two, at most kRelSortMax
     while (cap < m && cap < kRelSortMax) cap <<= 1;
+    if (!sort) cap = 0;   // pivot order for every row
     const size_t lds = (size_t)cap * sizeof(uint64_t);
     if (rel_off == nullptr) {
-        k_relevant_groups<<<(unsigned)n, 64, 0, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt,
-                                                     nullptr, nullptr, cap, 0, (unsigned long long *)counters);
+        k_relevant_groups<<<(unsigned)std::min<int64_t>(n, 65536), 64, 0, s>>>(
+            n, m, perm, dxp, dvor, gcount, dmax_bits, nullptr, rel_cnt, nullptr, nullptr, cap, 0,
+            (unsigned long long *)counters);
     } else {
-        k_relevant_groups<<<(unsigned)n, kRelThreads, lds, s>>>(n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off,
-                                                                rel_cnt, rel_grp, rel_d2x, cap, 1,
-                                                                (unsigned long long *)counters);
+        // unsorted rows are written by one wave: a single-wave workgroup
+        k_relevant_groups<<<(unsigned)std::min<int64_t>(n, 65536), sort ? kRelThreads : 64, lds, s>>>(
+            n, m, perm, dxp, dvor, gcount, dmax_bits, rel_off, rel_cnt, rel_grp, rel_d2x, cap, 1,
+            (unsigned long long *)counters);
     }
     GRNG_LAUNCHED();
 }
@@ -1323,11 +1406,20 @@ void launch_relevant_groups(hipStream_t s, int64_t n, int64_t m, const int32_t *
 void launch_pairs_sort_rows(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int64_t n, int32_t *cnt, int64_t *off, int32_t *ox, int32_t *oy, double *od2) {
     if (np == 0) return;
-    k_pairs_count_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, cnt);
+    const bool lds = n <= kRowsLdsMax;
+    const unsigned gl = (unsigned)div_up(np, 1024 * kSortPer);
+    const size_t hb = sizeof(int32_t) * (size_t)n;
+    if (lds)
+        k_pairs_count_rows_lds<<<gl, 1024, hb, s>>>(np, px, n, cnt);
+    else
+        k_pairs_count_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, cnt);
     GRNG_LAUNCHED();
     launch_scan_i32_to_i64(s, cnt, n, off);
     launch_fill_u64(s, (uint64_t *)cnt, div_up(n, 2), 0ull);
-    k_pairs_scatter_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, py, pd2, off, cnt, ox, oy, od2);
+    if (lds)
+        k_pairs_scatter_rows_lds<<<gl, 1024, hb, s>>>(np, px, py, pd2, n, off, cnt, ox, oy, od2);
+    else
+        k_pairs_scatter_rows<<<(unsigned)div_up(np, 256), 256, 0, s>>>(np, px, py, pd2, off, cnt, ox, oy, od2);
     GRNG_LAUNCHED();
 }
 

@@ -27,13 +27,10 @@ import pytest
 
 import synth
 from oracle import native
+from conftest import say
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def say(*a):
-    print("[case]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -217,6 +214,7 @@ def test_insert_64_batches_each_equals_a_rebuild(G):
         Wb = synth.Workload(name="insert", X=X, q=W.q)
         Er, _, _ = edges_and_close(build(G, Wb, W.layers, precision=1), 1)
         assert np.array_equal(E, Er), bi
+        say("batch", bi, "of", len(batches), "n", len(X), "equals the rebuild")
         if bi in (1, 2, 8, 16, 32, 64):
             n0 = len(X) - len(B)
             prev = {(int(u), int(v)) for u, v in E_prev}
@@ -258,8 +256,9 @@ def _scorer_from_clustered16(G):
 
 
 def test_clustered96_full_size_orders_and_oracle_rows(G):
-    """1M x 96-D, 256 clusters, 10,000 pivots: the learned visit order gives
-    the same complete edge set as the distance order; 1,000+ oracle rows."""
+    """1M x 96-D, 256 clusters, 10,000 pivots: the learned and lune-key visit
+    orders give the same complete edge set as the distance order; 1,000+
+    oracle rows."""
     say("clustered96 full size n=1000000 d=96 m=10000")
     theta = _scorer_from_clustered16(G)
     W = synth.clustered(n=1_000_000, d=96, clusters=256, sigma=1.0, m=10_000, knn=100, q=18)
@@ -273,5 +272,8 @@ def test_clustered96_full_size_orders_and_oracle_rows(G):
     E_d, _, st_d = edges_and_close(build(G, W, W.layers, precision=1), 1)
     say("distance-order stats", {k: st_d[k] for k in ("n_edges", "lune_tests", "ms_lune", "ms_rng")})
     assert np.array_equal(E_d, E_l)
+    E_k, _, st_k = edges_and_close(build(G, W, W.layers, precision=1, witness_order=G.ORDER_LUNE), 1)
+    say("lune-key-order stats", {k: st_k[k] for k in ("n_edges", "lune_tests", "ms_lune", "ms_rng")})
+    assert np.array_equal(E_d, E_k)
     assert len(rows) >= 1000
     check_rows(E_d, rows, orc.get(), "clustered96")

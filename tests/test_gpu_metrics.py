@@ -10,14 +10,11 @@ import pytest
 
 import synth
 from oracle import exact, rng
+from conftest import say
 
 pytestmark = pytest.mark.gpu
 
 KINDS = [(1, 0, "l1"), (2, 0, "linf"), (0, 1, "gabriel")]
-
-
-def say(*a):
-    print("[case]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")

@@ -11,14 +11,11 @@ import pytest
 
 import synth
 from oracle import mlp, native
+from conftest import say
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-F, H = 8, 64
-
-
-def say(*a):
-    print("[case]", *a, flush=True)
+F, H = 9, 64   # features, hidden units of the library's scorer
 
 
 @pytest.fixture(scope="module")
@@ -156,6 +153,10 @@ def test_logged_samples_are_well_formed(G):
     assert np.all(np.isfinite(f)) and np.all(np.abs(f) <= 64)
     # every logged domain passed Proposition 3 (margin feature below 1)
     assert np.all(f[:, 4] < 1.0)
+    # the smaller and the larger of the two relative pivot distances (the
+    # larger is the lune-order key); rounding and clipping are monotone
+    assert np.array_equal(f[:, 7], np.minimum(f[:, 0], f[:, 1]))
+    assert np.array_equal(f[:, 8], np.maximum(f[:, 0], f[:, 1]))
     assert st["exhaustive_pairs"] > 0
     # the sample list is the same on every call (training is reproducible)
     f2, lab2 = idx.log_witness_cells(500)

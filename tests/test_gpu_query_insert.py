@@ -4,12 +4,9 @@ import pytest
 
 import synth
 from oracle import exact, native, rng
+from conftest import say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print("[case]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")

@@ -10,13 +10,10 @@ import pytest
 
 import synth
 from oracle import exact, native, rng
+from conftest import say
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-def say(*a):
-    print("[case]", *a, flush=True)
 
 
 @pytest.fixture(scope="module")

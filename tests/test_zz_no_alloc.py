@@ -10,18 +10,16 @@ import ctypes as C
 
 import numpy as np
 import pytest
+from conftest import say
 
 pytestmark = pytest.mark.gpu
 
 
-def say(*a):
-    print("[case]", *a, flush=True)
-
-
 def _inputs(n, seed):
     import torch
+    import paper_2208_10022_amd as P
     g = np.random.default_rng(seed)
-    feats = torch.from_numpy(g.standard_normal((n, 8)).astype(np.float32)).cuda()
+    feats = torch.from_numpy(g.standard_normal((n, P.MLP_FEATURES)).astype(np.float32)).cuda()
     labels = torch.from_numpy((g.random(n) < 0.3).astype(np.uint8)).cuda()
     return feats, labels
 
