@@ -219,7 +219,12 @@ grng_status grng_build_rng(grng_index *idx);
  * the RNG to RNG(S u B) (Section 2: localization Stages I-VI for each new
  * point against S u B, then Stage VII invalidation of existing edges by the
  * new points, Proposition 5).  Pivot layers stay as built.  Requires a prior
- * grng_build_rng.  Errors: EINVAL, ENOTGRID, ESTATE, ENOMEM, EDEVICE. */
+ * grng_build_rng.  The index keeps its per-point tables between calls (the
+ * point-pivot squared distances, float64 [n][m] with room for growth, home
+ * cells, parents, virtual-pivot bits): an insertion computes them for the
+ * batch only and merges them in, redoing only the cell bits of home cells
+ * whose radius grew.  The result equals a rebuild over S u B.  On error the
+ * index is unchanged.  Errors: EINVAL, ENOTGRID, ESTATE, ENOMEM, EDEVICE. */
 grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t nb);
 
 /* RNG neighbours of nq query points (float32 [nq][d], device) within S u {Q}

@@ -324,7 +324,32 @@ def test_failed_allocation_leaves_the_index_unchanged(G, monkeypatch):
     idx.build_rng()
     assert np.array_equal(idx.edges().cpu().numpy(), E0)
     idx.insert_batch(to_dev(B))
-    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), native.rng_edges(np.vstack([W.X, B]), W.q))
+    E1 = idx.edges().cpu().numpy()
+    assert np.array_equal(E1.astype(np.int64), native.rng_edges(np.vstack([W.X, B]), W.q))
+    # A second, smaller batch fits the room the first insertion left in the
+    # kept distance table, so the insertion hands that table to the new state
+    # and must give it back when a later allocation fails.
+    B2 = synth.insert_batches(W, n_batches=1, lo=100, hi=101, sub=10)[0]
+    failed = 0
+    for k in (1, 10, 30, 50, 70, 90, 120, 160, 220, 300, 400, 600):
+        monkeypatch.setenv("GRNG_FAIL_ALLOC_AT", str(k))
+        try:
+            idx.insert_batch(to_dev(B2))
+        except G.GrngError as e:
+            assert e.status == -2, k
+            failed += 1
+            monkeypatch.delenv("GRNG_FAIL_ALLOC_AT")
+            assert np.array_equal(idx.edges().cpu().numpy(), E1), k
+            assert idx.stats()["n_points"] == W.n + len(B), k
+            continue
+        monkeypatch.delenv("GRNG_FAIL_ALLOC_AT")
+        break   # fewer than k allocations: the insertion went through
+    say("insertion failed at", failed, "allocation counts before it went through")
+    assert failed >= 4
+    if idx.stats()["n_points"] == W.n + len(B):
+        idx.insert_batch(to_dev(B2))
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64),
+                          native.rng_edges(np.vstack([W.X, B, B2]), W.q))
     idx.close()
 
 
