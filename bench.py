@@ -346,7 +346,8 @@ def other_form(P, W, precision, st, witness_order=0, scorer=None, warmup=1):
 
 def form_entry(ms, st, same, base_ms):
     return {"ms": ms, "speedup_vs_plain": base_ms / ms, "identical_edges": bool(same),
-            "exhaustive_pairs": st["exhaustive_pairs"], "lune_tests": st["lune_tests"], "rechecks": st["rechecks"],
+            "exhaustive_pairs": st["exhaustive_pairs"], "lune_tests": st["lune_tests"],
+            "lune_tests_kept": st["lune_tests_kept"], "rechecks": st["rechecks"],
             "screen_uncertain": st["screen_uncertain"], "ms_pairs": st["ms_pairs"], "ms_lune": st["ms_lune"]}
 
 
@@ -483,6 +484,7 @@ def main():
         "stage4_survivors": st["stage4_survivors"],
         "exhaustive_pairs": st["exhaustive_pairs"],
         "lune_tests": st["lune_tests"],
+        "lune_tests_kept": st["lune_tests_kept"],
         "rechecks": st["rechecks"],
         "screen_uncertain": st["screen_uncertain"],
         "tile_pairs": st["tile_pairs"],

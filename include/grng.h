@@ -171,6 +171,8 @@ typedef struct grng_stats {
                                      D(T,U), the pivot blocks, and D(U,U), D(T,T) where Stage V ran */
     double pair_method_distances; /* of those, the ones the method uses: candidate pairs' d(x,y), the pivot
                                      blocks and the Stage V witness matrices */
+    double lune_tests_kept;       /* of lune_tests, those spent on pairs that stayed edges (each such pair
+                                     tests every witness its cells hold; no visit order saves them) */
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -55,7 +55,8 @@ class Stats(C.Structure):
                 ("ms_lune", C.c_double), ("vgrng_ops", C.c_double), ("pairs_flops", C.c_double),
                 ("lune_bytes", C.c_double), ("stage4_ops", C.c_double), ("ms_autotune", C.c_double),
                 ("ms_pair_masks", C.c_double), ("screen_uncertain", C.c_double),
-                ("pair_tile_entries", C.c_double), ("pair_method_distances", C.c_double)]
+                ("pair_tile_entries", C.c_double), ("pair_method_distances", C.c_double),
+                ("lune_tests_kept", C.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

@@ -133,7 +133,7 @@ struct PointState {
     int64_t ntiles = 0;
     int64_t nw = 0;                // words of a transposed bit row: ceil(n / 64)
     int64_t orphans = 0;
-    std::vector<int32_t> h_perm;   // home-order position -> index in the set
+    std::vector<int32_t> h_perm;   // home-order position -> index in the set (empty after an insertion merge)
     std::vector<int32_t> h_off;    // [m+1] home-order start of each home cell
     DevBuf perm;                   // int32 [n]
     DevBuf inv;                    // int32 [n] index -> home-order position
@@ -181,6 +181,7 @@ enum Counter {
     C_PD_TU,          // pair kernels: entries of D(T,U) computed
     C_PD_PIV,         // pair kernels: entries of the pivot blocks D(T,P), D(U,P) computed
     C_PD_V,           // pair kernels: entries of the Stage V witness matrices D(U,U), D(T,T) computed
+    C_LUNE_KEPT,      // exhaustive scan: witness predicates of pairs that stayed edges
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 16,

@@ -989,6 +989,7 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.screen_uncertain = (double)c[C_UNCERTAIN];
     idx->stats.pair_tile_entries = (double)(c[C_PD_TU] + c[C_PD_PIV] + c[C_PD_V]);
     idx->stats.pair_method_distances = (double)(c[C_CAND] + c[C_PD_PIV] + c[C_PD_V]);
+    idx->stats.lune_tests_kept = (double)c[C_LUNE_KEPT];
     // Bytes a witness test reads: the witness row and its cell-distance
     // bound (float32 with the float32 screen, float64 otherwise); a test
     // that ends early on a partial sum reads less.

@@ -243,7 +243,11 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     __bf16 *hPa = (__bf16 *)region, *lPa = hPa + kPiv * ks, *hPb = lPa + kPiv * ks, *lPb = hPb + kPiv * ks;
     float *XP = (float *)(lPb + kPiv * ks), *YP = XP + kTile * kXs;
     float *DUU = (float *)region, *DTT = DUU + kTile * kDl;
-    __shared__ int64_t s_tp;
+    __shared__ int64_t s_tp, s_nx;
+    // record words before the masks (tiles' start, length and cell, pivot
+    // ids): the current tile pair's, and the next one's, fetched one tile
+    // pair ahead so that no wave waits on the record before loading rows
+    __shared__ uint64_t s_cm[kPairRecMeta], s_nm[kPairRecMeta];
     __shared__ int s_any, s_newT, s_newB;
     __shared__ int32_t s_sx, s_b;   // T tile whose rows are in LDS; the cell its cross terms are for
     __shared__ float s_tau4, s_tau5;
@@ -253,22 +257,38 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     WaveOut wo;
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
-    int64_t cur = 0, cend = 0;
+    int64_t cur = 0, cend = 0, nxt = -2;   // thread 0: the claimed chunk; the tile pair after the current one
+    auto next_tp = [&]() -> int64_t {
+        if (cur >= cend && !claim_chunk(ntp, kPairChunk, xcd0, xr, work, &cur, &cend)) {
+            cur = cend = -1;
+            return -1;
+        }
+        return cur++;
+    };
+    uint64_t nmeta = 0;   // lanes 0-11 of wave 0: a word of the next tile pair's record
     if (threadIdx.x == 0) {
         s_sx = -1;
         s_b = -1;
     }
     for (;;) {
         if (threadIdx.x == 0) {
-            if (cur >= cend && !claim_chunk(ntp, kPairChunk, xcd0, xr, work, &cur, &cend)) cur = cend = -1;
-            s_tp = cur < cend ? cur++ : -1;
+            if (nxt == -2) {
+                nxt = next_tp();
+                if (nxt >= 0)
+                    for (int k = 0; k < kPairRecMeta; ++k) s_nm[k] = rec[nxt * kPairRecWords + k];
+            }
+            s_tp = nxt;
+            if (s_tp >= 0)
+                for (int k = 0; k < kPairRecMeta; ++k) s_cm[k] = s_nm[k];
+            nxt = s_tp >= 0 ? next_tp() : -1;
+            s_nx = nxt;
             s_any = 0;
             // T's rows stay in LDS while consecutive tile pairs share T, and
             // its cross terms while they also share U's cell
             int32_t st = -1, sb = -1;
             if (s_tp >= 0) {
-                st = (int32_t)rec[s_tp * kPairRecWords];
-                sb = (int32_t)(rec[s_tp * kPairRecWords + 2] >> 32);
+                st = (int32_t)s_cm[0];
+                sb = (int32_t)(s_cm[2] >> 32);
             }
             s_newT = st != s_sx;
             s_newB = s_newT || sb != s_b;
@@ -288,7 +308,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         const int lane = tid & 63, w = tid >> 6;
         const bool newT = s_newT != 0, newB = s_newB != 0;
         const uint64_t *rc = rec + tp * kPairRecWords;
-        const uint64_t m0 = rc[0], m1 = rc[1], m2 = rc[2];
+        const uint64_t m0 = s_cm[0], m1 = s_cm[1], m2 = s_cm[2];
         const int32_t sT = (int32_t)m0, lTn = (int32_t)(m0 >> 32);
         const int32_t a = (int32_t)m1, lUn = (int32_t)(m1 >> 32), sU = (int32_t)m2, b = (int32_t)(m2 >> 32);
         const float *pa = Xpf + (int64_t)a * dp, *pb = Xpf + (int64_t)b * dp;
@@ -301,13 +321,57 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         } else if (w == 5) {
             // 16 pivot rows, each centred at p_a and at p_b, four lanes per row;
             // slots past K repeat a valid pivot (their distances become +inf)
-            const int t = lane >> 2;
-            const int32_t pv = (int32_t)(rc[3 + (t >> 1)] >> (32 * (t & 1)));
+            // (each row read once and split for both centres)
+            const int t = lane >> 2, q4 = lane & 3;
+            const int32_t pv = (int32_t)(s_cm[3 + (t >> 1)] >> (32 * (t & 1)));
             const float *src = Xpf + (int64_t)pv * dp;
-            load_split(hPa + t * ks, lPa + t * ks, nullptr, nPa + t, nullptr, &rad[2], nullptr, src, 1, 1, dp, kp, ks,
-                       pa, nullptr, lane & 3, 4);
-            load_split(hPb + t * ks, lPb + t * ks, nullptr, nPb + t, nullptr, &rad[3], nullptr, src, 1, 1, dp, kp, ks,
-                       pb, nullptr, lane & 3, 4);
+            double acca = 0.0, accb = 0.0;
+            for (int c0 = 8 * q4; c0 < kp; c0 += kKb) {
+                float4 v[2], ca[2], cb[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int c = c0 + 4 * q;
+                    v[q] = ca[q] = cb[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (c < dp) {
+                        v[q] = *reinterpret_cast<const float4 *>(src + c);
+                        ca[q] = *reinterpret_cast<const float4 *>(pa + c);
+                        cb[q] = *reinterpret_cast<const float4 *>(pb + c);
+                    }
+                }
+                bf16x8 ha, la, hb, lb;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float xv[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+                    const float av[4] = {ca[q].x, ca[q].y, ca[q].z, ca[q].w};
+                    const float bv[4] = {cb[q].x, cb[q].y, cb[q].z, cb[q].w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float ea = xv[k] - av[k], eb = xv[k] - bv[k];
+                        const __bf16 h1 = (__bf16)ea, h2 = (__bf16)eb;
+                        ha[4 * q + k] = h1;
+                        la[4 * q + k] = (__bf16)(ea - (float)h1);
+                        hb[4 * q + k] = h2;
+                        lb[4 * q + k] = (__bf16)(eb - (float)h2);
+                        const double fa = (double)xv[k] - (double)av[k], fb = (double)xv[k] - (double)bv[k];
+                        acca = fma(fa, fa, acca);   // exact (grid values)
+                        accb = fma(fb, fb, accb);
+                    }
+                }
+                *reinterpret_cast<bf16x8 *>(hPa + t * ks + c0) = ha;
+                *reinterpret_cast<bf16x8 *>(lPa + t * ks + c0) = la;
+                *reinterpret_cast<bf16x8 *>(hPb + t * ks + c0) = hb;
+                *reinterpret_cast<bf16x8 *>(lPb + t * ks + c0) = lb;
+            }
+            acca += __shfl_xor(acca, 1, kWave);
+            acca += __shfl_xor(acca, 2, kWave);
+            accb += __shfl_xor(accb, 1, kWave);
+            accb += __shfl_xor(accb, 2, kWave);
+            if (q4 == 0) {
+                nPa[t] = (float)acca;
+                nPb[t] = (float)accb;
+                atomicMax(&rad[2], __float_as_uint(__double2float_ru(sqrt(acca) * (1.0 + 0x1p-50))));
+                atomicMax(&rad[3], __float_as_uint(__double2float_ru(sqrt(accb) * (1.0 + 0x1p-50))));
+            }
             // |p_a - p_b|^2, exact in float64 (partial sums over the lanes)
             double acc = 0.0;
             for (int c = lane; c < dp; c += 64) {
@@ -332,6 +396,11 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         if (newB) {
             cross_terms(hT, lT, l2T, pa, pb, lTn, dp, ks, fT, &rad[4], tid, kBThreads);
             __syncthreads();
+        }
+        // The next tile pair's record words, in flight until Stage IV ends.
+        if (tid < kPairRecMeta) {
+            const int64_t nx = s_nx;
+            if (nx >= 0) nmeta = rec[nx * kPairRecWords + tid];
         }
         // 2a. D(T,U) (two blocks per wave) and one block of pivot distances
         // (rows of T for waves 0-3, of U for 4-7).
@@ -417,6 +486,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             }
         }
         __syncthreads();
+        if (tid < kPairRecMeta) s_nm[tid] = nmeta;   // read by thread 0 (same wave) at the next claim
         if (tid == 0) {
             dtu += (uint64_t)lTn * (uint64_t)lUn;
             dpv += (uint64_t)(lTn + lUn) * (uint64_t)K;

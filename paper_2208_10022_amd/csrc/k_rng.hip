@@ -953,6 +953,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
     uint32_t ntests = 0, ndist = 0, nrecheck = 0;
+    unsigned long long nkept = 0;   // tests of pairs that stay edges
     // Float32 screen: the direct-form sum of dp squared float32 differences
     // has relative error below gamma_{dp+2} = (dp+2)u / (1 - (dp+2)u),
     // u = 2^-24 (one rounding per difference, one per fused multiply-add,
@@ -987,6 +988,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
         const float *xf = F32 ? Xxf + x * dp : nullptr;
         const float *yf = F32 ? Xhf + y * dp : nullptr;
         const float tlo = __double2float_rd(d2 - d2 * g32), thi = __double2float_ru(d2 + d2 * g32);
+        const uint32_t ntests0 = ntests;
         bool dead = false;
         const int64_t r0 = rel_off[x], r1 = rel_off[x + 1];
         for (int64_t c0 = r0; c0 < r1 && !dead; c0 += 64) {
@@ -1225,15 +1227,18 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             __builtin_amdgcn_wave_barrier();   // the table is rewritten by the next chunk
         }
         if (lane == 0) alive[p] = dead ? 0 : 1;
+        if (!dead) nkept += ntests - ntests0;
     }
     ntests = wave_sum(ntests);
     ndist = wave_sum(ndist);
     nrecheck = wave_sum(nrecheck);
+    for (int o = 32; o > 0; o >>= 1) nkept += __shfl_xor(nkept, o, kWave);
     if (lane == 0) {
         atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
         atomicAdd(&counters[C_LUNE], (unsigned long long)ntests);
         atomicAdd(&counters[C_DIST], (unsigned long long)ndist);
         if (nrecheck) atomicAdd(&counters[C_RECHECK], (unsigned long long)nrecheck);
+        if (nkept) atomicAdd(&counters[C_LUNE_KEPT], nkept);
     }
 }
 
