@@ -17,7 +17,10 @@ Other workloads (--workload), each printing its own line:
   clustered96  1M x 96-D, 256 clusters, 10,000 pivots: the learned and the
                lune visit orders against the distance order;
   insert       64 batches into the 100k index: the incremental insertion
-               against a rebuild at every batch.
+               against a rebuild at every batch;
+  hierarchy    number of layers and pivot counts over 300k x 32-D points;
+  pivots       200 orphans of the 100k index promoted to pivots with
+               insert_pivots, against a rebuild with the merged pivots.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
@@ -258,7 +261,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="subspace3",
-                    choices=["subspace3", "clustered", "clustered96", "insert", "hierarchy"])
+                    choices=["subspace3", "clustered", "clustered96", "insert", "hierarchy", "pivots"])
     ap.add_argument("--precision", type=int, default=-1, help="0 = float64 everywhere, 1 = float32 screens "
                     "(the plain float32 form), 2 = bf16 tiles; -1 = the workload's form (2 for subspace3, "
                     "else 1)")
@@ -399,6 +402,8 @@ def main():
         return bench_insert(args)
     if args.workload == "hierarchy":
         return bench_hierarchy(args)
+    if args.workload == "pivots":
+        return bench_pivots(args)
 
     import paper_2208_10022_amd as P
 
@@ -555,6 +560,61 @@ def bench_insert(args):
         "forms": {"batched_insert_total_ms": total, "rebuild_total_ms": sum(reb_ms),
                   "speedup_vs_rebuild": sum(reb_ms) / total, "identical_edges_after_every_batch": bool(same),
                   "insert_ms": ins_ms, "rebuild_ms": reb_ms},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_pivots(args):
+    """Dynamic pivot layer on the 100k x 16-D index: 200 orphans (seeded
+    choice) promoted to pivots with 100-NN radii by insert_pivots (the layer's
+    GRNG updated in place, the per-point tables rebuilt against it), against
+    building the merged layer and the RNG from scratch; layer and RNG edge
+    sets compared in full."""
+    import numpy as np
+    import torch
+
+    import paper_2208_10022_amd as P
+    import synth
+    W, desc = workload_of("clustered")
+    L = W.layers[0]
+    b = Builder(P, W, precision=1, autotune=0)
+    b.step()
+    b.step()
+    orph = b.idx.orphans().cpu().numpy()
+    g = np.random.default_rng(2208)
+    promote = np.sort(g.choice(orph, min(200, len(orph)), replace=False)).astype(np.int32)
+    prad = synth.knn_radii(W.X, W.q, promote, 100)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pid, rad = torch.from_numpy(promote).cuda(), torch.from_numpy(prad).cuda()
+    torch.cuda.synchronize()
+    e0.record()
+    b.idx.insert_pivots(0, pid, rad)
+    e1.record()
+    e1.synchronize()
+    ins_ms = e0.elapsed_time(e1)
+    orph_after = int(b.idx.orphans().numel())
+    E_layer, E = b.idx.edges(0).cpu().numpy(), b.idx.edges().cpu().numpy()
+    b.idx.close()
+    ids = np.concatenate([L.pivot_ids, promote])
+    rads = np.concatenate([L.radii, prad])
+    order = np.argsort(ids)
+    Wm = synth.Workload(name="merged", X=W.X, q=W.q,
+                        layers=[synth.PivotLayer(ids[order].astype(np.int32), rads[order].astype(np.float32))])
+    r = Builder(P, Wm, precision=1, autotune=0)
+    r.step()
+    reb_ms = r.timed()
+    same = np.array_equal(r.idx.edges(0).cpu().numpy(), E_layer) and np.array_equal(r.idx.edges().cpu().numpy(), E)
+    r.idx.close()
+    line = {
+        "metric": "exact-RNG build time (s) & witness tests/s vs plain GPU form; MFMA%/HBM GB/s",
+        "value": ins_ms / 1000.0, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 2, "ms_per_step": ins_ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d orphans of the %s promoted to pivots" % (len(promote), desc),
+                   "precision": PRECISION_NAMES[1]},
+        "forms": {"insert_pivots_ms": ins_ms, "rebuild_ms": reb_ms, "speedup_vs_rebuild": reb_ms / ins_ms,
+                  "identical_layer_and_rng_edges": bool(same), "orphans_before": int(len(orph)),
+                  "orphans_after": orph_after, "pivots_before": int(len(L.pivot_ids)),
+                  "pivots_after": int(len(ids))},
     }
     print(json.dumps(line), flush=True)
 

@@ -206,6 +206,30 @@ grng_status grng_create(grng_index **out, const float *points_dev, int64_t n, in
 grng_status grng_build_grng_layer(grng_index *idx, int32_t layer, const int32_t *pivot_ids_dev,
                                   const float *radii_dev, int64_t m);
 
+/* Add nb pivots to the built layer `layer` (Section 2, Stage I promotes a
+ * point without parents to a pivot; Section 3 inserts pivots into a GRNG
+ * layer with Stages I-VI and unlinks old pivots with Stage VII): the layer's
+ * GRNG becomes GRNG(P u B) under Definition 1.  Old links are re-tested
+ * against the new pivots only (adding pivots can only unlink a pair), pairs
+ * with a new pivot against every pivot.  pivot_ids_dev: int32 [nb] point ids,
+ * strictly ascending, none a pivot of this layer yet; each must already be a
+ * pivot of every finer layer (layers stay nested).  radii_dev: float32 [nb]
+ * radii >= 0 on the grid; old pivots keep theirs.  The exemplar RNG does not
+ * change; when the finest layer changes after grng_build_rng, the index
+ * recomputes its per-point tables against it, so later insertions and
+ * queries use the new pivots.  On error the index is unchanged.  Errors:
+ * EINVAL, ENOTGRID, ESTATE, ENOMEM, EDEVICE. */
+grng_status grng_insert_pivots(grng_index *idx, int32_t layer, const int32_t *pivot_ids_dev, const float *radii_dev,
+                               int64_t nb);
+
+/* Ids (int32, ascending, device) of the points without a parent in the
+ * finest layer (no pivot domain holds them: the candidates for promotion
+ * with grng_insert_pivots).  *count = their number; if it exceeds capacity,
+ * returns ECAPACITY and copies nothing (ids_dev may be NULL with capacity 0).
+ * Requires a pivot layer and a prior grng_build_rng.  Errors: EINVAL,
+ * ESTATE, ECAPACITY, EDEVICE. */
+grng_status grng_get_orphans(grng_index *idx, int32_t *ids_dev, int64_t capacity, int64_t *count);
+
 /* Build the exact RNG of all indexed points (Section 1, RNG definition:
  * u, v linked iff no z has max(d(u,z), d(v,z)) < d(u,v); ties keep the edge).
  * With at least one layer built, candidate pairs and witnesses are pruned by

@@ -14,7 +14,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgrng.so")
 
-GRNG_OK = 0
+GRNG_OK, GRNG_ECAPACITY = 0, -5
 STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_EDEVICE", -4: "GRNG_ENOTGRID",
                 -5: "GRNG_ECAPACITY", -6: "GRNG_ESTATE"}
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
@@ -26,7 +26,7 @@ GRAPH_RNG, GRAPH_GABRIEL = 0, 1
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
                  "grng_insert_batch", "grng_query_neighbors", "grng_get_edges", "grng_get_stats", "grng_destroy",
                  "grng_mlp_params", "grng_mlp_grad", "grng_mlp_grad_noalloc", "grng_mlp_train", "grng_mlp_score", "grng_log_witness_cells",
-                 "grng_set_scorer")
+                 "grng_set_scorer", "grng_insert_pivots", "grng_get_orphans")
 MLP_FEATURES, MLP_HIDDEN = 9, 64
 
 
@@ -81,6 +81,8 @@ def lib():
             "grng_build_grng_layer": (i32, [vp, i32, vp, vp, i64]),
             "grng_build_rng": (i32, [vp]),
             "grng_insert_batch": (i32, [vp, vp, i64]),
+            "grng_insert_pivots": (i32, [vp, i32, vp, vp, i64]),
+            "grng_get_orphans": (i32, [vp, vp, i64, C.POINTER(i64)]),
             "grng_query_neighbors": (i32, [vp, vp, i64, vp, vp, i64, C.POINTER(i64)]),
             "grng_get_edges": (i32, [vp, i32, vp, i64, C.POINTER(i64)]),
             "grng_get_stats": (i32, [vp, C.POINTER(Stats)]),
@@ -216,6 +218,26 @@ class Index:
     def insert_batch(self, points) -> None:
         check(lib().grng_insert_batch(self._h, _dev_ptr(points, "float32", 2), points.shape[0]))
 
+    def insert_pivots(self, layer: int, pivot_ids, radii) -> None:
+        """Add pivots (ascending point ids, not yet pivots of `layer`) with their radii to a built layer."""
+        m = pivot_ids.numel()
+        if radii.numel() != m:
+            raise ValueError("pivot_ids and radii differ in length")
+        check(lib().grng_insert_pivots(self._h, layer, _dev_ptr(pivot_ids, "int32", 1),
+                                       _dev_ptr(radii, "float32", 1), m))
+
+    def orphans(self):
+        """Ids of the points without a parent in the finest layer (int32 device tensor, ascending)."""
+        import torch
+        n = C.c_int64(0)
+        st = lib().grng_get_orphans(self._h, None, 0, C.byref(n))
+        if st not in (GRNG_OK, GRNG_ECAPACITY):
+            check(st)
+        out = torch.empty(max(n.value, 1), dtype=torch.int32, device="cuda")
+        n2 = C.c_int64(0)
+        check(lib().grng_get_orphans(self._h, _dev_ptr(out, "int32") if n.value else None, n.value, C.byref(n2)))
+        return out[:n.value]
+
     def query_neighbors(self, queries):
         """Returns (offsets int64 [nq+1], neighbours int32 [total]) as device tensors."""
         import torch
@@ -252,7 +274,7 @@ class Index:
         return out
 
     def log_witness_cells(self, max_pairs: int):
-        """Training samples (feats float32 [n, 8], labels uint8 [n]) from the last build."""
+        """Training samples (feats float32 [n, MLP_FEATURES], labels uint8 [n]) from the last build."""
         import torch
         cnt = C.c_int64(0)
         st = lib().grng_log_witness_cells(self._h, max_pairs, None, None, 0, C.byref(cnt))

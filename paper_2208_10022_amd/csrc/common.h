@@ -315,9 +315,13 @@ void launch_bits_transpose(hipStream_t s, const uint64_t *rows, int64_t n, int32
 void launch_fill_u64(hipStream_t s, uint64_t *p, int64_t count, uint64_t v);
 
 // k_pivots.hip
+// Candidates after adding pivots to a layer: pairs with a new pivot, and old links.
+void launch_insert_candidates(hipStream_t s, int64_t m1, int32_t words1, const int32_t *oldpos,
+                              const uint64_t *old_bits, int32_t words0, uint64_t *cand);
 void launch_grng_layer(hipStream_t s, int64_t m, const double *dpp, const double *dpp2, const double *rad,
                        const int64_t *radi, int32_t q, const uint64_t *cand_bits, int32_t words,
-                       const int32_t *witness_first, int64_t nfirst, uint64_t *bits, uint64_t *counters);
+                       const int32_t *witness_first, int64_t nfirst, uint64_t *bits, uint64_t *counters,
+                       const uint8_t *isnew = nullptr);
 void launch_relative_parents(hipStream_t s, int64_t mc, const int32_t *coarse_pos_in_fine,
                              const double *dpp2_fine, int64_t mf, const double *rad_c, const double *rad_f,
                              uint64_t *parent_bits, int32_t cwords);

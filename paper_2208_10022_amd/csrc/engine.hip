@@ -1310,6 +1310,167 @@ void do_insert(grng_index *idx, const float *pts, int64_t nb) {
     fill_build_stats(idx, bt);
 }
 
+// Pivots added to a built layer: the dynamic pivot layers of the paper
+// (Section 2, Stage I promotes a point without parents to a pivot; Section 3
+// inserts pivots into a GRNG layer with Stages I-VI and unlinks pivots with
+// Stage VII).  The layer's GRNG becomes GRNG(P u B) exactly.  Adding pivots
+// can only unlink a pair of old pivots (a new pivot may lie in its
+// generalized lune), so the candidates are the old links, tested against the
+// new pivots only, and every pair with a new pivot, tested against all.
+// Layers stay nested: a pivot added to layer l must already be a pivot of
+// every finer layer.  The exemplar RNG does not depend on the pivots; when
+// the finest layer changes, the kept per-point state is rebuilt against it.
+void do_insert_pivots(grng_index *idx, int32_t layer, const int32_t *pid_dev, const float *rad_dev, int64_t nb) {
+    require(idx != nullptr, GRNG_EINVAL, "index is NULL");
+    require(pid_dev != nullptr && rad_dev != nullptr, GRNG_EINVAL, "pivot or radius pointer is NULL");
+    require(layer >= 0 && layer < (int32_t)idx->layers.size(), GRNG_ESTATE, "no such layer");
+    require(nb >= 1, GRNG_EINVAL, "nb must be >= 1");
+    hipStream_t s = idx->stream;
+    EventTimer timer(s);
+    reset_counters(idx);
+    const Layer &O = idx->layers[layer];
+    const int64_t m0 = O.m, m1 = m0 + nb;
+    require(m1 <= idx->n, GRNG_EINVAL, "more pivots than points");
+    std::vector<int32_t> nid;
+    d2h(nid, pid_dev, (size_t)nb, s);
+    for (int64_t t = 0; t < nb; ++t) {
+        require(nid[t] >= 0 && nid[t] < idx->n, GRNG_EINVAL, "pivot id out of range");
+        require(t == 0 || nid[t] > nid[t - 1], GRNG_EINVAL, "new pivot ids must be strictly ascending");
+        require(!std::binary_search(O.pid_host.begin(), O.pid_host.end(), nid[t]), GRNG_EINVAL,
+                "a new pivot is already a pivot of this layer");
+        for (size_t l = (size_t)layer + 1; l < idx->layers.size(); ++l)
+            require(std::binary_search(idx->layers[l].pid_host.begin(), idx->layers[l].pid_host.end(), nid[t]),
+                    GRNG_EINVAL, "a pivot added to layer l must be a pivot of every finer layer");
+    }
+    (void)grid_validate(idx, rad_dev, nb, "radii");
+    std::vector<float> nrad;
+    d2h(nrad, rad_dev, (size_t)nb, s);
+    std::vector<double> orad;
+    std::vector<int64_t> oradi;
+    d2h(orad, O.rad.p, (size_t)m0, s);
+    d2h(oradi, O.radi.p, (size_t)m0, s);
+    // Merged pivot list, ascending ids: old position of each (-1: new).
+    Layer L;
+    L.m = m1;
+    L.words = words_of(m1);
+    L.pid_host.resize((size_t)m1);
+    std::vector<int32_t> oldpos((size_t)m1), newpos;
+    std::vector<uint8_t> isnew((size_t)m1, 0);
+    std::vector<double> rad_d((size_t)m1);
+    std::vector<int64_t> rad_i((size_t)m1);
+    for (int64_t a = 0, b = 0, t = 0; t < m1; ++t) {
+        if (b >= nb || (a < m0 && O.pid_host[a] < nid[b])) {
+            L.pid_host[t] = O.pid_host[a];
+            oldpos[t] = (int32_t)a;
+            rad_d[t] = orad[a];
+            rad_i[t] = oradi[a];
+            ++a;
+        } else {
+            require(nrad[b] >= 0.0f, GRNG_ENOTGRID, "radii must be >= 0");
+            L.pid_host[t] = nid[b];
+            oldpos[t] = -1;
+            isnew[t] = 1;
+            newpos.push_back((int32_t)t);
+            rad_d[t] = (double)nrad[b];
+            rad_i[t] = (int64_t)std::ldexp(rad_d[t], idx->q);
+            ++b;
+        }
+    }
+    h2d(L.pid, L.pid_host, s);
+    h2d(L.rad, rad_d, s);
+    h2d(L.radi, rad_i, s);
+    DevBuf Xp, nrmp;
+    Xp.alloc(sizeof(double) * (size_t)(m1 * idx->dp));
+    nrmp.alloc(sizeof(double) * (size_t)m1);
+    launch_gather_rows(s, idx->X.as<double>(), L.pid.as<int32_t>(), m1, idx->dp, Xp.as<double>());
+    launch_gather_f64(s, idx->nrm.as<double>(), L.pid.as<int32_t>(), m1, nrmp.as<double>());
+    L.dpp2.alloc(sizeof(double) * (size_t)(m1 * m1));
+    L.dpp.alloc(sizeof(double) * (size_t)(m1 * m1));
+    launch_dist2(s, Xp.as<double>(), nrmp.as<double>(), m1, Xp.as<double>(), nrmp.as<double>(), m1, idx->dp,
+                 L.dpp2.as<double>(), m1, true);
+    launch_sqrt(s, L.dpp2.as<double>(), L.dpp.as<double>(), m1 * m1);
+    // Candidates (old links and pairs with a new pivot); new pivots are the
+    // first witnesses, the only ones for old links.
+    DevBuf d_oldpos, d_isnew, d_new, cand;
+    h2d(d_oldpos, oldpos, s);
+    h2d(d_isnew, isnew, s);
+    h2d(d_new, newpos, s);
+    cand.alloc(sizeof(uint64_t) * (size_t)(m1 * L.words));
+    launch_insert_candidates(s, m1, L.words, d_oldpos.as<int32_t>(), O.bits.as<uint64_t>(), O.words,
+                             cand.as<uint64_t>());
+    L.bits.alloc(sizeof(uint64_t) * (size_t)(m1 * L.words));
+    launch_grng_layer(s, m1, L.dpp.as<double>(), L.dpp2.as<double>(), L.rad.as<double>(), L.radi.as<int64_t>(),
+                      idx->q, cand.as<uint64_t>(), L.words, d_new.as<int32_t>(), nb, L.bits.as<uint64_t>(),
+                      idx->counters.as<uint64_t>(), d_isnew.as<uint8_t>());
+    bits_to_edges(s, m1, L.bits, L.words, L.edges, L.nedges);
+    // Relative-domain parents (Theorem 2) of this layer and of the next finer one.
+    auto parents_of = [&](const Layer &C, const Layer &F, DevBuf &out) {
+        std::vector<int32_t> cpos((size_t)C.m);
+        for (int64_t t = 0; t < C.m; ++t)
+            cpos[t] = (int32_t)(std::lower_bound(F.pid_host.begin(), F.pid_host.end(), C.pid_host[t]) -
+                                F.pid_host.begin());
+        DevBuf d_cpos;
+        h2d(d_cpos, cpos, s);
+        out.alloc(sizeof(uint64_t) * (size_t)(F.m * C.words));
+        launch_relative_parents(s, C.m, d_cpos.as<int32_t>(), F.dpp2.as<double>(), F.m, C.rad.as<double>(),
+                                F.rad.as<double>(), out.as<uint64_t>(), C.words);
+    };
+    if (layer > 0) parents_of(idx->layers[layer - 1], L, L.parent_bits);
+    DevBuf next_parents;
+    const bool has_finer = layer + 1 < (int32_t)idx->layers.size();
+    if (has_finer) parents_of(L, idx->layers[layer + 1], next_parents);
+    // The finest layer changed: per-point state against it.
+    const bool finest = !has_finer;
+    PointState ps;
+    LayerAux aux;
+    BuildTimes bt;
+    if (finest && idx->rng_built) {
+        prepare_aux(idx, L, aux);
+        prepare_points(idx, L, aux, idx->X.as<double>(), idx->nrm.as<double>(), idx->n, nullptr, nullptr, ps, bt,
+                       true);
+    }
+    const double ms = timer.stop();
+    uint64_t c[C_NUM];
+    read_counters(idx, c);
+    // Commit.
+    idx->layers[layer] = std::move(L);
+    if (has_finer) idx->layers[layer + 1].parent_bits = std::move(next_parents);
+    if (finest && idx->rng_built) {
+        idx->ps = std::move(ps);
+        idx->aux = std::move(aux);
+        idx->ex = ExhaustiveState();
+        idx->stats.orphans = idx->ps.orphans;
+    }
+    idx->stats.n_layers = (int64_t)idx->layers.size();
+    idx->stats.ms_layers = ms;
+    idx->stats.witness_tests = (double)c[C_WTEST];
+    idx->stats.rechecks = (double)c[C_RECHECK];
+}
+
+// Ids of the points without a parent in the finest layer (orphans), ascending.
+void do_get_orphans(grng_index *idx, int32_t *ids_dev, int64_t capacity, int64_t *count) {
+    require(idx != nullptr && count != nullptr, GRNG_EINVAL, "NULL argument");
+    require(capacity >= 0, GRNG_EINVAL, "capacity must be >= 0");
+    require(idx->rng_built && !idx->layers.empty(), GRNG_ESTATE, "needs a pivot layer and a built RNG");
+    hipStream_t s = idx->stream;
+    const PointState &P = idx->ps;
+    std::vector<int64_t> off;
+    std::vector<int32_t> perm;
+    d2h(off, P.par_off.p, (size_t)(P.n + 1), s);
+    d2h(perm, P.perm.p, (size_t)P.n, s);
+    std::vector<int32_t> ids;
+    for (int64_t i = 0; i < P.n; ++i)
+        if (off[i + 1] == off[i]) ids.push_back(perm[i]);
+    std::sort(ids.begin(), ids.end());
+    *count = (int64_t)ids.size();
+    if ((int64_t)ids.size() > capacity) throw Error(GRNG_ECAPACITY, "id buffer too small");
+    if (!ids.empty()) {
+        require(ids_dev != nullptr, GRNG_EINVAL, "id pointer is NULL");
+        GRNG_HIP(hipMemcpyAsync(ids_dev, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, s));
+        GRNG_HIP(hipStreamSynchronize(s));
+    }
+}
+
 void do_get_edges(const grng_index *idx, int32_t layer, int32_t *uv, int64_t capacity, int64_t *num) {
     require(idx != nullptr, GRNG_EINVAL, "index is NULL");
     require(num != nullptr, GRNG_EINVAL, "num_edges pointer is NULL");
@@ -1567,6 +1728,21 @@ grng_status grng_insert_batch(grng_index *idx, const float *points_dev, int64_t 
     return guarded([&] {
         PoolScope ps(idx);
         do_insert(idx, points_dev, nb);
+    });
+}
+
+grng_status grng_insert_pivots(grng_index *idx, int32_t layer, const int32_t *pivot_ids_dev, const float *radii_dev,
+                               int64_t nb) {
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_insert_pivots(idx, layer, pivot_ids_dev, radii_dev, nb);
+    });
+}
+
+grng_status grng_get_orphans(grng_index *idx, int32_t *ids_dev, int64_t capacity, int64_t *count) {
+    return guarded([&] {
+        PoolScope ps(idx);
+        do_get_orphans(idx, ids_dev, capacity, count);
     });
 }
 

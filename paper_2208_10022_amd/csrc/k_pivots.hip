@@ -50,11 +50,15 @@ __device__ inline bool side_lt(double dk, double c, double dij, double d2k, int6
 }
 
 // One wave per (row i, 64 consecutive columns j); only j > i is tested.
+// isnew (pivots added to a built layer, or null): a pair of two old pivots was
+// linked before the addition, so only the new pivots (listed first in
+// wfirst) can block it (the pivot-level Stage VII); other pairs test every
+// witness.
 __global__ __launch_bounds__(256) void k_grng_layer(int64_t m, const double *dpp, const double *dpp2,
                                                     const double *rad, const int64_t *radi, double s2,
                                                     const uint64_t *cand_bits, int32_t words,
-                                                    const int32_t *wfirst, int64_t nfirst, uint64_t *bits,
-                                                    unsigned long long *counters) {
+                                                    const int32_t *wfirst, int64_t nfirst, const uint8_t *isnew,
+                                                    uint64_t *bits, unsigned long long *counters) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t i = wave / words;
@@ -68,20 +72,22 @@ __global__ __launch_bounds__(256) void k_grng_layer(int64_t m, const double *dpp
     const double dij = active ? dpp[i * m + j] : 0.0, d2ij = active ? dpp2[i * m + j] : 0.0;
     const double c1 = 2.0 * ri + rj, c2 = ri + 2.0 * rj;
     const int64_t c1i = 2 * rii + rji, c2i = rii + 2 * rji;
-    bool linked = active;
+    const bool oldpair = isnew && active && !isnew[i] && !isnew[j];
+    bool linked = active, live = active;   // live: still testing witnesses
     uint32_t tests = 0, rechecks = 0;
     const int64_t total = nfirst + m;
     for (int64_t s = 0; s < total; ++s) {
-        if (!__ballot(linked)) break;
+        if (s == nfirst && oldpair) live = false;
+        if (!__ballot(live)) break;
         const int64_t k = s < nfirst ? wfirst[s] : s - nfirst;
-        if (!linked || k == i || k == j) continue;
+        if (!live || k == i || k == j) continue;
         ++tests;
         // Cheap exact pre-test on squared distances: dk + c < dij needs dk^2 < dij^2.
         const double d2ki = dpp2[k * m + i], d2kj = dpp2[k * m + j];
         if (d2ki >= d2ij || d2kj >= d2ij) continue;
         if (side_lt(dpp[k * m + i], c1, dij, d2ki, c1i, d2ij, s2, rechecks) &&
             side_lt(dpp[k * m + j], c2, dij, d2kj, c2i, d2ij, s2, rechecks))
-            linked = false;
+            linked = live = false;
     }
     const uint64_t word = __ballot(linked);
     if (lane == 0) bits[i * words + wj] = word;
@@ -93,6 +99,29 @@ __global__ __launch_bounds__(256) void k_grng_layer(int64_t m, const double *dpp
         atomicAdd(&counters[C_WTEST], (unsigned long long)tests);
         atomicAdd(&counters[C_RECHECK], (unsigned long long)rechecks);
     }
+}
+
+// Candidate pairs after pivots were added to a layer (m1 pivots, positions
+// of the merged ascending id list): every pair with a new pivot, and the
+// pairs of old pivots that were linked (adding witnesses can only unlink).
+// oldpos[i]: the old position of pivot i, or -1 for a new one.
+__global__ void k_insert_candidates(int64_t m1, int32_t words1, const int32_t *oldpos, const uint64_t *old_bits,
+                                    int32_t words0, uint64_t *cand) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= m1 * (int64_t)words1) return;
+    const int64_t i = e / words1;
+    const int32_t w = (int32_t)(e % words1);
+    const int32_t oi = oldpos[i];
+    uint64_t acc = 0;
+    for (int b = 0; b < 64; ++b) {
+        const int64_t j = (int64_t)w * 64 + b;
+        if (j >= m1) break;
+        if (j == i) continue;
+        const int32_t oj = oldpos[j];
+        const bool c = oi < 0 || oj < 0 || ((old_bits[(int64_t)oi * words0 + (oj >> 6)] >> (oj & 63)) & 1ull);
+        acc |= (uint64_t)c << b;
+    }
+    cand[e] = acc;
 }
 
 // Mirror the upper triangle: bit (j, i) = bit (i, j) for i < j.
@@ -431,16 +460,25 @@ __global__ __launch_bounds__(256) void k_vgrng_tiles(
 
 void launch_grng_layer(hipStream_t s, int64_t m, const double *dpp, const double *dpp2, const double *rad,
                        const int64_t *radi, int32_t q, const uint64_t *cand_bits, int32_t words,
-                       const int32_t *witness_first, int64_t nfirst, uint64_t *bits, uint64_t *counters) {
+                       const int32_t *witness_first, int64_t nfirst, uint64_t *bits, uint64_t *counters,
+                       const uint8_t *isnew) {
     if (m == 0) return;
     const double s2 = ldexp(1.0, 2 * q);
     const int64_t waves = m * words;
     k_grng_layer<<<(unsigned)div_up(waves, 4), 256, 0, s>>>(m, dpp, dpp2, rad, radi, s2, cand_bits, words,
-                                                            witness_first, nfirst, bits,
+                                                            witness_first, nfirst, isnew, bits,
                                                             (unsigned long long *)counters);
     GRNG_LAUNCHED();
     const int64_t e = m * words;
     k_symmetrize<<<(unsigned)div_up(e, 256), 256, 0, s>>>(m, words, bits);
+    GRNG_LAUNCHED();
+}
+
+void launch_insert_candidates(hipStream_t s, int64_t m1, int32_t words1, const int32_t *oldpos,
+                              const uint64_t *old_bits, int32_t words0, uint64_t *cand) {
+    if (m1 == 0) return;
+    k_insert_candidates<<<(unsigned)div_up(m1 * words1, 256), 256, 0, s>>>(m1, words1, oldpos, old_bits, words0,
+                                                                          cand);
     GRNG_LAUNCHED();
 }
 
