@@ -190,6 +190,17 @@ def roofline(st: dict, d: int, precision: int, workload: str) -> dict:
     return r
 
 
+def kernels_with_traffic(ks: dict, workload: str) -> dict:
+    """Each kernel's entry with its measured HBM bytes per build and the
+    rate they imply (null while the committed counters do not match the
+    kernel's sources or this workload)."""
+    for k, r in ks.items():
+        t = measured_traffic(k, workload)
+        r["traffic"] = t
+        r["hbm_gb_s"] = t / (r["ms"] / 1e3) / 1e9 if t is not None and r["ms"] > 0 else None
+    return ks
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -505,7 +516,7 @@ def main():
         "ms_lune": st["ms_lune"],
         "queries": queries,
         "roofline": roofline(st, W.d, prec, workload),
-        "kernels": kernel_rooflines(st, W.d, prec),
+        "kernels": kernels_with_traffic(kernel_rooflines(st, W.d, prec), workload),
         "wall_s": wall,
     }
     if not args.no_cpu_baseline:
@@ -539,6 +550,9 @@ def bench_insert(args):
         e1.synchronize()
         ins_ms.append(e0.elapsed_time(e1))
         allX.append(B)
+        if args.no_forms:   # insertions only (e.g. under a profiler)
+            progress("batch", n=len(allX) - 1, insert_ms=ins_ms[-1])
+            continue
         Wb = synth.Workload(name="all", X=np.vstack(allX), q=W.q, layers=W.layers)
         r = Builder(P, Wb, precision=1, autotune=0, vgrng_pivots=int(tune["vgrng_pivots"]),
                     stage4_pivots=int(tune["stage4_pivots"]))
@@ -557,9 +571,10 @@ def bench_insert(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "64 insertion batches (sizes log-uniform in [1000, 50000]) into the " + desc,
                    "n_final": int(n_final), "precision": PRECISION_NAMES[1]},
-        "forms": {"batched_insert_total_ms": total, "rebuild_total_ms": sum(reb_ms),
-                  "speedup_vs_rebuild": sum(reb_ms) / total, "identical_edges_after_every_batch": bool(same),
-                  "insert_ms": ins_ms, "rebuild_ms": reb_ms},
+        "forms": None if args.no_forms else {
+            "batched_insert_total_ms": total, "rebuild_total_ms": sum(reb_ms),
+            "speedup_vs_rebuild": sum(reb_ms) / total, "identical_edges_after_every_batch": bool(same),
+            "insert_ms": ins_ms, "rebuild_ms": reb_ms},
     }
     print(json.dumps(line), flush=True)
 
