@@ -68,11 +68,14 @@ constexpr float kU6 = 6.0f * 0x1p-24f;    // six float32 roundings per entry
 __host__ __device__ inline int bstride(int kp) { return kp + 8; }
 
 // LDS layout (bytes): T rows (hi, lo, lo2), U rows (hi, lo), masks, per-row
-// terms, D(T,U); then a phase region: the pivot rows (twice centred) and
-// pivot distances for Stages I-IV, later D(U,U) and D(T,T) for Stage V.
+// terms, D(T,U) (float32), D(T,T) (16-bit upper bounds, kept while
+// consecutive tile pairs share T); then a phase region: the pivot rows
+// (twice centred) and pivot distances for Stages I-IV, later D(U,U) (16-bit
+// upper bounds) for Stage V.  A Stage V witness entry only needs to bound
+// the estimate from above: the kill test stays a proof.
 struct BLayout {
     int kp, ks;
-    size_t rows, fixed, dmat, phase_a, region, total;
+    size_t rows, fixed, dmat, dtt, phase_a, region, total;
 };
 
 constexpr int kTerms = 4 * kTile + 2 * kPiv + 16;   // floats of per-row terms and tile radii
@@ -84,10 +87,11 @@ __host__ __device__ inline BLayout blayout(int kp) {
     L.rows = 5 * (size_t)kTile * L.ks * 2;                          // hT, lT, l2T, hU, lU
     L.fixed = L.rows + 8 * 3 * (size_t)kTile + 4 * (size_t)kTerms;  // masks, terms
     L.dmat = 4 * (size_t)kTile * kDl;
+    L.dtt = 2 * (size_t)kTile * kDl;
     L.phase_a = 4 * (size_t)kPiv * L.ks * 2 + 4 * 2 * (size_t)kTile * kXs;   // pivot rows x2, XP, YP
-    const size_t b = 2 * L.dmat;
+    const size_t b = 2 * (size_t)kTile * kDl;                                 // D(U,U), 16-bit
     L.region = L.phase_a > b ? L.phase_a : b;
-    L.total = L.fixed + L.dmat + L.region;
+    L.total = L.fixed + L.dmat + L.dtt + L.region;
     return L;
 }
 
@@ -188,12 +192,20 @@ __device__ inline void cross_terms(const __bf16 *hi, const __bf16 *lo, const __b
     }
 }
 
+// Entries of the distance blocks: float32, or the upper 16 bits of the
+// float32 value rounded up (an upper bound with 8 significant bits; the
+// values are non-negative or +inf, so the bit patterns order like the values).
+__device__ inline void put_d(float *p, float v) { *p = v; }
+__device__ inline void put_d(uint16_t *p, float v) { *p = (uint16_t)((__float_as_uint(v) + 0xffffu) >> 16); }
+__device__ inline float get_d16(const uint16_t *p) { return __uint_as_float((uint32_t)*p << 16); }
+
 // One wave: a 16 x 16 block of estimated squared distances,
 //     D[i][j] = max(0, ta[i] + (tb[j] - off) - 2 (hi.hi + hi.lo + lo.hi)),
 // rows r0.. of A against rows c0.. of B.
+template <typename DT>
 __device__ inline void bf16_block(const __bf16 *ah, const __bf16 *al, const float *ta, const __bf16 *bh,
                                   const __bf16 *bl, const float *tb, float off, int r0, int c0, int kp, int ks,
-                                  float *D, int dld) {
+                                  DT *D, int dld) {
     const int lane = threadIdx.x & 63, il = lane & 15, kl = lane >> 4;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int kk = 0; kk < kp; kk += kKb) {
@@ -211,7 +223,7 @@ __device__ inline void bf16_block(const __bf16 *ah, const __bf16 *al, const floa
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = r0 + 4 * kl + r;
-        D[i * dld + j] = fmaxf(0.f, fmaf(-2.f, acc[r], ta[i] + tbj));
+        put_d(&D[i * dld + j], fmaxf(0.f, fmaf(-2.f, acc[r], ta[i] + tbj)));
     }
 }
 
@@ -239,10 +251,11 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     // [5] max |y - p_a|^2, [6] |p_a - p_b|^2
     unsigned int *rad = (unsigned int *)(nPb + kPiv);
     float *DTU = (float *)(smem + LY.fixed);
-    unsigned char *region = smem + LY.fixed + LY.dmat;
+    uint16_t *DTT = (uint16_t *)(smem + LY.fixed + LY.dmat);
+    unsigned char *region = smem + LY.fixed + LY.dmat + LY.dtt;
     __bf16 *hPa = (__bf16 *)region, *lPa = hPa + kPiv * ks, *hPb = lPa + kPiv * ks, *lPb = hPb + kPiv * ks;
     float *XP = (float *)(lPb + kPiv * ks), *YP = XP + kTile * kXs;
-    float *DUU = (float *)region, *DTT = DUU + kTile * kDl;
+    uint16_t *DUU = (uint16_t *)region;
     __shared__ int64_t s_tp, s_nx;
     // record words before the masks (tiles' start, length and cell, pivot
     // ids): the current tile pair's, and the next one's, fetched one tile
@@ -250,9 +263,10 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     __shared__ uint64_t s_cm[kPairRecMeta], s_nm[kPairRecMeta];
     __shared__ int s_any, s_newT, s_newB;
     __shared__ int32_t s_sx, s_b;   // T tile whose rows are in LDS; the cell its cross terms are for
+    __shared__ int32_t s_dtt;       // T tile whose D(T,T) is in LDS
     __shared__ float s_tau4, s_tau5;
     const bool self = (mode & PM_SELF) != 0;
-    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nunc = 0;
+    uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nttv = 0, nunc = 0;
     uint64_t dtu = 0, dpv = 0, dv = 0;   // tile entries computed (thread 0)
     WaveOut wo;
     const int xcd0 = blockIdx.x % kXcds;
@@ -269,6 +283,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     if (threadIdx.x == 0) {
         s_sx = -1;
         s_b = -1;
+        s_dtt = -1;
     }
     for (;;) {
         if (threadIdx.x == 0) {
@@ -493,23 +508,27 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         }
         if (!s_any) continue;   // uniform
         ntpv += tid == 0;
-        // 2c. D(U,U) and, when T's points may witness, D(T,T), over the pivot
-        // region (two blocks of each per wave).
-        if (tid == 0) dv += (uint64_t)lUn * lUn + (self ? (uint64_t)lTn * lTn : 0);
+        // 2c. D(U,U) over the pivot region and, when T's points may witness
+        // and T changed since D(T,T) was last formed, D(T,T) (two blocks of
+        // each per wave).
+        const bool newTT = self && s_dtt != sT;
+        if (tid == 0) dv += (uint64_t)lUn * lUn + (newTT ? (uint64_t)lTn * lTn : 0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int id = 2 * w + q;
             bf16_block(hU, lU, nU, hU, lU, nU, 0.f, (id >> 2) * 16, (id & 3) * 16, kp, ks, DUU, kDl);
-            if (self) bf16_block(hT, lT, nT, hT, lT, nT, 0.f, (id >> 2) * 16, (id & 3) * 16, kp, ks, DTT, kDl);
+            if (newTT) bf16_block(hT, lT, nT, hT, lT, nT, 0.f, (id >> 2) * 16, (id & 3) * 16, kp, ks, DTT, kDl);
         }
+        nttv += tid == 0 && newTT;
         __syncthreads();
+        if (tid == 0 && newTT) s_dtt = sT;
         // 3. Stage V: each wave walks rows w, w + 8, ...; every Stage IV
         // survivor (i, j) against the 128 points of T and U, one lane per
         // witness z (T[lane] and U[lane]).
         for (int i = w; i < lTn; i += kBWaves) {
             uint64_t row = surv[i];
             if (!row) continue;
-            const float ax = (self && lane < lTn) ? DTT[i * kDl + lane] : INFINITY;
+            const float ax = (self && lane < lTn) ? get_d16(&DTT[i * kDl + lane]) : INFINITY;
             const float au = lane < lUn ? DTU[i * kDl + lane] : INFINITY;
             while (row) {
                 const int j = __ffsll((long long)row) - 1;
@@ -517,7 +536,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 const float dxy = DTU[i * kDl + j];
                 const float t = sub_dn(dxy, tau5), tu = add_up(dxy, tau5);
                 const float by = (self && lane < lTn) ? DTU[lane * kDl + j] : INFINITY;
-                const float bu = lane < lUn ? DUU[j * kDl + lane] : INFINITY;
+                const float bu = lane < lUn ? get_d16(&DUU[j * kDl + lane]) : INFINITY;
                 if (__ballot((ax < t && by < t) || (au < t && bu < t))) continue;   // a certain witness
                 // a survivor; uncertain when some witness other than x and y lies
                 // within the bound
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         atomicAdd(&counters[C_SURV], (unsigned long long)nsurv);
         if (nunc) atomicAdd(&counters[C_UNCERTAIN], (unsigned long long)nunc);
         if (ntpv) atomicAdd(&counters[C_TPV], (unsigned long long)ntpv);
-        if (ntpv && self) atomicAdd(&counters[C_TTV], (unsigned long long)ntpv);
+        if (nttv) atomicAdd(&counters[C_TTV], (unsigned long long)nttv);
         if (w == 0) {
             atomicAdd(&counters[C_DIST], (unsigned long long)(dtu + dpv + dv));
             atomicAdd(&counters[C_PD_TU], (unsigned long long)dtu);
