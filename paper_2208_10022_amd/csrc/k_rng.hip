@@ -925,16 +925,23 @@ __device__ inline int wave_incl_scan(int v) {
     return v;
 }
 
+// The first 8 coordinates of each float32 row, packed (dp > 8).
+__global__ void k_row_prefix(const float *__restrict__ X, int64_t n, int dp, float *__restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * 8) return;
+    out[e] = X[(e >> 3) * dp + (e & 7)];
+}
+
 template <bool F32>
 __global__ __launch_bounds__(256) void k_lune_guided(
     int64_t npairs, const int32_t *__restrict__ px, const int32_t *__restrict__ py, const double *__restrict__ pd2,
     int dp, const double *__restrict__ Xx, const double *__restrict__ nrmx, const double *__restrict__ Xh,
     const double *__restrict__ nrmh, const double *__restrict__ dhome, const float *__restrict__ Xxf,
-    const float *__restrict__ Xhf, const float *__restrict__ dhomef, const int32_t *__restrict__ zstart,
-    const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ Xp,
-    const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off, const int32_t *__restrict__ rel_grp,
-    const double *__restrict__ rel_d2x, const double *__restrict__ rad, const uint16_t *__restrict__ scorer,
-    bool lune_order,
+    const float *__restrict__ Xhf, const float *__restrict__ Xpre, int pst, const float *__restrict__ dhomef,
+    const int32_t *__restrict__ zstart, const int32_t *__restrict__ grp_off, const double *__restrict__ dvor,
+    const double *__restrict__ Xp, const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off,
+    const int32_t *__restrict__ rel_grp, const double *__restrict__ rel_d2x, const double *__restrict__ rad,
+    const uint16_t *__restrict__ scorer, bool lune_order,
     uint8_t *__restrict__ alive, unsigned long long *work, unsigned long long *counters) {
     // Per-wave cell table in visit order: first member, exclusive member
     // prefix (entry 64 = total) and max(d(x,p), d(y,p)) lower bound.
@@ -1127,7 +1134,8 @@ __global__ __launch_bounds__(256) void k_lune_guided(
                     for (int u = 0; u < 4; ++u) {
                         r0[u] = r1[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                         if (ok[u]) {
-                            const float *zr = Xhf + (int64_t)zz[u] * dp;
+                            // the first 8 coordinates from the packed prefix rows
+                            const float *zr = Xpre + (int64_t)zz[u] * pst;
                             r0[u] = *reinterpret_cast<const float4 *>(zr);
                             if (dp > 4) r1[u] = *reinterpret_cast<const float4 *>(zr + 4);
                         }
@@ -1449,15 +1457,29 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     const bool f32 = Xxf && Xhf && dhomef;
     const bool cached = f32 && nh * (int64_t)dp * 4 <= (int64_t)256 << 20;
     const int64_t grid = std::max<int64_t>(kXcds, std::min<int64_t>(div_up(npairs, 4), 256 * (cached ? 4 : 3)));
+    // Most float32 witness tests end after the first 8 coordinates (their
+    // partial sums already exceed the pair's distance); a packed copy of
+    // those 8 coordinates per row lets a scan step read them from a quarter
+    // of the cache lines (rows of more than 8 coordinates).
+    DevBuf pre;
+    const float *Xpre = Xhf;
+    int pst = dp;
+    if (f32 && dp > 8) {
+        pre.alloc(sizeof(float) * 8 * (size_t)std::max<int64_t>(nh, 1));
+        k_row_prefix<<<(unsigned)div_up(nh * 8, 256), 256, 0, s>>>(Xhf, nh, dp, pre.as<float>());
+        GRNG_LAUNCHED();
+        Xpre = pre.as<float>();
+        pst = 8;
+    }
     if (f32)
         k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
-            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
-            rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, Xpre, pst, dhomef, zstart, grp_off, dvor,
+            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
             (unsigned long long *)counters);
     else
         k_lune_guided<false><<<(unsigned)grid, 256, 0, s>>>(
-            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, dhomef, zstart, grp_off, dvor, Xp, nrmp,
-            rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, Xpre, pst, dhomef, zstart, grp_off, dvor,
+            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
             (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
