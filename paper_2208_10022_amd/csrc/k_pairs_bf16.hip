@@ -256,12 +256,15 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     __bf16 *hPa = (__bf16 *)region, *lPa = hPa + kPiv * ks, *hPb = lPa + kPiv * ks, *lPb = hPb + kPiv * ks;
     float *XP = (float *)(lPb + kPiv * ks), *YP = XP + kTile * kXs;
     uint16_t *DUU = (uint16_t *)region;
-    __shared__ int64_t s_tp, s_nx;
+    // Claims alternate between two sets of slots (iteration parity): thread
+    // 0 claims the next tile pair during Stage IV of the current one, so no
+    // barrier is needed between two tile pairs' work.
+    __shared__ int64_t s_tp[2], s_nx;
     // record words before the masks (tiles' start, length and cell, pivot
     // ids): the current tile pair's, and the next one's, fetched one tile
     // pair ahead so that no wave waits on the record before loading rows
-    __shared__ uint64_t s_cm[kPairRecMeta], s_nm[kPairRecMeta];
-    __shared__ int s_any, s_newT, s_newB;
+    __shared__ uint64_t s_cm[2][kPairRecMeta], s_nm[kPairRecMeta];
+    __shared__ int s_any[2], s_newT[2], s_newB[2];
     __shared__ int32_t s_sx, s_b;   // T tile whose rows are in LDS; the cell its cross terms are for
     __shared__ int32_t s_dtt;       // T tile whose D(T,T) is in LDS
     __shared__ float s_tau4, s_tau5;
@@ -280,50 +283,51 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         return cur++;
     };
     uint64_t nmeta = 0;   // lanes 0-11 of wave 0: a word of the next tile pair's record
+    // Thread 0: the tile pair of parity q is the one claimed ahead (nxt),
+    // whose record words are in s_nm; claim the one after it.
+    auto claim = [&](int q) {
+        s_tp[q] = nxt;
+        if (nxt >= 0)
+            for (int k = 0; k < kPairRecMeta; ++k) s_cm[q][k] = s_nm[k];
+        nxt = nxt >= 0 ? next_tp() : -1;
+        s_nx = nxt;
+        s_any[q] = 0;
+        // T's rows stay in LDS while consecutive tile pairs share T, and
+        // its cross terms while they also share U's cell
+        int32_t st = -1, sb = -1;
+        if (s_tp[q] >= 0) {
+            st = (int32_t)s_cm[q][0];
+            sb = (int32_t)(s_cm[q][2] >> 32);
+        }
+        s_newT[q] = st != s_sx;
+        s_newB[q] = s_newT[q] || sb != s_b;
+        s_sx = st;
+        s_b = sb;
+        if (s_newT[q]) rad[0] = 0u;
+        if (s_newB[q]) rad[4] = 0u;
+        rad[1] = rad[2] = rad[3] = rad[5] = 0u;
+    };
     if (threadIdx.x == 0) {
         s_sx = -1;
         s_b = -1;
         s_dtt = -1;
+        nxt = next_tp();
+        if (nxt >= 0)
+            for (int k = 0; k < kPairRecMeta; ++k) s_nm[k] = rec[nxt * kPairRecWords + k];
+        claim(0);
     }
-    for (;;) {
-        if (threadIdx.x == 0) {
-            if (nxt == -2) {
-                nxt = next_tp();
-                if (nxt >= 0)
-                    for (int k = 0; k < kPairRecMeta; ++k) s_nm[k] = rec[nxt * kPairRecWords + k];
-            }
-            s_tp = nxt;
-            if (s_tp >= 0)
-                for (int k = 0; k < kPairRecMeta; ++k) s_cm[k] = s_nm[k];
-            nxt = s_tp >= 0 ? next_tp() : -1;
-            s_nx = nxt;
-            s_any = 0;
-            // T's rows stay in LDS while consecutive tile pairs share T, and
-            // its cross terms while they also share U's cell
-            int32_t st = -1, sb = -1;
-            if (s_tp >= 0) {
-                st = (int32_t)s_cm[0];
-                sb = (int32_t)(s_cm[2] >> 32);
-            }
-            s_newT = st != s_sx;
-            s_newB = s_newT || sb != s_b;
-            s_sx = st;
-            s_b = sb;
-            if (s_newT) rad[0] = 0u;
-            if (s_newB) rad[4] = 0u;
-            rad[1] = rad[2] = rad[3] = rad[5] = 0u;
-        }
-        __syncthreads();
-        const int64_t tp = uniform_i64(s_tp);
+    __syncthreads();
+    for (int par = 0;; par ^= 1) {
+        const int64_t tp = uniform_i64(s_tp[par]);
         if (tp < 0) break;
         // Per-thread LDS addresses are recomputed in every iteration rather
         // than held across it (held, they exceed the register budget).
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const int lane = tid & 63, w = tid >> 6;
-        const bool newT = s_newT != 0, newB = s_newB != 0;
+        const bool newT = s_newT[par] != 0, newB = s_newB[par] != 0;
         const uint64_t *rc = rec + tp * kPairRecWords;
-        const uint64_t m0 = s_cm[0], m1 = s_cm[1], m2 = s_cm[2];
+        const uint64_t m0 = s_cm[par][0], m1 = s_cm[par][1], m2 = s_cm[par][2];
         const int32_t sT = (int32_t)m0, lTn = (int32_t)(m0 >> 32);
         const int32_t a = (int32_t)m1, lUn = (int32_t)(m1 >> 32), sU = (int32_t)m2, b = (int32_t)(m2 >> 32);
         const float *pa = Xpf + (int64_t)a * dp, *pb = Xpf + (int64_t)b * dp;
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             // slots past K repeat a valid pivot (their distances become +inf)
             // (each row read once and split for both centres)
             const int t = lane >> 2, q4 = lane & 3;
-            const int32_t pv = (int32_t)(s_cm[3 + (t >> 1)] >> (32 * (t & 1)));
+            const int32_t pv = (int32_t)(s_cm[par][3 + (t >> 1)] >> (32 * (t & 1)));
             const float *src = Xpf + (int64_t)pv * dp;
             double acca = 0.0, accb = 0.0;
             for (int c0 = 8 * q4; c0 < kp; c0 += kKb) {
@@ -496,17 +500,20 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 if (bits) {
                     ns4 += __popcll(bits);
                     atomicOr((unsigned long long *)&surv[i], (unsigned long long)bits);
-                    s_any = 1;
+                    s_any[par] = 1;
                 }
             }
         }
+        // The next tile pair's record words, then its claim (thread 0, same
+        // wave, in program order), before the barrier that ends Stage IV.
+        if (tid < kPairRecMeta) s_nm[tid] = nmeta;
+        if (tid == 0) claim(par ^ 1);
         __syncthreads();
-        if (tid < kPairRecMeta) s_nm[tid] = nmeta;   // read by thread 0 (same wave) at the next claim
         if (tid == 0) {
             dtu += (uint64_t)lTn * (uint64_t)lUn;
             dpv += (uint64_t)(lTn + lUn) * (uint64_t)K;
         }
-        if (!s_any) continue;   // uniform
+        if (!s_any[par]) continue;   // uniform
         ntpv += tid == 0;
         // 2c. D(U,U) over the pivot region and, when T's points may witness
         // and T changed since D(T,T) was last formed, D(T,T) (two blocks of
