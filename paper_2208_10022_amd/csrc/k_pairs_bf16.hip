@@ -67,12 +67,14 @@ constexpr float kU6 = 6.0f * 0x1p-24f;    // six float32 roundings per entry
 // rows one MFMA operand load touches start in different LDS banks.
 __host__ __device__ inline int bstride(int kp) { return kp + 8; }
 
-// LDS layout (bytes): T rows (hi, lo, lo2), U rows (hi, lo), masks, per-row
-// terms, D(T,U) (float32), D(T,T) (16-bit upper bounds, kept while
-// consecutive tile pairs share T); then a phase region: the pivot rows
-// (twice centred) and pivot distances for Stages I-IV, later D(U,U) (16-bit
-// upper bounds) for Stage V.  A Stage V witness entry only needs to bound
-// the estimate from above: the kill test stays a proof.
+// LDS layout (bytes): T rows (hi, lo, lo2), U rows (hi, lo), masks, Stage
+// IV survivor bits (two sets, by iteration parity), per-row terms, D(T,U)
+// (float32), D(T,T) (16-bit upper bounds, kept while consecutive tile pairs
+// share T), D(U,U) (16-bit upper bounds), then the pivot rows (twice
+// centred) and pivot distances of Stages I-IV.  A Stage V witness entry
+// only needs to bound the estimate from above: the kill test stays a proof.
+// Nothing Stage V reads is written before the next tile pair's second
+// barrier, so no barrier ends Stage V.
 struct BLayout {
     int kp, ks;
     size_t rows, fixed, dmat, dtt, phase_a, region, total;
@@ -85,13 +87,12 @@ __host__ __device__ inline BLayout blayout(int kp) {
     L.kp = kp;
     L.ks = bstride(kp);
     L.rows = 5 * (size_t)kTile * L.ks * 2;                          // hT, lT, l2T, hU, lU
-    L.fixed = L.rows + 8 * 3 * (size_t)kTile + 4 * (size_t)kTerms;  // masks, terms
+    L.fixed = L.rows + 8 * 4 * (size_t)kTile + 4 * (size_t)kTerms;  // masks, survivor bits, terms
     L.dmat = 4 * (size_t)kTile * kDl;
     L.dtt = 2 * (size_t)kTile * kDl;
     L.phase_a = 4 * (size_t)kPiv * L.ks * 2 + 4 * 2 * (size_t)kTile * kXs;   // pivot rows x2, XP, YP
-    const size_t b = 2 * (size_t)kTile * kDl;                                 // D(U,U), 16-bit
-    L.region = L.phase_a > b ? L.phase_a : b;
-    L.total = L.fixed + L.dmat + L.dtt + L.region;
+    L.region = L.phase_a;
+    L.total = L.fixed + L.dmat + 2 * L.dtt + L.region;   // D(T,T) and D(U,U) take dtt bytes each
     return L;
 }
 
@@ -242,20 +243,20 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     const int ks = LY.ks;
     __bf16 *hT = (__bf16 *)smem, *lT = hT + kTile * ks, *l2T = lT + kTile * ks;
     __bf16 *hU = l2T + kTile * ks, *lU = hU + kTile * ks;
-    uint64_t *mX = (uint64_t *)(smem + LY.rows), *mY = mX + kTile, *surv = mY + kTile;
+    uint64_t *mX = (uint64_t *)(smem + LY.rows), *mY = mX + kTile, *survb = mY + kTile;   // survb: 2 x 64
     // per-row terms: |x - p_a|^2, |x - p_b|^2 (T); |y - p_b|^2, |y - p_a|^2 (U);
     // |p - p_a|^2, |p - p_b|^2 (pivots); then the tile radii and maxima
-    float *nT = (float *)(surv + kTile), *fT = nT + kTile, *nU = fT + kTile, *fU = nU + kTile;
+    float *nT = (float *)(survb + 2 * kTile), *fT = nT + kTile, *nU = fT + kTile, *fU = nU + kTile;
     float *nPa = fU + kTile, *nPb = nPa + kPiv;
     // rad (float bits): [0] R_T, [1] R_U, [2] R_Pa, [3] R_Pb, [4] max |x - p_b|^2,
     // [5] max |y - p_a|^2, [6] |p_a - p_b|^2
     unsigned int *rad = (unsigned int *)(nPb + kPiv);
     float *DTU = (float *)(smem + LY.fixed);
     uint16_t *DTT = (uint16_t *)(smem + LY.fixed + LY.dmat);
-    unsigned char *region = smem + LY.fixed + LY.dmat + LY.dtt;
+    uint16_t *DUU = (uint16_t *)(smem + LY.fixed + LY.dmat + LY.dtt);
+    unsigned char *region = smem + LY.fixed + LY.dmat + 2 * LY.dtt;
     __bf16 *hPa = (__bf16 *)region, *lPa = hPa + kPiv * ks, *hPb = lPa + kPiv * ks, *lPb = hPb + kPiv * ks;
     float *XP = (float *)(lPb + kPiv * ks), *YP = XP + kTile * kXs;
-    uint16_t *DUU = (uint16_t *)region;
     // Claims alternate between two sets of slots (iteration parity): thread
     // 0 claims the next tile pair during Stage IV of the current one, so no
     // barrier is needed between two tile pairs' work.
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         // 1. masks; centred split rows of T (when new), of U and of the pivots.
         if (w == 6) {
             mX[lane] = rc[kPairRecMeta + lane];
-            surv[lane] = 0;
+            survb[par * kTile + lane] = 0;
         } else if (w == 7) {
             mY[lane] = rc[kPairRecMeta + kTile + lane];
         } else if (w == 5) {
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 }
                 if (bits) {
                     ns4 += __popcll(bits);
-                    atomicOr((unsigned long long *)&surv[i], (unsigned long long)bits);
+                    atomicOr((unsigned long long *)&survb[par * kTile + i], (unsigned long long)bits);
                     s_any[par] = 1;
                 }
             }
@@ -515,9 +516,8 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         }
         if (!s_any[par]) continue;   // uniform
         ntpv += tid == 0;
-        // 2c. D(U,U) over the pivot region and, when T's points may witness
-        // and T changed since D(T,T) was last formed, D(T,T) (two blocks of
-        // each per wave).
+        // 2c. D(U,U) and, when T's points may witness and T changed since
+        // D(T,T) was last formed, D(T,T) (two blocks of each per wave).
         const bool newTT = self && s_dtt != sT;
         if (tid == 0) dv += (uint64_t)lUn * lUn + (newTT ? (uint64_t)lTn * lTn : 0);
 #pragma unroll
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         // survivor (i, j) against the 128 points of T and U, one lane per
         // witness z (T[lane] and U[lane]).
         for (int i = w; i < lTn; i += kBWaves) {
-            uint64_t row = surv[i];
+            uint64_t row = survb[par * kTile + i];
             if (!row) continue;
             const float ax = (self && lane < lTn) ? get_d16(&DTT[i * kDl + lane]) : INFINITY;
             const float au = lane < lUn ? DTU[i * kDl + lane] : INFINITY;
@@ -560,7 +560,6 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
                 if (++wo.cnt == 64) wo.flush(out);
             }
         }
-        __syncthreads();
     }
     wo.flush(out);
     ncand = wave_sum(ncand);
