@@ -408,12 +408,17 @@ __global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             else
                 load_split(hU, lU, nullptr, nU, fU, &rad[1], &rad[5], XBf + (int64_t)sU * dp, lUn, kTile, dp, kp, ks,
                            pb, pa, tid - 256, 256);
-        } else {
+        } else if (tid < 256) {
             load_split(hU, lU, nullptr, nU, fU, &rad[1], &rad[5], XBf + (int64_t)sU * dp, lUn, kTile, dp, kp, ks, pb,
-                       pa, tid, kBThreads);
+                       pa, tid, 256);
+        } else if (newB && w != 5) {
+            // T's rows are in LDS already: its cross terms for U's new cell,
+            // by waves 4, 6 and 7 (the last two after their mask loads)
+            const int t = w == 4 ? lane : (w == 6 ? 64 + lane : 128 + lane);
+            cross_terms(hT, lT, l2T, pa, pb, lTn, dp, ks, fT, &rad[4], t, 192);
         }
         __syncthreads();
-        if (newB) {
+        if (newB && newT) {   // T's rows arrived in this phase
             cross_terms(hT, lT, l2T, pa, pb, lTn, dp, ks, fT, &rad[4], tid, kBThreads);
             __syncthreads();
         }
