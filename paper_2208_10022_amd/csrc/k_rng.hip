@@ -316,24 +316,47 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
     uint32_t ncand = 0, ns4 = 0, nsurv = 0, ntpv = 0, nttv = 0;
     uint64_t ndist = 0, dtu = 0, dpv = 0, dv = 0;   // tile entries computed (thread 0)
     WaveOut wo;
-    __shared__ int64_t s_tp;
-    __shared__ int s_any;
+    // Claims alternate between two sets of slots (iteration parity): thread
+    // 0 claims the next tile pair during Stage IV of the current one, so the
+    // loop needs no barrier of its own.  The record words before the masks
+    // (tiles' start, length and cell, pivot ids) are fetched one tile pair
+    // ahead, so that no wave waits on the record before loading rows.
+    __shared__ int64_t s_tp[2], s_nx;
+    __shared__ uint64_t s_cm[2][kPairRecMeta], s_nm[kPairRecMeta];
+    __shared__ int s_any[2];
     const int xcd0 = blockIdx.x % kXcds;
     int xr = 0;
-    int64_t cur = 0, cend = 0;   // tid 0's claimed chunk
-    for (;;) {
-        if (tid == 0) {
-            if (cur >= cend && !claim_chunk(ntp, kPairChunk, xcd0, xr, work, &cur, &cend)) cur = cend = -1;
-            s_tp = cur < cend ? cur++ : -1;
-            s_any = 0;
+    int64_t cur = 0, cend = 0, nxt = -2;   // thread 0: the claimed chunk; the tile pair after the current one
+    auto next_tp = [&]() -> int64_t {
+        if (cur >= cend && !claim_chunk(ntp, kPairChunk, xcd0, xr, work, &cur, &cend)) {
+            cur = cend = -1;
+            return -1;
         }
-        __syncthreads();
-        const int64_t tp = uniform_i64(s_tp);
-        __syncthreads();
+        return cur++;
+    };
+    uint64_t nmeta = 0;   // lanes 0-11 of wave 0: a word of the next tile pair's record
+    // Thread 0: the tile pair of parity q is the one claimed ahead (nxt),
+    // whose record words are in s_nm; claim the one after it.
+    auto claim = [&](int q) {
+        s_tp[q] = nxt;
+        if (nxt >= 0)
+            for (int k = 0; k < kPairRecMeta; ++k) s_cm[q][k] = s_nm[k];
+        nxt = nxt >= 0 ? next_tp() : -1;
+        s_nx = nxt;
+        s_any[q] = 0;
+    };
+    if (tid == 0) {
+        nxt = next_tp();
+        if (nxt >= 0)
+            for (int k = 0; k < kPairRecMeta; ++k) s_nm[k] = rec[nxt * kPairRecWords + k];
+        claim(0);
+    }
+    __syncthreads();
+    for (int par = 0;; par ^= 1) {
+        const int64_t tp = uniform_i64(s_tp[par]);
         if (tp < 0) break;
-        // wave-uniform from here on: the record head is read by scalar loads
         const uint64_t *rc = rec + tp * kPairRecWords;
-        const uint64_t m0 = rc[0], m1 = rc[1], m2 = rc[2];
+        const uint64_t m0 = s_cm[par][0], m1 = s_cm[par][1], m2 = s_cm[par][2];
         // (the two home cells, in the low half of m1 and the high half of m2,
         // are not needed here)
         const int32_t sT = (int32_t)m0, lT = (int32_t)(m0 >> 32);
@@ -349,7 +372,7 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             mY[lane] = rc[kPairRecMeta + kTile + lane];
         } else if (w == 5) {
             const int t = lane >> 2;
-            const int32_t pv = (int32_t)(rc[3 + (t >> 1)] >> (32 * (t & 1)));
+            const int32_t pv = (int32_t)(s_cm[par][3 + (t >> 1)] >> (32 * (t & 1)));
             for (int c = 2 * (lane & 3); c < dp; c += 8) {
                 const double2 v = *reinterpret_cast<const double2 *>(Xp + (int64_t)pv * dp + c);
                 sP[t * ld + c] = v.x;
@@ -365,6 +388,11 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
             load_rows(sY, XB + (int64_t)sU * dp, lU, kTile, dp, ld, tid - 256, 256);
         }
         __syncthreads();
+        // The next tile pair's record words, in flight until Stage IV ends.
+        if (tid < kPairRecMeta) {
+            const int64_t nx = s_nx;
+            if (nx >= 0) nmeta = rec[nx * kPairRecWords + tid];
+        }
         // 2a. Per wave: one 16-row block of d^2 to the pivot witnesses (rows
         // of T for waves 0-3, of U for 4-7; +inf past K) and two 16x16 blocks
         // of D(T,U); three interleaved MFMA f64 chains, float32 results.
@@ -432,16 +460,20 @@ __global__ __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(4)
                 if (bits) {
                     ns4 += __popcll(bits);
                     atomicOr((unsigned long long *)&surv[i], (unsigned long long)bits);
-                    s_any = 1;
+                    s_any[par] = 1;
                 }
             }
         }
+        // The next tile pair's record words, then its claim (thread 0, same
+        // wave, in program order), before the barrier that ends Stage IV.
+        if (tid < kPairRecMeta) s_nm[tid] = nmeta;
+        if (tid == 0) claim(par ^ 1);
         __syncthreads();
         if (tid == 0) {
             dtu += (uint64_t)lT * (uint64_t)lU;
             dpv += (uint64_t)(lT + lU) * (uint64_t)K;
         }
-        if (!s_any) continue;   // uniform: no Stage IV survivor in this tile pair
+        if (!s_any[par]) continue;   // uniform: no Stage IV survivor in this tile pair
         ntpv += tid == 0;
         // 2c. D(U,U), written over the pivot data, which is dead now, and
         // D(T,T) when T's points may witness and it is not in LDS already:
