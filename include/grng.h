@@ -102,7 +102,7 @@ typedef struct grng_options {
                               depend on it. */
     int32_t metric;        /* GRNG_METRIC_*: the distance of the RNG (0 = Euclidean) */
     int32_t graph;         /* GRNG_GRAPH_*: the empty-region graph to build (0 = RNG) */
-    int32_t reserved_i[1]; /* must be 0 */
+    int32_t beta_quarters; /* GRNG_GRAPH_BETA: beta = beta_quarters / 4, in [4, 64] (beta 1 to 16); 0 otherwise */
     uint64_t reserved[3];  /* must be 0 */
 } grng_options;
 
@@ -121,7 +121,13 @@ enum {
 };
 enum {
     GRNG_GRAPH_RNG = 0,     /* u, v linked iff no z has max(d(u,z), d(v,z)) < d(u,v) */
-    GRNG_GRAPH_GABRIEL = 1  /* Euclidean only: u, v linked iff no z has d(u,z)^2 + d(v,z)^2 < d(u,v)^2 */
+    GRNG_GRAPH_GABRIEL = 1, /* Euclidean only: u, v linked iff no z has d(u,z)^2 + d(v,z)^2 < d(u,v)^2 */
+    GRNG_GRAPH_BETA = 2     /* Euclidean only, the lune-based beta-skeleton (the beta-skeleton graph Section 1
+                               names, in the lune-based form of its cited work), beta = beta_quarters / 4 >= 1:
+                               u, v linked iff no z lies in both open balls of radius beta d(u,v) / 2 centred at
+                               (1 - beta/2) u + (beta/2) v and (beta/2) u + (1 - beta/2) v.  beta 1 gives the
+                               Gabriel graph, 2 the RNG; larger beta, fewer edges.  Exact: integer sums of
+                               squares in 128 bits. */
 };
 
 typedef struct grng_stats {

@@ -11,12 +11,23 @@ the same decision since squaring is monotone on non-negative numbers.  Ties
 Gabriel graph (Section 1): u and v are linked iff for every other z,
 d^2(z,u) + d^2(z,v) >= d^2(u,v).
 
+Lune-based beta-skeleton (named in Section 1 among the proximity graphs; the
+paper gives no formula, so this is the standard lune-based form of the work it
+cites, for beta >= 1): u and v are linked iff no other z lies in both open
+balls of radius beta d(u,v)/2 centred at (1 - beta/2) u + (beta/2) v and
+(beta/2) u + (1 - beta/2) v.  beta = 1 gives the Gabriel graph, beta = 2 the
+RNG.  With beta = a/4 both balls' tests become integer comparisons after
+multiplying by 16: |8(z - u) + a(u - v)|^2 < a^2 d^2(u,v) and
+|8(z - v) + a(v - u)|^2 < a^2 d^2(u,v).
+
 Other metrics (the paper's setting is a general metric space, Section 1):
 ``rng_edges_metric`` applies the same RNG definition with the L1 (sum of
 absolute differences) or L-infinity (largest absolute difference) distance,
 again on exact integers.
 """
 from __future__ import annotations
+
+from fractions import Fraction
 
 import numpy as np
 
@@ -146,3 +157,69 @@ def rng_edges_metric_loops(K, metric: str) -> list:
 
     return [(u, v) for u in range(n) for v in range(u + 1, n)
             if all(max(dist(z, u), dist(z, v)) >= dist(u, v) for z in range(n) if z != u and z != v)]
+
+
+def _beta_checked(K: np.ndarray, beta_quarters: int):
+    a = int(beta_quarters)
+    if a < 4:
+        raise ValueError("the lune-based beta-skeleton needs beta >= 1")
+    K = np.asarray(K, dtype=np.int64)
+    n, d = K.shape
+    span = int((K.max(axis=0) - K.min(axis=0)).max()) if n else 0
+    if d * ((8 + a) * span) ** 2 >= 2 ** 62 or a * a * d * span * span >= 2 ** 62:
+        raise ValueError("coordinates too large for the int64 beta-skeleton oracle")
+    return K, a
+
+
+def _beta_alive(K: np.ndarray, u: int, v: np.ndarray, a: int) -> np.ndarray:
+    """alive[k]: no point other than u and v[k] lies in the beta-lune of (u, v[k])."""
+    uv = K[u][None, :] - K[v]                                    # u - v, (|v|, d)
+    rhs = a * a * (uv * uv).sum(axis=1)                          # a^2 d^2(u, v)
+    e1 = 8 * (K[None, :, :] - K[u][None, None, :]) + a * uv[:, None, :]   # 8(z - u) + a(u - v)
+    e2 = 8 * (K[None, :, :] - K[v][:, None, :]) - a * uv[:, None, :]      # 8(z - v) + a(v - u)
+    inside = ((e1 * e1).sum(axis=2) < rhs[:, None]) & ((e2 * e2).sum(axis=2) < rhs[:, None])
+    inside[:, u] = False
+    inside[np.arange(len(v)), v] = False
+    return ~inside.any(axis=1)
+
+
+def beta_skeleton_edges(K: np.ndarray, beta_quarters: int) -> np.ndarray:
+    """Sorted (u < v) pairs of the lune-based beta-skeleton, beta = beta_quarters / 4 >= 1,
+    on exact int64 arithmetic (raises where int64 could overflow)."""
+    K, a = _beta_checked(K, beta_quarters)
+    n = K.shape[0]
+    out = []
+    for u in range(n - 1):
+        v = np.arange(u + 1, n)
+        out.extend((u, int(w)) for w in v[_beta_alive(K, u, v, a)])
+    return np.asarray(out, dtype=np.int64).reshape(-1, 2)
+
+
+def beta_skeleton_row(K: np.ndarray, i: int, beta_quarters: int) -> np.ndarray:
+    """Sorted neighbours of point i in the beta-skeleton of K (the test is
+    symmetric in the pair's two points)."""
+    K, a = _beta_checked(K, beta_quarters)
+    v = np.array([w for w in range(K.shape[0]) if w != i], dtype=np.int64)
+    return v[_beta_alive(K, i, v, a)]
+
+
+def beta_skeleton_edges_loops(K, beta: Fraction) -> list:
+    """Loop-only beta-skeleton for tiny inputs, in exact rationals: the two
+    centres are formed as points and the squared radius as (beta d / 2)^2."""
+    pts = [tuple(Fraction(int(c)) for c in row) for row in np.asarray(K)]
+    n = len(pts)
+    beta = Fraction(beta)
+
+    def d2(p, q):
+        return sum((x - y) ** 2 for x, y in zip(p, q))
+
+    edges = []
+    for u in range(n):
+        for v in range(u + 1, n):
+            pu, pv = pts[u], pts[v]
+            c1 = tuple((1 - beta / 2) * x + beta / 2 * y for x, y in zip(pu, pv))
+            c2 = tuple(beta / 2 * x + (1 - beta / 2) * y for x, y in zip(pu, pv))
+            r2 = (beta / 2) ** 2 * d2(pu, pv)
+            if all(not (d2(pts[z], c1) < r2 and d2(pts[z], c2) < r2) for z in range(n) if z != u and z != v):
+                edges.append((u, v))
+    return edges

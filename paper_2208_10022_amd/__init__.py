@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_ED
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 ORDER_DISTANCE, ORDER_LEARNED, ORDER_LUNE = 0, 1, 2
 METRIC_L2, METRIC_L1, METRIC_LINF = 0, 1, 2
-GRAPH_RNG, GRAPH_GABRIEL = 0, 1
+GRAPH_RNG, GRAPH_GABRIEL, GRAPH_BETA = 0, 1, 2
 
 # Entry points declared in include/grng.h (checked by the CPU tests).
 ABI_FUNCTIONS = ("grng_abi_version", "grng_last_error", "grng_create", "grng_build_grng_layer", "grng_build_rng",
@@ -40,7 +40,7 @@ class Options(C.Structure):
     _fields_ = [("grid_exp", C.c_int32), ("precision", C.c_int32), ("witness_order", C.c_int32),
                 ("use_graph", C.c_int32), ("autotune", C.c_int32), ("stage4_pivots", C.c_int32),
                 ("vgrng_pivots", C.c_int32), ("metric", C.c_int32), ("graph", C.c_int32),
-                ("reserved_i", C.c_int32 * 1), ("reserved", C.c_uint64 * 3)]
+                ("beta_quarters", C.c_int32), ("reserved", C.c_uint64 * 3)]
 
 
 class Stats(C.Structure):
@@ -194,12 +194,18 @@ class Index:
 
     def __init__(self, points, grid_exp: int, precision: int = PREC_FP64, witness_order: int = ORDER_DISTANCE,
                  use_graph: int = 0, autotune: int = 0, stage4_pivots: int = 0, vgrng_pivots: int = 0,
-                 metric: int = METRIC_L2, graph: int = GRAPH_RNG, stream=None):
+                 metric: int = METRIC_L2, graph: int = GRAPH_RNG, beta: float = 0.0, stream=None):
+        """beta: the beta of graph=GRAPH_BETA, a multiple of 1/4 in [1, 16] (ignored otherwise)."""
         self._h = C.c_void_p()
         self._stream = stream
+        bq = 0
+        if graph == GRAPH_BETA:
+            bq = int(round(beta * 4))
+            if bq != beta * 4:
+                raise ValueError("beta must be a multiple of 1/4")
         opt = Options(grid_exp=grid_exp, precision=precision, witness_order=witness_order, use_graph=use_graph,
                       autotune=autotune, stage4_pivots=stage4_pivots, vgrng_pivots=vgrng_pivots, metric=metric,
-                      graph=graph)
+                      graph=graph, beta_quarters=bq)
         n, d = points.shape
         check(lib().grng_create(C.byref(self._h), _dev_ptr(points, "float32", 2), n, d,
                                 _stream_handle(stream), C.byref(opt)))

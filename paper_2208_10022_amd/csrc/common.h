@@ -426,7 +426,8 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         uint64_t *work, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
-                     int64_t z_from, int metric, int graph, uint8_t *alive, uint64_t *counters);
+                     int64_t z_from, int metric, int graph, int beta_q, int grid_exp, uint8_t *alive,
+                     uint64_t *counters);
 void launch_pair_d2(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, int dp, const double *Xh,
                     const double *nrmh, double *d2, uint64_t *dmax_bits);
 void launch_query_csr(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const uint8_t *alive,

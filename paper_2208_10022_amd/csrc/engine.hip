@@ -96,10 +96,13 @@ void check_opts(const grng_options *o) {
     require(o->stage4_pivots >= 0 && o->stage4_pivots <= kPivWitness, GRNG_EINVAL, "stage4_pivots must be in [0, 16]");
     require(o->vgrng_pivots >= 0, GRNG_EINVAL, "vgrng_pivots must be >= 0");
     require(o->metric >= GRNG_METRIC_L2 && o->metric <= GRNG_METRIC_LINF, GRNG_EINVAL, "unknown metric");
-    require(o->graph == GRNG_GRAPH_RNG || o->graph == GRNG_GRAPH_GABRIEL, GRNG_EINVAL, "unknown graph");
+    require(o->graph >= GRNG_GRAPH_RNG && o->graph <= GRNG_GRAPH_BETA, GRNG_EINVAL, "unknown graph");
     require(o->graph == GRNG_GRAPH_RNG || o->metric == GRNG_METRIC_L2, GRNG_EINVAL,
-            "the Gabriel graph is defined for the Euclidean metric only");
-    require(o->reserved_i[0] == 0, GRNG_EINVAL, "reserved option fields must be 0");
+            "the Gabriel graph and the beta-skeleton are defined for the Euclidean metric only");
+    if (o->graph == GRNG_GRAPH_BETA)
+        require(o->beta_quarters >= 4 && o->beta_quarters <= 64, GRNG_EINVAL, "beta_quarters must be in [4, 64]");
+    else
+        require(o->beta_quarters == 0, GRNG_EINVAL, "beta_quarters must be 0 unless graph is GRNG_GRAPH_BETA");
     for (int t = 0; t < 3; ++t) require(o->reserved[t] == 0, GRNG_EINVAL, "reserved option fields must be 0");
 }
 
@@ -335,7 +338,8 @@ void build_rng_brute(grng_index *idx, DevBuf &edges, int64_t &ne, double &ms_lun
     EventTimer lt(s);
     launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), n, idx->dp, idx->X.as<double>(),
                     idx->nrm.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0, idx->opt.metric,
-                    idx->opt.graph, alive.as<uint8_t>(), idx->counters.as<uint64_t>());
+                    idx->opt.graph, idx->opt.beta_quarters, idx->opt.grid_exp, alive.as<uint8_t>(),
+                    idx->counters.as<uint64_t>());
     ms_lune = lt.stop();
     pairs_to_edges(s, n, np, P.x.as<int32_t>(), P.y.as<int32_t>(), alive.as<uint8_t>(), nullptr, edges, ne);
 }
@@ -1123,7 +1127,8 @@ void do_query(grng_index *idx, const float *q, int64_t nq, int64_t *offsets, int
         EventTimer lt(s);
         launch_lune_all(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->n, idx->dp,
                         Xq.as<double>(), nq2.as<double>(), idx->X.as<double>(), idx->nrm.as<double>(), 0,
-                        idx->opt.metric, idx->opt.graph, alive.as<uint8_t>(), idx->counters.as<uint64_t>());
+                        idx->opt.metric, idx->opt.graph, idx->opt.beta_quarters, idx->opt.grid_exp,
+                        alive.as<uint8_t>(), idx->counters.as<uint64_t>());
         bt.lune = lt.stop();
     } else {
         const Layer &L = idx->layers.back();

@@ -1282,13 +1282,32 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     }
 }
 
+// Unsigned 128-bit sums of squares for the exact beta-skeleton test.
+struct U128 {
+    uint64_t lo, hi;
+};
+__device__ inline void add_square(U128 &acc, int64_t e) {
+    const uint64_t u = (uint64_t)(e < 0 ? -e : e);
+    const uint64_t lo = u * u;
+    acc.lo += lo;
+    acc.hi += __umul64hi(u, u) + (acc.lo < lo);
+}
+__device__ inline bool lt_u128(const U128 &a, const U128 &b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+
 // Empty-region test against every point (no pivot layer).  One wave per
 // pair, 64 witnesses per step, a ballot ends the pair at the first point in
 // its region:
 //   RNG      max(d(x,z), d(y,z)) < d(x,y) under the index's metric (distance
 //            keys: squared Euclidean, L1, L-infinity);
 //   Gabriel  d^2(x,z) + d^2(y,z) < d^2(x,y), tested as d^2(x,z) < d^2(x,y) -
-//            d^2(y,z) (exact: a difference of integers below 2^53).
+//            d^2(y,z) (exact: a difference of integers below 2^53);
+//   beta     (lune-based beta-skeleton, beta = a/4 >= 1) z in both open balls
+//            of radius beta d(x,y)/2 centred at (1 - beta/2) x + (beta/2) y
+//            and (beta/2) x + (1 - beta/2) y; times 16 these are
+//            |8(z - x) + a(x - y)|^2 < a^2 d^2(x,y) and the same with x and y
+//            swapped.  On the grid each term 8(z - x) + a(x - y) is an integer
+//            of at most 32 bits in units of 2^-q, formed exactly in float64;
+//            its square and the sums are taken in 128-bit integers.
 // Partial sums (or maxima) of non-negative terms only grow, so a partial key
 // at or above the threshold ends a test early.
 __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t *__restrict__ px,
@@ -1296,12 +1315,14 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
                                                   int64_t n, int dp, const double *__restrict__ Xx,
                                                   const double *__restrict__ nrmx, const double *__restrict__ X,
                                                   const double *__restrict__ nrm, int64_t z_from, int metric,
-                                                  int graph, uint8_t *__restrict__ alive,
+                                                  int graph, int beta_q, double gscale, uint8_t *__restrict__ alive,
                                                   unsigned long long *counters) {
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const bool gabriel = graph == GRNG_GRAPH_GABRIEL;
+    const bool beta = graph == GRNG_GRAPH_BETA;
+    const double a = (double)beta_q;
     uint32_t ntests = 0;
     for (int64_t p = wave0; p < npairs; p += nwaves) {
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
@@ -1309,11 +1330,33 @@ __global__ __launch_bounds__(256) void k_lune_all(int64_t npairs, const int32_t 
         const double d2 = pd2[p];
         const double *xs = Xx + x * dp;
         const double *ys = X + y * dp;
+        U128 rhs = {0, 0};   // beta: a^2 d^2(x,y) in grid units
+        if (beta) {
+            uint64_t s = 0;   // d^2(x,y) < 2^53 grid units under the grid contract
+            for (int c = 0; c < dp; ++c) {
+                const int64_t e = (int64_t)((xs[c] - ys[c]) * gscale);
+                s += (uint64_t)(e * e);
+            }
+            const uint64_t a2 = (uint64_t)beta_q * (uint64_t)beta_q;
+            rhs.lo = a2 * s;
+            rhs.hi = __umul64hi(a2, s);
+        }
         bool dead = false;
         for (int64_t zb = z_from; zb < n; zb += 64) {
             const int64_t z = zb + lane;
             bool wit = false;
-            if (z < n) {
+            if (z < n && beta) {
+                const double *zr = X + z * dp;
+                U128 s1 = {0, 0}, s2 = {0, 0};
+                for (int c = 0; c < dp; ++c) {
+                    if (c >= 8 && (c & 7) == 0 && !(lt_u128(s1, rhs) && lt_u128(s2, rhs))) break;
+                    const double xy = xs[c] - ys[c];
+                    add_square(s1, (int64_t)((8.0 * (zr[c] - xs[c]) + a * xy) * gscale));
+                    add_square(s2, (int64_t)((8.0 * (zr[c] - ys[c]) - a * xy) * gscale));
+                }
+                wit = lt_u128(s1, rhs) && lt_u128(s2, rhs);
+                ++ntests;
+            } else if (z < n) {
                 const double *zr = X + z * dp;
                 double sx = 0.0, sy = 0.0;
                 for (int c = 0; c < dp; ++c) {
@@ -1518,11 +1561,13 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
 
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
-                     int64_t z_from, int metric, int graph, uint8_t *alive, uint64_t *counters) {
+                     int64_t z_from, int metric, int graph, int beta_q, int grid_exp, uint8_t *alive,
+                     uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
     const int64_t grid = std::min<int64_t>(div_up(npairs, 4), 1 << 16);
     k_lune_all<<<(unsigned)grid, 256, 0, s>>>(npairs, px, py, pd2, n, dp, Xx, nrmx, X, nrm, z_from, metric, graph,
+                                              beta_q, std::ldexp(1.0, grid_exp),
                                               alive, (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }

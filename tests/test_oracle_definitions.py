@@ -13,6 +13,8 @@
 """
 import math
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -117,6 +119,85 @@ def test_rng_is_strictly_inside_gabriel_on_a_fixed_case():
     K = np.array([[0, 0], [4, 0], [2, 3]], np.int64)
     assert edge_set(rng.rng_edges(K)) == {(0, 2), (1, 2)}
     assert edge_set(rng.gabriel_edges(K)) == {(0, 1), (0, 2), (1, 2)}
+
+
+# --- lune-based beta-skeleton ---------------------------------------------------
+
+# u = (0,0), v = (40,0), beta = 3/2: the balls have radius 30 around (30,0) and
+# (10,0), so z = (20,28) (10^2 + 28^2 = 884 < 900) blocks (u, v) and z = (20,29)
+# (941 > 900) does not; the RNG lune (radius 40 around u and v) holds both.
+@pytest.mark.parametrize("z,beta,want", [
+    ((20, 28), Fraction(3, 2), {(0, 2), (1, 2)}),
+    ((20, 29), Fraction(3, 2), {(0, 1), (0, 2), (1, 2)}),
+    ((20, 29), Fraction(2), {(0, 2), (1, 2)}),
+    ((20, 29), Fraction(1), {(0, 1), (0, 2), (1, 2)}),
+    # (20, 20) lies on the Gabriel circle of (u, v): the open disk keeps the edge
+    ((20, 20), Fraction(1), {(0, 1), (0, 2), (1, 2)}),
+    ((20, 20), Fraction(5, 4), {(0, 2), (1, 2)}),
+])
+def test_beta_skeleton_fixed_cases(z, beta, want):
+    K = np.array([[0, 0], [40, 0], list(z)], np.int64)
+    assert edge_set(rng.beta_skeleton_edges(K, int(beta * 4))) == want
+    assert set(rng.beta_skeleton_edges_loops(K, beta)) == want
+
+
+def test_beta_skeleton_special_cases_and_nesting():
+    # beta 1 is the Gabriel graph and beta 2 the RNG (both pinned above by
+    # their own fixed cases); a larger beta widens the region, so the graphs
+    # nest; on a line every beta >= 1 leaves the sorted path.
+    g = np.random.default_rng(41)
+    for t in range(12):
+        n, d = int(g.integers(5, 40)), int(g.integers(1, 4))
+        K = g.integers(0, 5 if t % 3 == 0 else 10 ** 5, size=(n, d)).astype(np.int64)
+        assert edge_set(rng.beta_skeleton_edges(K, 4)) == edge_set(rng.gabriel_edges(K))
+        assert edge_set(rng.beta_skeleton_edges(K, 8)) == edge_set(rng.rng_edges(K))
+        prev = None
+        for a in (4, 5, 6, 8, 11, 16, 64):
+            E = edge_set(rng.beta_skeleton_edges(K, a))
+            if prev is not None:
+                assert E <= prev, (t, a)
+            prev = E
+    x = np.unique(g.integers(0, 1000, size=30))
+    K = x[g.permutation(len(x))][:, None].astype(np.int64)
+    order = np.argsort(K[:, 0])
+    path = {tuple(sorted((int(order[i]), int(order[i + 1])))) for i in range(len(order) - 1)}
+    for a in (4, 6, 8, 13, 64):
+        assert edge_set(rng.beta_skeleton_edges(K, a)) == path
+
+
+def test_beta_skeleton_on_a_ball_boundary_at_large_coordinates():
+    # x = (-5u, 0), y = (5u, 0), u = 2^20.  beta 2: z = (-3u, 6u) has |z - y| =
+    # 10u = |x - y| (a 6-8-10 triangle), on the boundary; one unit toward y it
+    # is inside.  beta 3/2: the ball around (2.5u, 0) has radius 7.5u and
+    # z = (-2u, 6u) lies on it (4.5^2 + 6^2 = 7.5^2), while |z - (-2.5u, 0)|^2 =
+    # 36.25 u^2 < 56.25 u^2 puts it inside the other ball.
+    u = 2 ** 20
+    for z, beta in (((-3 * u, 6 * u), Fraction(2)), ((-2 * u, 6 * u), Fraction(3, 2))):
+        on = np.array([[-5 * u, 0], [5 * u, 0], list(z)], np.int64)
+        inside = on.copy()
+        inside[2, 0] += 1
+        assert set(rng.beta_skeleton_edges_loops(on, beta)) == {(0, 1), (0, 2), (1, 2)}
+        assert set(rng.beta_skeleton_edges_loops(inside, beta)) == {(0, 2), (1, 2)}
+
+
+def test_beta_skeleton_rows_match_the_edge_set():
+    g = np.random.default_rng(47)
+    for t in range(6):
+        K = g.integers(0, 8 if t % 2 else 500, size=(30, 2)).astype(np.int64)
+        a = int(g.integers(4, 20))
+        E = rng.beta_skeleton_edges(K, a)
+        for i in range(len(K)):
+            want = np.sort(np.concatenate([E[E[:, 1] == i, 0], E[E[:, 0] == i, 1]]))
+            assert np.array_equal(rng.beta_skeleton_row(K, i, a), want), (t, i)
+
+
+def test_beta_skeleton_integer_form_matches_the_rational_centres():
+    g = np.random.default_rng(43)
+    for t in range(25):
+        n, d = int(g.integers(3, 12)), int(g.integers(1, 4))
+        K = g.integers(0, 4 if t % 2 else 50, size=(n, d)).astype(np.int64)
+        a = int(g.integers(4, 30))
+        assert edge_set(rng.beta_skeleton_edges(K, a)) == set(rng.beta_skeleton_edges_loops(K, Fraction(a, 4))), t
 
 
 # --- Stage VII bounds (Proposition 5) -----------------------------------------
