@@ -361,7 +361,8 @@ def other_form(P, W, precision, st, witness_order=0, scorer=None, warmup=1):
 def form_entry(ms, st, same, base_ms):
     return {"ms": ms, "speedup_vs_plain": base_ms / ms, "identical_edges": bool(same),
             "exhaustive_pairs": st["exhaustive_pairs"], "lune_tests": st["lune_tests"],
-            "lune_tests_kept": st["lune_tests_kept"], "rechecks": st["rechecks"],
+            "lune_tests_kept": st["lune_tests_kept"], "partner_kills": st["partner_kills"],
+            "ms_partner": st["ms_partner"], "rechecks": st["rechecks"],
             "screen_uncertain": st["screen_uncertain"], "ms_pairs": st["ms_pairs"], "ms_lune": st["ms_lune"]}
 
 
@@ -501,6 +502,9 @@ def main():
         "exhaustive_pairs": st["exhaustive_pairs"],
         "lune_tests": st["lune_tests"],
         "lune_tests_kept": st["lune_tests_kept"],
+        "partner_tests": st["partner_tests"],
+        "partner_kills": st["partner_kills"],
+        "ms_partner": st["ms_partner"],
         "rechecks": st["rechecks"],
         "screen_uncertain": st["screen_uncertain"],
         "tile_pairs": st["tile_pairs"],

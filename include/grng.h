@@ -147,7 +147,8 @@ typedef struct grng_stats {
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
     double stage4_survivors;      /* pairs left after pivot witnesses (Stage IV) */
-    double exhaustive_pairs;      /* pairs left for the exhaustive scan after Stage V */
+    double exhaustive_pairs;      /* pairs left after Stage V in the tiles (the partner pass below takes
+                                     them first, the exhaustive scan what it leaves) */
     double lune_tests;            /* witness predicates evaluated by the exhaustive scan */
     double rechecks;              /* comparisons re-decided in float64 / exact integers */
     double ms_layers;             /* device time of the last layer build */
@@ -179,6 +180,12 @@ typedef struct grng_stats {
                                      blocks and the Stage V witness matrices */
     double lune_tests_kept;       /* of lune_tests, those spent on pairs that stayed edges (each such pair
                                      tests every witness its cells hold; no visit order saves them) */
+    double partner_tests;         /* Stage V with the row's other candidates (Algorithm 1, Stage 5): witness
+                                     predicates evaluated, each pair of exhaustive_pairs against the 64
+                                     partners nearest to each of its ends in that list */
+    double partner_kills;         /* of exhaustive_pairs, those this pass proved non-edges (the exhaustive
+                                     scan skips them) */
+    double ms_partner;            /* device time of that pass in the last build */
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("lune_bytes", C.c_double), ("stage4_ops", C.c_double), ("ms_autotune", C.c_double),
                 ("ms_pair_masks", C.c_double), ("screen_uncertain", C.c_double),
                 ("pair_tile_entries", C.c_double), ("pair_method_distances", C.c_double),
-                ("lune_tests_kept", C.c_double)]
+                ("lune_tests_kept", C.c_double), ("partner_tests", C.c_double), ("partner_kills", C.c_double),
+                ("ms_partner", C.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

@@ -182,9 +182,11 @@ enum Counter {
     C_PD_PIV,         // pair kernels: entries of the pivot blocks D(T,P), D(U,P) computed
     C_PD_V,           // pair kernels: entries of the Stage V witness matrices D(U,U), D(T,T) computed
     C_LUNE_KEPT,      // exhaustive scan: witness predicates of pairs that stayed edges
+    C_PARTNER_TESTS,  // Stage V with the row's other candidates: witness predicates evaluated
+    C_PARTNER_KILLS,  // Stage V with the row's other candidates: pairs proven non-edges
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
-    C_WORK0 = 16,
+    C_WORK0 = 32,
     C_WORK_END = C_WORK0 + 8 * 16,
     C_NUM = C_WORK_END
 };
@@ -422,8 +424,17 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const int32_t *zstart, const int32_t *grp_off, const double *dvor,
                         const double *Xp, const double *nrmp, const int64_t *rel_off, const int32_t *rel_grp,
                         const double *rel_d2x, const double *rad, const uint16_t *scorer, bool lune_order,
-                        uint8_t *alive,
+                        bool prekilled, uint8_t *alive,
                         uint64_t *work, uint64_t *counters);
+constexpr int kPartnerWitnesses = 64;   // nearest partners kept per row point
+// Stage V with the row's other candidates as witnesses: each row point's 64
+// nearest partners in a row-sorted pair list (off: row offsets), then a
+// proven-kill pass writing alive[p] (0: proven non-edge, 1: left to the scan).
+void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
+                        int32_t *wid, float *wd2);
+void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
+                            int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
+                            bool both, uint8_t *alive, uint64_t *counters);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
                      int64_t z_from, int metric, int graph, int beta_q, int grid_exp, uint8_t *alive,

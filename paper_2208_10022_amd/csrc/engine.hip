@@ -356,7 +356,7 @@ void trace(const char *stage, double ms, int64_t count) {
 }
 
 struct BuildTimes {
-    double vgrng = 0, masks = 0, pairs = 0, lune = 0;
+    double vgrng = 0, masks = 0, pairs = 0, lune = 0, partner = 0;
     int64_t tile_pairs = 0;
     double host_dist = 0;   // squared distances of whole tables (point-pivot D_XP) computed on the way
 };
@@ -899,8 +899,9 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     hipStream_t s = idx->stream;
     const int64_t n = X.n, m = L.m;
     uint64_t *ctr = idx->counters.as<uint64_t>();
+    DevBuf roff;
     {
-        DevBuf cnt, roff, sx, sy, sd2;
+        DevBuf cnt, sx, sy, sd2;
         cnt.alloc(4 * (size_t)std::max<int64_t>(n + 1, 2));
         zero(cnt, s);
         roff.alloc(8 * (size_t)(n + 1));
@@ -912,6 +913,27 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
         P.x = std::move(sx);
         P.y = std::move(sy);
         P.d2 = std::move(sd2);
+    }
+    const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
+    alive.alloc((size_t)std::max<int64_t>(np, 8));
+    // Stage V with the row's other candidates as witnesses: each pair against
+    // the nearest partners of its ends in this list (both ends when they are
+    // points of one set; a query's or batch point's partners otherwise).  Not
+    // in Stage VII, whose pairs are edges no old point can invalidate.
+    const bool prekilled = zstart == nullptr && np > 0;
+    if (prekilled) {
+        DevBuf wid, wd2;
+        wid.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
+        wd2.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
+        EventTimer pt(s);
+        launch_partner_top(s, n, roff.as<int64_t>(), P.y.as<int32_t>(), P.d2.as<double>(), wid.as<int32_t>(),
+                           wd2.as<float>());
+        launch_partner_witness(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp,
+                               f32 ? S.Xf.as<float>() : nullptr, S.Xh.as<double>(), wid.as<int32_t>(),
+                               wd2.as<float>(), X.Xh.p == S.Xh.p, alive.as<uint8_t>(), ctr);
+        const double ms = pt.stop();
+        bt.partner += ms;
+        trace("Stage V on partner witnesses", ms, np);
     }
     DevBuf rel_cnt, rel_off, rel_grp, rel_d2x;
     rel_cnt.alloc(4 * (size_t)n);
@@ -929,9 +951,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
     launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter,
                            dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(),
                            rel_d2x.as<double>(), ctr, sort);
-    alive.alloc((size_t)std::max<int64_t>(np, 8));
     EventTimer lt(s);
-    const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
                        X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.n, S.dhome.as<double>(),
                        f32 ? X.Xf.as<float>() : nullptr, f32 ? S.Xf.as<float>() : nullptr,
@@ -939,7 +959,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                        S.grp_off.as<int32_t>(), crad, aux.Xp.as<double>(), aux.nrmp.as<double>(),
                        rel_off.as<int64_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(), L.rad.as<double>(),
                        idx->opt.witness_order == GRNG_ORDER_LEARNED ? idx->scorer.as<uint16_t>() : nullptr,
-                       idx->opt.witness_order == GRNG_ORDER_LUNE,
+                       idx->opt.witness_order == GRNG_ORDER_LUNE, prekilled,
                        alive.as<uint8_t>(), ctr + C_WORK0, ctr);
     const double lms = lt.stop();
     bt.lune += lms;
@@ -994,6 +1014,9 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     idx->stats.pair_tile_entries = (double)(c[C_PD_TU] + c[C_PD_PIV] + c[C_PD_V]);
     idx->stats.pair_method_distances = (double)(c[C_CAND] + c[C_PD_PIV] + c[C_PD_V]);
     idx->stats.lune_tests_kept = (double)c[C_LUNE_KEPT];
+    idx->stats.partner_tests = (double)c[C_PARTNER_TESTS];
+    idx->stats.partner_kills = (double)c[C_PARTNER_KILLS];
+    idx->stats.ms_partner = bt.partner;
     // Bytes a witness test reads: the witness row and its cell-distance
     // bound (float32 with the float32 screen, float64 otherwise); a test
     // that ends early on a partial sum reads less.

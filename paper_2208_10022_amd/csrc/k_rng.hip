@@ -935,6 +935,144 @@ __global__ __launch_bounds__(kRelThreads) void k_relevant_groups(int64_t n, int6
 }
 
 // ---------------------------------------------------------------------------
+// Stage V with the row's other candidates as witnesses (Algorithm 1, Stage 5:
+// a candidate x_k of Q invalidates link (Q, x_j) when it lies in their lune).
+// Here a row point's candidates are its partners in the exhaustive pair list
+// (the pairs Stages I-V left), and each pair (x, y) is tested against the 64
+// partners of x nearest to x and, when y is a point of the same set, the 64
+// partners of y nearest to y.  Only proven kills count (anything uncertain is
+// left to the exhaustive scan), so the witness choice affects work only.
+
+static_assert(kPartnerWitnesses == kWave, "one partner witness per lane");
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, kWave), hi = __shfl_xor((uint32_t)(v >> 32), m, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = __shfl((uint32_t)v, src, kWave), hi = __shfl((uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+// Ascending bitonic sort of one value per lane across the wave.
+__device__ inline uint64_t wave_sort_u64(uint64_t k) {
+    const int lane = threadIdx.x & 63;
+    for (int size = 2; size <= 64; size <<= 1)
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            const uint64_t o = shfl_xor_u64(k, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0 || size == 64);
+            k = keep_min ? (o < k ? o : k) : (o > k ? o : k);
+        }
+    return k;
+}
+// Ascending order of a bitonic sequence held one value per lane.
+__device__ inline uint64_t wave_merge_u64(uint64_t k) {
+    const int lane = threadIdx.x & 63;
+    for (int j = 32; j > 0; j >>= 1) {
+        const uint64_t o = shfl_xor_u64(k, j);
+        k = (lane & j) == 0 ? (o < k ? o : k) : (o > k ? o : k);
+    }
+    return k;
+}
+
+// The kPartnerWitnesses (64) nearest partners of each row point (rows of the list sorted
+// by row point, row r at [off[r], off[r+1])): key = float32 d^2 rounded up
+// (an upper bound; bit patterns of non-negative floats order as integers),
+// then the partner's index.  One wave per row, 64 entries per step merged
+// into the running best 64.  Unused slots: id -1, d^2 +inf.
+__global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ py, const double *__restrict__ pd2,
+                                                     int32_t *__restrict__ wid, float *__restrict__ wd2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += nw) {
+        const int64_t b = off[r], e = off[r + 1];
+        uint64_t best = ~0ull;
+        for (int64_t c0 = b; c0 < e; c0 += 64) {
+            const int64_t i = c0 + lane;
+            uint64_t k = ~0ull;
+            if (i < e) k = ((uint64_t)__float_as_uint(__double2float_ru(pd2[i])) << 32) | (uint32_t)py[i];
+            k = wave_sort_u64(k);
+            if (c0 == b) {
+                best = k;
+                continue;
+            }
+            // best and k ascending: the lane-wise min of best and k reversed
+            // holds the 64 smallest of both, as a bitonic sequence
+            const uint64_t rk = shfl_u64(k, 63 - lane);
+            best = wave_merge_u64(rk < best ? rk : best);
+        }
+        const bool none = best == ~0ull;
+        wid[r * kPartnerWitnesses + lane] = none ? -1 : (int32_t)(uint32_t)best;
+        wd2[r * kPartnerWitnesses + lane] = none ? INFINITY : __uint_as_float((uint32_t)(best >> 32));
+    }
+}
+
+// d^2(a, b) < t proven on rows of dp values (early exit once a partial sum
+// reaches t: partial sums only grow).  Float32 rows: the direct-form sum's
+// relative error is below (dp+2) 2^-24, so t is the pair's d^2 lowered by
+// (dp+8) 2^-24 and rounded down; float64 rows: exact sums, t = d^2.
+template <typename T>
+__device__ inline bool below(const T *__restrict__ a, const T *__restrict__ b, int dp, T t) {
+    T s = 0;
+    for (int c = 0; c < dp; c += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T e = a[c + u] - b[c + u];
+            s = fma(e, e, s);
+        }
+        if (!(s < t)) return false;
+    }
+    return true;
+}
+
+template <bool F32>
+__global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32_t *__restrict__ px,
+                                                         const int32_t *__restrict__ py,
+                                                         const double *__restrict__ pd2, int dp,
+                                                         const float *__restrict__ Xf, const double *__restrict__ Xd,
+                                                         const int32_t *__restrict__ wid,
+                                                         const float *__restrict__ wd2, bool both,
+                                                         uint8_t *__restrict__ alive,
+                                                         unsigned long long *counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const double g32 = (double)(dp + 8) * 0x1p-24;
+    uint32_t ntests = 0, nkill = 0;
+    for (int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6); p < np; p += nw) {
+        const int32_t x = __builtin_amdgcn_readfirstlane(px[p]);
+        const int32_t y = __builtin_amdgcn_readfirstlane(py[p]);
+        const double d2 = pd2[p];
+        const float tf = __double2float_rd(d2 - d2 * g32);
+        bool dead = false;
+        for (int side = 0; side < (both ? 2 : 1) && !dead; ++side) {
+            // witnesses z near a (d(a,z) < d(x,y) proven by the rounded-up key),
+            // tested against the other end b
+            const int32_t a = side ? y : x, b = side ? x : y;
+            const int32_t z = wid[(int64_t)a * kPartnerWitnesses + lane];
+            const bool elig = z >= 0 && z != b && z != a && (double)wd2[(int64_t)a * kPartnerWitnesses + lane] < d2;
+            bool kill = false;
+            if (elig) {
+                ++ntests;
+                kill = F32 ? below(Xf + (int64_t)b * dp, Xf + (int64_t)z * dp, dp, tf)
+                           : below(Xd + (int64_t)b * dp, Xd + (int64_t)z * dp, dp, d2);
+            }
+            dead = __ballot(kill) != 0;
+        }
+        if (lane == 0) {
+            alive[p] = dead ? 0 : 1;
+            nkill += dead;
+        }
+    }
+    ntests = wave_sum(ntests);
+    if (lane == 0) {
+        atomicAdd(&counters[C_WTEST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_DIST], (unsigned long long)ntests);
+        atomicAdd(&counters[C_PARTNER_TESTS], (unsigned long long)ntests);
+        if (nkill) atomicAdd(&counters[C_PARTNER_KILLS], (unsigned long long)nkill);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Exhaustive lune test of surviving pairs (Stages IV-VI).  One wave per pair.
 //
 // The row point's relevant cells are taken 64 at a time (one per lane):
@@ -973,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
     const int32_t *__restrict__ zstart, const int32_t *__restrict__ grp_off, const double *__restrict__ dvor,
     const double *__restrict__ Xp, const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off,
     const int32_t *__restrict__ rel_grp, const double *__restrict__ rel_d2x, const double *__restrict__ rad,
-    const uint16_t *__restrict__ scorer, bool lune_order,
+    const uint16_t *__restrict__ scorer, bool lune_order, bool prekilled,
     uint8_t *__restrict__ alive, unsigned long long *work, unsigned long long *counters) {
     // Per-wave cell table in visit order: first member, exclusive member
     // prefix (entry 64 = total) and max(d(x,p), d(y,p)) lower bound.
@@ -1017,6 +1155,7 @@ __global__ __launch_bounds__(256) void k_lune_guided(
             if (cur < 0) break;
         }
         const int64_t p = cur++;
+        if (prekilled && alive[p] == 0) continue;   // a proven kill of the partner pass (uniform)
         const int64_t x = __builtin_amdgcn_readfirstlane(px[p]);
         const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
         const double d2 = pd2[p];
@@ -1517,7 +1656,7 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const int32_t *zstart, const int32_t *grp_off,
                         const double *dvor, const double *Xp, const double *nrmp, const int64_t *rel_off,
                         const int32_t *rel_grp, const double *rel_d2x, const double *rad, const uint16_t *scorer,
-                        bool lune_order,
+                        bool lune_order, bool prekilled,
                         uint8_t *alive, uint64_t *work, uint64_t *counters) {
     if (npairs == 0) return;
     require(dp <= kMaxDp, GRNG_EINVAL, "dimension too large for the lune kernel");
@@ -1549,13 +1688,35 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
     if (f32)
         k_lune_guided<true><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, Xpre, pst, dhomef, zstart, grp_off, dvor,
-            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, prekilled, alive, (unsigned long long *)work,
             (unsigned long long *)counters);
     else
         k_lune_guided<false><<<(unsigned)grid, 256, 0, s>>>(
             npairs, px, py, pd2, dp, Xx, nrmx, Xh, nrmh, dhome, Xxf, Xhf, Xpre, pst, dhomef, zstart, grp_off, dvor,
-            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, alive, (unsigned long long *)work,
+            Xp, nrmp, rel_off, rel_grp, rel_d2x, rad, scorer, lune_order, prekilled, alive, (unsigned long long *)work,
             (unsigned long long *)counters);
+    GRNG_LAUNCHED();
+}
+
+void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
+                        int32_t *wid, float *wd2) {
+    if (nrows == 0) return;
+    const int64_t grid = std::min<int64_t>(div_up(nrows, 4), 1 << 16);
+    k_partner_top<<<(unsigned)grid, 256, 0, s>>>(nrows, off, py, pd2, wid, wd2);
+    GRNG_LAUNCHED();
+}
+
+void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
+                            int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
+                            bool both, uint8_t *alive, uint64_t *counters) {
+    if (np == 0) return;
+    const int64_t grid = std::min<int64_t>(div_up(np, 4), 1 << 16);
+    if (Xf)
+        k_partner_witness<true><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, Xd, wid, wd2, both, alive,
+                                                               (unsigned long long *)counters);
+    else
+        k_partner_witness<false><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, Xd, wid, wd2, both, alive,
+                                                                (unsigned long long *)counters);
     GRNG_LAUNCHED();
 }
 
