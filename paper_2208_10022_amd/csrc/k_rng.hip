@@ -1025,42 +1025,92 @@ __device__ inline bool below(const T *__restrict__ a, const T *__restrict__ b, i
     return true;
 }
 
-template <bool F32>
+// The proven-kill pass.  The list is sorted by row point, and each wave
+// takes chunks of kPartnerChunk consecutive pairs, so most of a chunk shares
+// its row point x: the 64 partners of x (one per lane) are loaded once per
+// row point with the first KR coordinates of their rows in registers, and a
+// pair (x, y) then tests them against y's row, which is the same for the
+// whole wave.  A pair that survives is tested against the partners of y
+// (their rows gathered) with x's row.
+constexpr int kPartnerChunk = 64;
+
+template <typename T, int KR>
 __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32_t *__restrict__ px,
                                                          const int32_t *__restrict__ py,
                                                          const double *__restrict__ pd2, int dp,
-                                                         const float *__restrict__ Xf, const double *__restrict__ Xd,
-                                                         const int32_t *__restrict__ wid,
+                                                         const T *__restrict__ X, const int32_t *__restrict__ wid,
                                                          const float *__restrict__ wd2, bool both,
                                                          uint8_t *__restrict__ alive,
                                                          unsigned long long *counters) {
+    constexpr bool F32 = sizeof(T) == 4;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const double g32 = (double)(dp + 8) * 0x1p-24;
+    const int64_t nchunks = (np + kPartnerChunk - 1) / kPartnerChunk;
     uint32_t ntests = 0, nkill = 0;
-    for (int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6); p < np; p += nw) {
-        const int32_t x = __builtin_amdgcn_readfirstlane(px[p]);
-        const int32_t y = __builtin_amdgcn_readfirstlane(py[p]);
-        const double d2 = pd2[p];
-        const float tf = __double2float_rd(d2 - d2 * g32);
-        bool dead = false;
-        for (int side = 0; side < (both ? 2 : 1) && !dead; ++side) {
-            // witnesses z near a (d(a,z) < d(x,y) proven by the rounded-up key),
-            // tested against the other end b
-            const int32_t a = side ? y : x, b = side ? x : y;
-            const int32_t z = wid[(int64_t)a * kPartnerWitnesses + lane];
-            const bool elig = z >= 0 && z != b && z != a && (double)wd2[(int64_t)a * kPartnerWitnesses + lane] < d2;
-            bool kill = false;
-            if (elig) {
-                ++ntests;
-                kill = F32 ? below(Xf + (int64_t)b * dp, Xf + (int64_t)z * dp, dp, tf)
-                           : below(Xd + (int64_t)b * dp, Xd + (int64_t)z * dp, dp, d2);
+    for (int64_t ch = blockIdx.x * 4 + (threadIdx.x >> 6); ch < nchunks; ch += nw) {
+        const int64_t p0 = ch * kPartnerChunk, p1 = p0 + kPartnerChunk < np ? p0 + kPartnerChunk : np;
+        int32_t cx = -1, z0 = -1;
+        float w0 = INFINITY;
+        T zr[KR];
+        for (int64_t p = p0; p < p1; ++p) {
+            const int32_t x = __builtin_amdgcn_readfirstlane(px[p]);
+            const int32_t y = __builtin_amdgcn_readfirstlane(py[p]);
+            const double d2 = pd2[p];
+            if (x != cx) {   // uniform
+                cx = x;
+                z0 = wid[(int64_t)x * kPartnerWitnesses + lane];
+                w0 = wd2[(int64_t)x * kPartnerWitnesses + lane];
+                const T *zrow = X + (int64_t)(z0 < 0 ? 0 : z0) * dp;
+#pragma unroll
+                for (int c = 0; c < KR; ++c) zr[c] = c < dp ? zrow[c] : T(0);
             }
-            dead = __ballot(kill) != 0;
-        }
-        if (lane == 0) {
-            alive[p] = dead ? 0 : 1;
-            nkill += dead;
+            const T t = F32 ? (T)__double2float_rd(d2 - d2 * g32) : (T)d2;
+            // x's partners against y
+            bool kill = false;
+            if (z0 >= 0 && z0 != y && (double)w0 < d2) {
+                ++ntests;
+                const T *yr = X + (int64_t)y * dp;
+                T acc = 0;
+                bool out = false;
+#pragma unroll
+                for (int c = 0; c < KR; c += 4) {
+                    if (c < dp && !out) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const T e = yr[c + u] - zr[c + u];
+                            acc = fma(e, e, acc);
+                        }
+                        if ((c & 4) && !(acc < t)) out = true;
+                    }
+                }
+                const T *zrow = X + (int64_t)z0 * dp;
+                for (int c = KR; c < dp && !out; c += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const T e = yr[c + u] - zrow[c + u];
+                        acc = fma(e, e, acc);
+                    }
+                    if (!(acc < t)) out = true;
+                }
+                kill = !out && acc < t;
+            }
+            bool dead = __ballot(kill) != 0;
+            if (!dead && both) {
+                // y's partners against x
+                const int32_t z1 = wid[(int64_t)y * kPartnerWitnesses + lane];
+                const float w1 = wd2[(int64_t)y * kPartnerWitnesses + lane];
+                bool kill1 = false;
+                if (z1 >= 0 && z1 != x && (double)w1 < d2) {
+                    ++ntests;
+                    kill1 = below(X + (int64_t)x * dp, X + (int64_t)z1 * dp, dp, t);
+                }
+                dead = __ballot(kill1) != 0;
+            }
+            if (lane == 0) {
+                alive[p] = dead ? 0 : 1;
+                nkill += dead;
+            }
         }
     }
     ntests = wave_sum(ntests);
@@ -1710,13 +1760,15 @@ void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const 
                             int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
                             bool both, uint8_t *alive, uint64_t *counters) {
     if (np == 0) return;
-    const int64_t grid = std::min<int64_t>(div_up(np, 4), 1 << 16);
-    if (Xf)
-        k_partner_witness<true><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, Xd, wid, wd2, both, alive,
-                                                               (unsigned long long *)counters);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(div_up(div_up(np, kPartnerChunk), 4), 4096));
+    unsigned long long *ctr = (unsigned long long *)counters;
+    if (Xf && dp <= 16)
+        k_partner_witness<float, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, alive, ctr);
+    else if (Xf)
+        k_partner_witness<float, 32><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, alive, ctr);
     else
-        k_partner_witness<false><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, Xd, wid, wd2, both, alive,
-                                                                (unsigned long long *)counters);
+        k_partner_witness<double, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xd, wid, wd2, both, alive,
+                                                                    ctr);
     GRNG_LAUNCHED();
 }
 
