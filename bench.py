@@ -55,6 +55,7 @@ KERNEL_SOURCES = {"k_pairs_tiled": ["k_rng.hip", "dev_util.h", "common.h"],
                   "k_pairs_bf16": ["k_pairs_bf16.hip", "dev_util.h", "common.h"],
                   "k_pair_masks": ["k_rng.hip", "dev_util.h", "common.h"],
                   "k_lune_guided": ["k_rng.hip", "dev_util.h", "common.h"],
+                  "k_partner_witness": ["k_rng.hip", "dev_util.h", "common.h"],
                   "k_vgrng_tiles": ["k_pivots.hip", "common.h"]}
 
 
@@ -141,6 +142,10 @@ def kernel_rooflines(st: dict, d: int, precision: int) -> dict:
                   (a subtraction and a fused multiply-add each), 4 d float32
                   flops, against the float32 VALU rate (the witness rows are
                   served from cache; HBM bytes are in 'traffic').
+    k_partner_witness  (with the top-64 selection before it, in ms_partner) one
+                  witness test = one squared distance of d coordinates, 3 d
+                  float32 flops (the other end's distance is known), against
+                  the float32 VALU rate.
     k_vgrng_tiles (min,max) product: 2 ops per (point, pivot j, witness k)
                   for each of two radius choices = 2 * vgrng_ops.
     k_pair_masks  one 1,120-byte record written per tile pair.
@@ -168,6 +173,11 @@ def kernel_rooflines(st: dict, d: int, precision: int) -> dict:
     if ms > 0:
         fl = st["lune_tests"] * 4.0 * d
         out["k_lune_guided"] = _entry("alu", fl / (ms / 1e3) / 1e12, MI355X_FP32_VALU_TFLOPS, "TFLOP/s", ms)
+    ms = st.get("ms_partner", 0.0)
+    if ms > 0:
+        fl = st["partner_tests"] * 3.0 * d
+        out["k_partner_witness"] = _entry("alu", fl / (ms / 1e3) / 1e12, MI355X_FP32_VALU_TFLOPS, "TFLOP/s", ms,
+                                          kills=st["partner_kills"])
     ms = st["ms_vgrng"]
     if ms > 0:
         ach = 2.0 * st["vgrng_ops"] / (ms / 1e3) / 1e12

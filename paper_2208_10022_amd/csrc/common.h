@@ -428,10 +428,11 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         uint64_t *work, uint64_t *counters);
 constexpr int kPartnerWitnesses = 64;   // nearest partners kept per row point
 // Stage V with the row's other candidates as witnesses: each row point's 64
-// nearest partners in a row-sorted pair list (off: row offsets), then a
+// nearest partners in a row-sorted pair list (off: row offsets) and, when
+// off2 is given, in the same pairs sorted by their second point; then a
 // proven-kill pass writing alive[p] (0: proven non-edge, 1: left to the scan).
 void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
-                        int32_t *wid, float *wd2);
+                        const int64_t *off2, const int32_t *py2, const double *pd22, int32_t *wid, float *wd2);
 void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
                             bool both, uint8_t *alive, uint64_t *counters);

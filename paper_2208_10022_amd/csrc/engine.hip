@@ -925,12 +925,27 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
         DevBuf wid, wd2;
         wid.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
         wd2.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
+        const bool self = X.Xh.p == S.Xh.p;
         EventTimer pt(s);
-        launch_partner_top(s, n, roff.as<int64_t>(), P.y.as<int32_t>(), P.d2.as<double>(), wid.as<int32_t>(),
-                           wd2.as<float>());
+        // One set: a point's partners are in its row and in its column.
+        DevBuf ccnt, coff, cx, cy, cd2;
+        if (self) {
+            ccnt.alloc(4 * (size_t)std::max<int64_t>(n + 1, 2));
+            zero(ccnt, s);
+            coff.alloc(8 * (size_t)(n + 1));
+            cx.alloc(4 * (size_t)np);
+            cy.alloc(4 * (size_t)np);
+            cd2.alloc(8 * (size_t)np);
+            launch_pairs_sort_rows(s, np, P.y.as<int32_t>(), P.x.as<int32_t>(), P.d2.as<double>(), n,
+                                   ccnt.as<int32_t>(), coff.as<int64_t>(), cx.as<int32_t>(), cy.as<int32_t>(),
+                                   cd2.as<double>());
+        }
+        launch_partner_top(s, n, roff.as<int64_t>(), P.y.as<int32_t>(), P.d2.as<double>(),
+                           self ? coff.as<int64_t>() : nullptr, self ? cy.as<int32_t>() : nullptr,
+                           self ? cd2.as<double>() : nullptr, wid.as<int32_t>(), wd2.as<float>());
         launch_partner_witness(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp,
                                f32 ? S.Xf.as<float>() : nullptr, S.Xh.as<double>(), wid.as<int32_t>(),
-                               wd2.as<float>(), X.Xh.p == S.Xh.p, alive.as<uint8_t>(), ctr);
+                               wd2.as<float>(), self, alive.as<uint8_t>(), ctr);
         const double ms = pt.stop();
         bt.partner += ms;
         trace("Stage V on partner witnesses", ms, np);

@@ -974,32 +974,44 @@ __device__ inline uint64_t wave_merge_u64(uint64_t k) {
     return k;
 }
 
-// The kPartnerWitnesses (64) nearest partners of each row point (rows of the list sorted
-// by row point, row r at [off[r], off[r+1])): key = float32 d^2 rounded up
-// (an upper bound; bit patterns of non-negative floats order as integers),
-// then the partner's index.  One wave per row, 64 entries per step merged
-// into the running best 64.  Unused slots: id -1, d^2 +inf.
+// The kPartnerWitnesses (64) nearest partners of each row point: in the list
+// sorted by row point (row r at [off[r], off[r+1])) and, when given, in the
+// same pairs sorted by their other point (off2, py2, pd22: the pairs where r
+// is the second point).  Key = float32 d^2 rounded up (an upper bound; bit
+// patterns of non-negative floats order as integers), then the partner's
+// index.  One wave per row, 64 entries per step merged into the running best
+// 64.  Unused slots: id -1, d^2 +inf.
 __global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ py, const double *__restrict__ pd2,
-                                                     int32_t *__restrict__ wid, float *__restrict__ wd2) {
+                                                     const int64_t *__restrict__ off2,
+                                                     const int32_t *__restrict__ py2,
+                                                     const double *__restrict__ pd22, int32_t *__restrict__ wid,
+                                                     float *__restrict__ wd2) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += nw) {
-        const int64_t b = off[r], e = off[r + 1];
         uint64_t best = ~0ull;
-        for (int64_t c0 = b; c0 < e; c0 += 64) {
-            const int64_t i = c0 + lane;
-            uint64_t k = ~0ull;
-            if (i < e) k = ((uint64_t)__float_as_uint(__double2float_ru(pd2[i])) << 32) | (uint32_t)py[i];
-            k = wave_sort_u64(k);
-            if (c0 == b) {
-                best = k;
-                continue;
+        bool first = true;
+        for (int src = 0; src < (off2 ? 2 : 1); ++src) {
+            const int64_t *o = src ? off2 : off;
+            const int32_t *ids = src ? py2 : py;
+            const double *dd = src ? pd22 : pd2;
+            const int64_t b = o[r], e = o[r + 1];
+            for (int64_t c0 = b; c0 < e; c0 += 64) {
+                const int64_t i = c0 + lane;
+                uint64_t k = ~0ull;
+                if (i < e) k = ((uint64_t)__float_as_uint(__double2float_ru(dd[i])) << 32) | (uint32_t)ids[i];
+                k = wave_sort_u64(k);
+                if (first) {
+                    best = k;
+                    first = false;
+                    continue;
+                }
+                // best and k ascending: the lane-wise min of best and k reversed
+                // holds the 64 smallest of both, as a bitonic sequence
+                const uint64_t rk = shfl_u64(k, 63 - lane);
+                best = wave_merge_u64(rk < best ? rk : best);
             }
-            // best and k ascending: the lane-wise min of best and k reversed
-            // holds the 64 smallest of both, as a bitonic sequence
-            const uint64_t rk = shfl_u64(k, 63 - lane);
-            best = wave_merge_u64(rk < best ? rk : best);
         }
         const bool none = best == ~0ull;
         wid[r * kPartnerWitnesses + lane] = none ? -1 : (int32_t)(uint32_t)best;
@@ -1749,10 +1761,10 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
 }
 
 void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
-                        int32_t *wid, float *wd2) {
+                        const int64_t *off2, const int32_t *py2, const double *pd22, int32_t *wid, float *wd2) {
     if (nrows == 0) return;
     const int64_t grid = std::min<int64_t>(div_up(nrows, 4), 1 << 16);
-    k_partner_top<<<(unsigned)grid, 256, 0, s>>>(nrows, off, py, pd2, wid, wd2);
+    k_partner_top<<<(unsigned)grid, 256, 0, s>>>(nrows, off, py, pd2, off2, py2, pd22, wid, wd2);
     GRNG_LAUNCHED();
 }
 
