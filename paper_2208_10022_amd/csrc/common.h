@@ -245,8 +245,8 @@ void launch_mlp_score(hipStream_t s, const uint16_t *wb, const float *feats, int
 int64_t launch_log_cells(hipStream_t s, int64_t nsamp, int64_t npairs, const int32_t *px, const int32_t *py,
                          const double *pd2, int dp, const double *Xh, const double *nrmh, const int32_t *grp_off,
                          const double *dvor, const double *rad, const double *Xp, const double *nrmp,
-                         const int64_t *rel_off, const int32_t *rel_grp, const double *rel_d2x, float *feats,
-                         uint8_t *labels, int64_t capacity);
+                         const int64_t *rel_off, const int32_t *rel_grp, const double *rel_d2x,
+                         const uint64_t *row_dmax, float *feats, uint8_t *labels, int64_t capacity);
 
 // State of the last build's exhaustive scan, kept for logging training samples.
 struct ExhaustiveState {
@@ -254,6 +254,7 @@ struct ExhaustiveState {
     int64_t np = 0;
     DevBuf x, y, d2;               // pairs sorted by row point
     DevBuf rel_off, rel_grp, rel_d2x;
+    DevBuf row_dmax;               // uint64 [n]: the d^2 bound the rows' cell lists were formed for
 };
 
 }  // namespace grng
@@ -436,6 +437,10 @@ void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const 
 void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
                             bool both, uint8_t *alive, uint64_t *counters);
+// Per row of a row-sorted pair list, the largest d^2 of its pairs with
+// alive[p] != 0 (0 when there is none), as float64 bits.
+void launch_live_dmax(hipStream_t s, int64_t nrows, const int64_t *off, const double *pd2, const uint8_t *alive,
+                      uint64_t *dmax_bits);
 void launch_lune_all(hipStream_t s, int64_t npairs, const int32_t *px, const int32_t *py, const double *pd2,
                      int64_t n, int dp, const double *Xx, const double *nrmx, const double *X, const double *nrm,
                      int64_t z_from, int metric, int graph, int beta_q, int grid_exp, uint8_t *alive,

@@ -950,22 +950,30 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
         bt.partner += ms;
         trace("Stage V on partner witnesses", ms, np);
     }
+    // The rows' witness cells are those of their live pairs.
+    DevBuf ldmax;
+    const uint64_t *row_dmax = dmax.as<uint64_t>();
+    if (prekilled) {
+        ldmax.alloc(8 * (size_t)std::max<int64_t>(n, 1));
+        launch_live_dmax(s, n, roff.as<int64_t>(), P.d2.as<double>(), alive.as<uint8_t>(), ldmax.as<uint64_t>());
+        row_dmax = ldmax.as<uint64_t>();
+    }
     DevBuf rel_cnt, rel_off, rel_grp, rel_d2x;
     rel_cnt.alloc(4 * (size_t)n);
     rel_off.alloc(8 * (size_t)(n + 1));
     // Nearest witness cells first, except in Stage VII, whose cells hold only
     // the inserted points (a few each): there the order is pivot order.
     const bool sort = zstart == nullptr;
-    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter,
-                           dmax.as<uint64_t>(), nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr, ctr, sort);
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter, row_dmax,
+                           nullptr, rel_cnt.as<int32_t>(), nullptr, nullptr, ctr, sort);
     launch_scan_i32_to_i64(s, rel_cnt.as<int32_t>(), n, rel_off.as<int64_t>());
     std::vector<int64_t> tot;
     d2h(tot, rel_off.as<int64_t>() + n, 1, s);
     rel_grp.alloc(4 * (size_t)std::max<int64_t>(tot[0], 1));
     rel_d2x.alloc(8 * (size_t)std::max<int64_t>(tot[0], 1));
-    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter,
-                           dmax.as<uint64_t>(), rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(),
-                           rel_d2x.as<double>(), ctr, sort);
+    launch_relevant_groups(s, n, m, X.perm.as<int32_t>(), X.dxp.as<double>(), crad, cell_filter, row_dmax,
+                           rel_off.as<int64_t>(), rel_cnt.as<int32_t>(), rel_grp.as<int32_t>(), rel_d2x.as<double>(),
+                           ctr, sort);
     EventTimer lt(s);
     launch_lune_guided(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp, X.Xh.as<double>(),
                        X.nrmh.as<double>(), S.Xh.as<double>(), S.nrmh.as<double>(), S.n, S.dhome.as<double>(),
@@ -988,6 +996,12 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
         keep->rel_off = std::move(rel_off);
         keep->rel_grp = std::move(rel_grp);
         keep->rel_d2x = std::move(rel_d2x);
+        if (prekilled) {
+            keep->row_dmax = std::move(ldmax);
+        } else {
+            keep->row_dmax.alloc(8 * (size_t)std::max<int64_t>(n, 1));
+            GRNG_HIP(hipMemcpyAsync(keep->row_dmax.p, dmax.p, 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        }
     }
 }
 
@@ -1605,7 +1619,7 @@ void do_log_cells(grng_index *idx, int64_t max_pairs, float *feats, uint8_t *lab
                               ps.Xh.as<double>(), ps.nrmh.as<double>(), ps.grp_off.as<int32_t>(),
                               ps.dvor.as<double>(), idx->layers.back().rad.as<double>(), idx->aux.Xp.as<double>(),
                               idx->aux.nrmp.as<double>(), ex.rel_off.as<int64_t>(), ex.rel_grp.as<int32_t>(),
-                              ex.rel_d2x.as<double>(), feats, labels, capacity);
+                              ex.rel_d2x.as<double>(), ex.row_dmax.as<uint64_t>(), feats, labels, capacity);
     if (*count > capacity) throw Error(GRNG_ECAPACITY, "sample buffer too small");
 }
 

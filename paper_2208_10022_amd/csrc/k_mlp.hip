@@ -171,8 +171,9 @@ __global__ __launch_bounds__(256) void k_log_cells(
     const double *__restrict__ pd2, int dp, const double *__restrict__ Xh, const double *__restrict__ nrmh,
     const int32_t *__restrict__ grp_off, const double *__restrict__ dvor, const double *__restrict__ rad,
     const double *__restrict__ Xp, const double *__restrict__ nrmp, const int64_t *__restrict__ rel_off,
-    const int32_t *__restrict__ rel_grp, const double *__restrict__ rel_d2x, int64_t *__restrict__ cnt,
-    const int64_t *__restrict__ off, float *__restrict__ feats, uint8_t *__restrict__ labels, int pass) {
+    const int32_t *__restrict__ rel_grp, const double *__restrict__ rel_d2x, const uint64_t *__restrict__ row_dmax,
+    int64_t *__restrict__ cnt, const int64_t *__restrict__ off, float *__restrict__ feats,
+    uint8_t *__restrict__ labels, int pass) {
     const int lane = threadIdx.x & 63;
     const int64_t s = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (s >= nsamp) return;
@@ -181,7 +182,9 @@ __global__ __launch_bounds__(256) void k_log_cells(
     const int64_t y = __builtin_amdgcn_readfirstlane(py[p]);
     const double d2 = pd2[p];
     int64_t slot = pass ? off[s] : 0;
-    if (d2 <= 0.0) {
+    // a pair beyond its row's cell bound (one the partner pass decided)
+    // would see only part of its cells: not a sample
+    if (d2 <= 0.0 || d2 > __longlong_as_double((long long)row_dmax[x])) {
         if (!pass && lane == 0) cnt[s] = 0;
         return;
     }
@@ -311,15 +314,15 @@ void launch_mlp_score(hipStream_t s, const uint16_t *wb, const float *feats, int
 int64_t launch_log_cells(hipStream_t s, int64_t nsamp, int64_t npairs, const int32_t *px, const int32_t *py,
                          const double *pd2, int dp, const double *Xh, const double *nrmh, const int32_t *grp_off,
                          const double *dvor, const double *rad, const double *Xp, const double *nrmp,
-                         const int64_t *rel_off, const int32_t *rel_grp, const double *rel_d2x, float *feats,
-                         uint8_t *labels, int64_t capacity) {
+                         const int64_t *rel_off, const int32_t *rel_grp, const double *rel_d2x,
+                         const uint64_t *row_dmax, float *feats, uint8_t *labels, int64_t capacity) {
     if (nsamp == 0 || npairs == 0) return 0;
     DevBuf cnt, off;
     cnt.alloc(sizeof(int64_t) * (size_t)nsamp);
     off.alloc(sizeof(int64_t) * (size_t)(nsamp + 1));
     const unsigned grid = (unsigned)div_up(nsamp, 4);
     k_log_cells<<<grid, 256, 0, s>>>(nsamp, npairs, px, py, pd2, dp, Xh, nrmh, grp_off, dvor, rad, Xp, nrmp, rel_off,
-                                     rel_grp, rel_d2x, cnt.as<int64_t>(), nullptr, nullptr, nullptr, 0);
+                                     rel_grp, rel_d2x, row_dmax, cnt.as<int64_t>(), nullptr, nullptr, nullptr, 0);
     GRNG_LAUNCHED();
     launch_scan_i64(s, cnt.as<int64_t>(), nsamp, off.as<int64_t>());
     int64_t total = 0;
@@ -327,7 +330,7 @@ int64_t launch_log_cells(hipStream_t s, int64_t nsamp, int64_t npairs, const int
     GRNG_HIP(hipStreamSynchronize(s));
     if (total > capacity || total == 0) return total;
     k_log_cells<<<grid, 256, 0, s>>>(nsamp, npairs, px, py, pd2, dp, Xh, nrmh, grp_off, dvor, rad, Xp, nrmp, rel_off,
-                                     rel_grp, rel_d2x, nullptr, off.as<int64_t>(), feats, labels, 1);
+                                     rel_grp, rel_d2x, row_dmax, nullptr, off.as<int64_t>(), feats, labels, 1);
     GRNG_LAUNCHED();
     GRNG_HIP(hipStreamSynchronize(s));
     return total;

@@ -1019,6 +1019,22 @@ __global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_
     }
 }
 
+// Largest d^2 of each row's pairs that the partner pass left (0 for none):
+// the witness cells a row needs shrink to those of its live pairs.
+__global__ __launch_bounds__(256) void k_live_dmax(int64_t nrows, const int64_t *__restrict__ off,
+                                                   const double *__restrict__ pd2, const uint8_t *__restrict__ alive,
+                                                   uint64_t *__restrict__ dmax_bits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += nw) {
+        double mx = 0.0;
+        for (int64_t i = off[r] + lane; i < off[r + 1]; i += 64)
+            if (alive[i]) mx = fmax(mx, pd2[i]);
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+        if (lane == 0) dmax_bits[r] = (uint64_t)__double_as_longlong(mx);
+    }
+}
+
 // d^2(a, b) < t proven on rows of dp values (early exit once a partial sum
 // reaches t: partial sums only grow).  Float32 rows: the direct-form sum's
 // relative error is below (dp+2) 2^-24, so t is the pair's d^2 lowered by
@@ -1781,6 +1797,14 @@ void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const 
     else
         k_partner_witness<double, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xd, wid, wd2, both, alive,
                                                                     ctr);
+    GRNG_LAUNCHED();
+}
+
+void launch_live_dmax(hipStream_t s, int64_t nrows, const int64_t *off, const double *pd2, const uint8_t *alive,
+                      uint64_t *dmax_bits) {
+    if (nrows == 0) return;
+    k_live_dmax<<<(unsigned)std::min<int64_t>(div_up(nrows, 4), 1 << 16), 256, 0, s>>>(nrows, off, pd2, alive,
+                                                                                        dmax_bits);
     GRNG_LAUNCHED();
 }
 
