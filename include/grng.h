@@ -142,8 +142,9 @@ typedef struct grng_stats {
                                      4,096 entries sorted on chip, and was scanned in pivot order */
     double distance_computations; /* squared distances produced (the paper's cost unit, Section 1): every
                                      point-pivot entry, every entry of the pair kernel's distance tiles
-                                     (D(T,U), the pivot blocks, D(T,T), D(U,U) when computed) and two per
-                                     witness test of the exhaustive scan (plus one per witness cell's pivot) */
+                                     (D(T,U), the pivot blocks, D(T,T), D(U,U) when computed), one per
+                                     partner-pass test, and two per witness test of the exhaustive scan
+                                     (plus one per witness cell's pivot) */
     double witness_tests;         /* (pair, witness) lune predicates evaluated, pivots included */
     double candidate_pairs;       /* pairs left after Stages I-III (Theorem 1, Propositions 1-2) */
     double stage4_survivors;      /* pairs left after pivot witnesses (Stage IV) */
