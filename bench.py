@@ -284,8 +284,9 @@ def parse():
     ap.add_argument("--workload", default="subspace3",
                     choices=["subspace3", "clustered", "clustered96", "insert", "hierarchy", "pivots"])
     ap.add_argument("--precision", type=int, default=-1, help="0 = float64 everywhere, 1 = float32 screens "
-                    "(the plain float32 form), 2 = bf16 tiles; -1 = the workload's form (2 for subspace3, "
-                    "else 1)")
+                    "(the plain float32 form), 2 = bf16 tiles, 3 = float32 screens with the pair kernel's tile "
+                    "shape (float64 or bf16 tiles) chosen by the autotuner; -1 = the workload's form (3 for "
+                    "subspace3, else 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the comparison builds of the other forms")
     ap.add_argument("--form-warmup", type=int, default=1, help="untimed builds before each form's timed one")
@@ -429,7 +430,10 @@ def main():
 
     import paper_2208_10022_amd as P
 
-    prec = args.precision if args.precision >= 0 else (2 if args.workload == "subspace3" else 1)
+    # 1M x 32-D: the autotuner picks the pair kernel's tile shape (float64 or
+    # split bf16 MFMA tiles) with the witness-pivot counts
+    auto = args.precision == 3 or (args.precision < 0 and args.workload == "subspace3")
+    prec = 3 if auto else (args.precision if args.precision >= 0 else 1)
     W, desc = workload_of(args.workload)
     scorer, train = None, None
     if args.workload == "clustered96":
@@ -452,6 +456,7 @@ def main():
     wall = time.perf_counter() - t_start
     ms = float(np.median(times))
     st = b.idx.stats()
+    prec = int(st["precision_used"])   # the form that ran (the tuner's choice under automatic precision)
     E = b.idx.edges().cpu().numpy()
     queries = query_throughput(b.idx, W, args.queries) if args.workload == "clustered" and args.queries else None
     b.idx.close()
@@ -496,7 +501,9 @@ def main():
         "dtype": PRECISION_DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": desc, "n": W.n, "d": W.d, "pivots": sizes if len(sizes) > 1 else sizes[0],
-                   "grid_exp": W.q, "precision": PRECISION_NAMES[prec]},
+                   "grid_exp": W.q, "precision": PRECISION_NAMES[prec] + (
+                       " (tile shape chosen by the autotuner)" if auto and args.autotune else
+                       " (tile shape chosen from the padded dimension)" if auto else "")},
         "edges": int(st["n_edges"]),
         "forms": forms,
         "witness_tests": st["witness_tests"],

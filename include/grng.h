@@ -69,11 +69,16 @@ typedef enum grng_status {
 enum {
     GRNG_PREC_FP64 = 0, /* exact float64 squared distance for every witness test */
     GRNG_PREC_FP32 = 1, /* float32 rows with an error-bounded screen; undecided tests are recomputed in float64 */
-    GRNG_PREC_BF16 = 2  /* GRNG_PREC_FP32, but the pair kernel's distance tiles come from bf16 MFMA with
+    GRNG_PREC_BF16 = 2, /* GRNG_PREC_FP32, but the pair kernel's distance tiles come from bf16 MFMA with
                            float32 accumulation on cell-centred coordinates split into two bf16 parts
                            (three products per tile), with a per-tile error bound; a certificate kills a
                            pair only outside the bound, and pairs within it go on to the exhaustive scan,
                            which re-decides them exactly */
+    GRNG_PREC_AUTO = 3  /* GRNG_PREC_FP32 or GRNG_PREC_BF16, i.e. the pair kernel's tile shape (float64
+                           16x16x4 MFMA tiles or split bf16 16x16x32 tiles), chosen per index: by trial
+                           builds of the autotuner when autotune = 1, else bf16 from a padded dimension
+                           of 32 (one bf16 MFMA step; below it half of each step is padding).  Both give
+                           the same edges; stats.precision_used tells which ran */
 };
 
 enum {
@@ -92,9 +97,10 @@ typedef struct grng_options {
     int32_t use_graph;     /* must be 0: graph capture is not implemented (grng_create returns GRNG_EINVAL
                               for any other value) */
     int32_t autotune;      /* 1: the first grng_build_rng with a pivot layer times complete builds over a
-                              small set of witness-pivot counts (vgrng_pivots, then stage4_pivots) and
-                              keeps the fastest for later builds, insertions and queries of this index;
-                              0: use the two fields below */
+                              small set of choices (with GRNG_PREC_AUTO the pair kernel's tile shape first,
+                              then the witness-pivot counts vgrng_pivots and stage4_pivots) and keeps the
+                              fastest for later builds, insertions and queries of this index; 0: use the
+                              fields below */
     int32_t stage4_pivots; /* pivot witnesses tested per pair before the exhaustive scan: 0 = default (16), 1..16 */
     int32_t vgrng_pivots;  /* Proposition 1 witnesses per 64-point block: the pivots nearest the block's home
                               cell, 0 = default (256), values >= the layer size use every pivot.  Any subset
@@ -187,6 +193,7 @@ typedef struct grng_stats {
     double partner_kills;         /* of exhaustive_pairs, those this pass proved non-edges (the exhaustive
                                      scan skips them) */
     double ms_partner;            /* device time of that pass in the last build */
+    int64_t precision_used;       /* GRNG_PREC_* form in effect (the autotuner's choice under GRNG_PREC_AUTO) */
 } grng_stats;
 
 /* ABI version the library was built with (GRNG_ABI_VERSION). */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgrng.so")
 GRNG_OK, GRNG_ECAPACITY = 0, -5
 STATUS_NAMES = {0: "GRNG_OK", -1: "GRNG_EINVAL", -2: "GRNG_ENOMEM", -3: "GRNG_EDEVICE", -4: "GRNG_ENOTGRID",
                 -5: "GRNG_ECAPACITY", -6: "GRNG_ESTATE"}
-PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16, PREC_AUTO = 0, 1, 2, 3
 ORDER_DISTANCE, ORDER_LEARNED, ORDER_LUNE = 0, 1, 2
 METRIC_L2, METRIC_L1, METRIC_LINF = 0, 1, 2
 GRAPH_RNG, GRAPH_GABRIEL, GRAPH_BETA = 0, 1, 2
@@ -57,7 +57,7 @@ class Stats(C.Structure):
                 ("ms_pair_masks", C.c_double), ("screen_uncertain", C.c_double),
                 ("pair_tile_entries", C.c_double), ("pair_method_distances", C.c_double),
                 ("lune_tests_kept", C.c_double), ("partner_tests", C.c_double), ("partner_kills", C.c_double),
-                ("ms_partner", C.c_double)]
+                ("ms_partner", C.c_double), ("precision_used", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

@@ -279,6 +279,7 @@ struct grng_index {
     grng::DevBuf scorer;       // uint16 [kMlpParams] bf16 scorer weights (learned order)
     int32_t tuned_kw = 0;      // Proposition 1 witness pivots chosen by the autotuner (0: not tuned)
     int32_t tuned_k4 = 0;      // Stage IV pivot witnesses chosen by the autotuner (0: not tuned)
+    int32_t tuned_prec = -1;   // GRNG_PREC_AUTO: the form chosen by the autotuner (-1: not tuned)
     double ms_tune = 0;        // device time the autotuner spent
     grng_stats stats{};
 };

@@ -47,6 +47,15 @@ int32_t stage4_pivots(const grng_index *idx) {
     return idx->tuned_k4 > 0 ? idx->tuned_k4 : (idx->opt.stage4_pivots > 0 ? idx->opt.stage4_pivots : kDefaultK);
 }
 
+// Arithmetic form in effect: the option, or under GRNG_PREC_AUTO the
+// autotuner's choice of the pair kernel's tiles, else bf16 tiles from a
+// padded dimension of 32 (one bf16 MFMA step deep).
+int32_t precision(const grng_index *idx) {
+    if (idx->opt.precision != GRNG_PREC_AUTO) return idx->opt.precision;
+    if (idx->tuned_prec >= 0) return idx->tuned_prec;
+    return idx->dp >= 32 ? GRNG_PREC_BF16 : GRNG_PREC_FP32;
+}
+
 struct EventTimer {
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s;
@@ -87,7 +96,7 @@ void zero(DevBuf &b, hipStream_t s) { launch_fill_u64(s, b.as<uint64_t>(), (int6
 void check_opts(const grng_options *o) {
     require(o != nullptr, GRNG_EINVAL, "options pointer is NULL");
     require(o->grid_exp >= 0 && o->grid_exp <= 60, GRNG_EINVAL, "grid_exp must be in [0, 60]");
-    require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_BF16, GRNG_EINVAL, "unknown precision");
+    require(o->precision >= GRNG_PREC_FP64 && o->precision <= GRNG_PREC_AUTO, GRNG_EINVAL, "unknown precision");
     require(o->witness_order == GRNG_ORDER_DISTANCE || o->witness_order == GRNG_ORDER_LEARNED ||
                 o->witness_order == GRNG_ORDER_LUNE, GRNG_EINVAL,
             "unknown witness order");
@@ -835,7 +844,7 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
     // Tile-pair records (bounds, pivot ids and candidate masks), written by
     // the mask pass and streamed by the pair kernel, in chunks of at most
     // 2^21 tile pairs (2.3 GB).
-    const bool bf16 = idx->opt.precision == GRNG_PREC_BF16;
+    const bool bf16 = precision(idx) == GRNG_PREC_BF16;
     const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 21);
     DevBuf rec;
     rec.alloc(8 * (size_t)kPairRecordWords * (size_t)std::max<int64_t>(chunk, 1));
@@ -914,7 +923,7 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
         P.y = std::move(sy);
         P.d2 = std::move(sd2);
     }
-    const bool f32 = idx->opt.precision != GRNG_PREC_FP64;
+    const bool f32 = precision(idx) != GRNG_PREC_FP64;
     alive.alloc((size_t)std::max<int64_t>(np, 8));
     // Stage V with the row's other candidates as witnesses: each pair against
     // the nearest partners of its ends in this list (both ends when they are
@@ -1049,7 +1058,8 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     // Bytes a witness test reads: the witness row and its cell-distance
     // bound (float32 with the float32 screen, float64 otherwise); a test
     // that ends early on a partial sum reads less.
-    idx->stats.lune_bytes = (double)c[C_LUNE] * (idx->opt.precision == GRNG_PREC_FP64 ? 8.0 * idx->dp + 8.0
+    idx->stats.precision_used = precision(idx);
+    idx->stats.lune_bytes = (double)c[C_LUNE] * (precision(idx) == GRNG_PREC_FP64 ? 8.0 * idx->dp + 8.0
                                                                                      : 4.0 * idx->dp + 4.0);
     const double m = idx->layers.empty() ? 0.0 : (double)idx->layers.back().m;
     idx->stats.vgrng_ops = 2.0 * (double)idx->n * m * (double)idx->aux.kw;
@@ -1064,9 +1074,10 @@ void fill_build_stats(grng_index *idx, const BuildTimes &bt) {
     }
 }
 
-// Autotuner: complete guided builds (results discarded) over candidate
-// witness-pivot counts, coordinate-wise: Proposition 1 witnesses per block
-// first, then Stage IV pivots; the fastest device time wins.  Every
+// Autotuner: complete guided builds (results discarded), coordinate-wise:
+// under GRNG_PREC_AUTO the pair kernel's tile shape (float64 16x16x4 or
+// split bf16 16x16x32 MFMA tiles) first, then Proposition 1 witnesses per
+// block, then Stage IV pivots; the fastest device time wins.  Every
 // candidate gives the same edges, so only speed is compared.
 void autotune(grng_index *idx) {
     const int64_t m = idx->layers.back().m;
@@ -1085,6 +1096,17 @@ void autotune(grng_index *idx) {
     for (int64_t k = 64; k < m && k <= 1024; k *= 2) kws.push_back((int32_t)k);
     if (m <= 2048) kws.push_back((int32_t)m);
     double best = INFINITY, spent = 0;
+    if (idx->opt.precision == GRNG_PREC_AUTO) {
+        int32_t best_p = GRNG_PREC_FP32;
+        for (int32_t p : {GRNG_PREC_FP32, GRNG_PREC_BF16}) {
+            idx->tuned_prec = p;
+            const double ms = trial();
+            spent += ms;
+            trace("autotune tile shape", ms, p);
+            if (ms < best) { best = ms; best_p = p; }
+        }
+        idx->tuned_prec = best_p;
+    }
     int32_t best_kw = vgrng_pivots(idx, m);
     idx->tuned_k4 = stage4_pivots(idx);
     for (int32_t kw : kws) {

@@ -158,6 +158,31 @@ def test_autotune_keeps_edges_and_tunes_once(G):
     idx.close()
 
 
+def test_autotune_chooses_the_tile_shape(G):
+    """GRNG_PREC_AUTO: the autotuner times the float64-tile and the bf16-tile
+    forms and keeps one; without the autotuner the padded dimension decides."""
+    say("automatic tile shape, subspace n=6000 d=32")
+    W = synth.subspace_layers(6000, ms=(30, 240))
+    want = native.rng_edges(W.X, W.q)
+    idx = G.Index(to_dev(W.X), grid_exp=W.q, precision=G.PREC_AUTO, autotune=1)
+    for l, L in enumerate(W.layers):
+        idx.build_grng_layer(l, to_dev(L.pivot_ids), to_dev(L.radii))
+    idx.build_rng()
+    st = idx.stats()
+    assert st["precision_used"] in (G.PREC_FP32, G.PREC_BF16) and st["ms_autotune"] > 0
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), want)
+    idx.build_rng()   # the choice is kept
+    assert idx.stats()["precision_used"] == st["precision_used"]
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), want)
+    idx.close()
+    W16 = synth.clustered(n=2000, d=16, clusters=8, m=40, knn=40)
+    for X, q, d_used in ((W.X, W.q, G.PREC_BF16), (W16.X, W16.q, G.PREC_FP32)):
+        idx = G.Index(to_dev(X), grid_exp=q, precision=G.PREC_AUTO)
+        idx.build_rng()   # no layer: the exhaustive path, form from the padded dimension
+        assert idx.stats()["precision_used"] == d_used
+        idx.close()
+
+
 @pytest.mark.parametrize("prec", PRECISIONS)
 def test_degenerate_inputs(G, prec):
     say("degenerate inputs precision", prec)
