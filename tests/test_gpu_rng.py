@@ -158,6 +158,25 @@ def test_autotune_keeps_edges_and_tunes_once(G):
     idx.close()
 
 
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_partner_pass_only_removes_non_edges(G, prec):
+    """Stage V with the row's other candidates: every pair it removes is a
+    non-edge (the edge set stays the oracle's), and it removes most of them."""
+    say("partner pass, clustered n=3000, precision", prec)
+    W = synth.clustered(n=3000, d=16, clusters=8, m=60, knn=40)
+    L = W.layers[0]
+    idx = G.Index(to_dev(W.X), grid_exp=W.q, precision=prec)
+    idx.build_grng_layer(0, to_dev(L.pivot_ids), to_dev(L.radii))
+    idx.build_rng()
+    st = idx.stats()
+    assert np.array_equal(idx.edges().cpu().numpy().astype(np.int64), golden_edges("clustered_n3000_d16_rng_edges.txt"))
+    left = st["exhaustive_pairs"] - st["partner_kills"]
+    assert st["n_edges"] <= left   # the edges are among the pairs the scan decides
+    assert st["partner_kills"] > 0.5 * (st["exhaustive_pairs"] - st["n_edges"])
+    assert st["partner_tests"] > 0 and st["ms_partner"] > 0
+    idx.close()
+
+
 def test_autotune_chooses_the_tile_shape(G):
     """GRNG_PREC_AUTO: the autotuner times the float64-tile and the bf16-tile
     forms and keeps one; without the autotuner the padded dimension decides."""
