@@ -843,11 +843,12 @@ void run_pairs(grng_index *idx, const Layer &L, const LayerAux &aux, const Point
                      vb = view_of(B, ins ? B.perm.as<int32_t>() : nullptr, ins ? (int32_t)(B.n - A.n) : 0, with_new);
     // Tile-pair records (bounds, pivot ids and candidate masks), written by
     // the mask pass and streamed by the pair kernel, in chunks of at most
-    // 2^23 tile pairs (9.4 GB): the pair kernel's workgroups drain unevenly
-    // at the end of each launch, so fewer, longer launches run faster
-    // (records chunks that fit the last-level cache were slower still).
+    // 2^21 tile pairs (2.3 GB).  Chunks that fit the last-level cache run
+    // slower (the pair kernel's workgroups drain unevenly at the end of each
+    // launch); 4x larger ones gain under 1% in a build but cost insertions
+    // a fresh multi-GB allocation whenever their tile-pair count changes.
     const bool bf16 = precision(idx) == GRNG_PREC_BF16;
-    const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 23);
+    const int64_t chunk = std::min<int64_t>(ntp, (int64_t)1 << 21);
     DevBuf rec;
     rec.alloc(8 * (size_t)kPairRecordWords * (size_t)std::max<int64_t>(chunk, 1));
     for (int attempt = 0; attempt < 3; ++attempt) {
