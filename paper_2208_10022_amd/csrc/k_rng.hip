@@ -9,7 +9,8 @@
 //                 Propositions 1-2), and if the home cells of x and y survive
 //                 the same virtual-pivot test with cell radii;
 //   Stage IV      pivots as witnesses;
-//   Stage V       the points of the pair's two tiles as witnesses;
+//   Stage V       the points of the pair's two tiles as witnesses, then the
+//                 nearest other candidates of each end (partner pass);
 //   Stage VI      exhaustive scan over points grouped by home cell, skipping a
 //                 whole cell when max(d(x,p), d(y,p)) - radius(p) >= d(x,y)
 //                 (Proposition 3) and a single point z of the cell when
@@ -23,9 +24,10 @@
 // zero-padded float64 rows of dp values and their exact float32 copies.
 // Stages I-III run in k_pair_masks (one wave per 64 x 64 tile pair, writing
 // a record); Stages IV-V in k_pairs_tiled (one workgroup per tile pair at a
-// time, tiles in LDS); Stage VI in k_lune_guided (one wave per surviving
-// pair, 64 lanes streaming witnesses, a wave ballot ends the scan at the
-// first witness).
+// time, tiles in LDS), the partner pass in k_partner_top / k_partner_witness
+// (64 partner witnesses per wave); Stage VI in k_lune_guided (one wave per
+// surviving pair, 64 lanes streaming witnesses, a wave ballot ends the scan
+// at the first witness).
 #include <algorithm>
 
 #include "common.h"
