@@ -87,7 +87,7 @@ def test_unimplemented_options_are_rejected(L):
     silently running something else."""
     lib = L.lib()
     h = C.c_void_p()
-    for kw in ({"use_graph": 1}, {"graph": 3}, {"graph": 2, "beta_quarters": 3}, {"graph": 2, "beta_quarters": 65},
+    for kw in ({"use_graph": 1}, {"precision": 4}, {"precision": -1}, {"graph": 3}, {"graph": 2, "beta_quarters": 3}, {"graph": 2, "beta_quarters": 65},
                {"graph": 0, "beta_quarters": 8}, {"graph": 1, "beta_quarters": 4},
                {"graph": 2, "beta_quarters": 8, "metric": 1}):
         opt = L.Options(grid_exp=3, **kw)
