@@ -21,6 +21,7 @@ def _stats():
         "pair_tile_entries": 1000 * (4096 + 128 * 16) + 600 * 4096,
         "ms_lune": 5.0, "lune_tests": 1e9,
         "ms_pair_masks": 1.0, "tile_pairs": 1000,
+        "ms_partner": 0.5, "partner_tests": 1e8, "partner_kills": 5e5,
     }
 
 
@@ -41,6 +42,9 @@ def test_roofline_fractions_follow_from_the_counts():
     assert p["dense_tile_tflop_s"] == pytest.approx(st["pair_tile_entries"] * 2 * 16 / 1e-2 / 1e12)
     lu = ks["k_lune_guided"]
     assert lu["bound"] == "alu" and lu["achieved"] == pytest.approx(1e9 * 4 * d / 5e-3 / 1e12)
+    pw = ks["k_partner_witness"]   # one squared distance (3 d flops) per partner test
+    assert pw["bound"] == "alu" and pw["achieved"] == pytest.approx(1e8 * 3 * d / 0.5e-3 / 1e12)
+    assert pw["kills"] == 5e5
     mk = ks["k_pair_masks"]
     assert mk["achieved"] == pytest.approx(1120 * 1000 / 1e-3 / 1e9)
     for r in ks.values():
