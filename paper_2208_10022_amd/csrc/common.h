@@ -184,6 +184,7 @@ enum Counter {
     C_LUNE_KEPT,      // exhaustive scan: witness predicates of pairs that stayed edges
     C_PARTNER_TESTS,  // Stage V with the row's other candidates: witness predicates evaluated
     C_PARTNER_KILLS,  // Stage V with the row's other candidates: pairs proven non-edges
+    C_PARTNER_DEEP,   // of those, pairs whose nearest killing partner was in the last quarter of its list
     // 8 work counters for dynamic scheduling (one per XCD), each on its own
     // 128-byte line: atomics on one shared line serialize across the chip.
     C_WORK0 = 32,
@@ -428,16 +429,21 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const double *rel_d2x, const double *rad, const uint16_t *scorer, bool lune_order,
                         bool prekilled, uint8_t *alive,
                         uint64_t *work, uint64_t *counters);
-constexpr int kPartnerWitnesses = 64;   // nearest partners kept per row point
+constexpr int kPartnerWitnesses = 64;   // nearest partners kept per row point and round
+constexpr int kPartnerRounds = 2;       // rounds: the 64 nearest partners, then the next 64
+constexpr double kPartnerDeepShare = 0.01;   // a next round runs while this share of kills came from deep partners
 // Stage V with the row's other candidates as witnesses: each row point's 64
 // nearest partners in a row-sorted pair list (off: row offsets) and, when
-// off2 is given, in the same pairs sorted by their second point; then a
-// proven-kill pass writing alive[p] (0: proven non-edge, 1: left to the scan).
+// off2 is given, in the same pairs sorted by their second point (with a
+// previous round's lists pid / pd2p: the next 64); then a proven-kill pass
+// writing alive[p] (0: proven non-edge, 1: left to the scan; again: pairs
+// an earlier round decided are skipped).
 void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
-                        const int64_t *off2, const int32_t *py2, const double *pd22, int32_t *wid, float *wd2);
+                        const int64_t *off2, const int32_t *py2, const double *pd22, const int32_t *pid,
+                        const float *pd2p, int32_t *wid, float *wd2);
 void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
-                            bool both, uint8_t *alive, uint64_t *counters);
+                            bool both, bool again, uint8_t *alive, uint64_t *counters);
 // Per row of a row-sorted pair list, the largest d^2 of its pairs with
 // alive[p] != 0 (0 when there is none), as float64 bits.
 void launch_live_dmax(hipStream_t s, int64_t nrows, const int64_t *off, const double *pd2, const uint8_t *alive,

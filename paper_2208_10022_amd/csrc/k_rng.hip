@@ -982,27 +982,40 @@ __device__ inline uint64_t wave_merge_u64(uint64_t k) {
 // is the second point).  Key = float32 d^2 rounded up (an upper bound; bit
 // patterns of non-negative floats order as integers), then the partner's
 // index.  One wave per row, 64 entries per step merged into the running best
-// 64.  Unused slots: id -1, d^2 +inf.
+// 64.  Unused slots: id -1, d^2 +inf.  With a previous round's lists (pid,
+// pd2p), only keys after the row's last one there count: the next 64.
 __global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ py, const double *__restrict__ pd2,
                                                      const int64_t *__restrict__ off2,
                                                      const int32_t *__restrict__ py2,
-                                                     const double *__restrict__ pd22, int32_t *__restrict__ wid,
+                                                     const double *__restrict__ pd22,
+                                                     const int32_t *__restrict__ pid,
+                                                     const float *__restrict__ pd2p, int32_t *__restrict__ wid,
                                                      float *__restrict__ wd2) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += nw) {
         uint64_t best = ~0ull;
         bool first = true;
+        uint64_t after = 0;   // keys up to this one were taken by the previous round
+        bool any = true;
+        if (pid) {
+            const int32_t last = pid[r * kPartnerWitnesses + kPartnerWitnesses - 1];
+            any = last >= 0;   // a previous round with fewer than 64 took them all
+            if (any)
+                after = ((uint64_t)__float_as_uint(pd2p[r * kPartnerWitnesses + kPartnerWitnesses - 1]) << 32) |
+                        (uint32_t)last;
+        }
         for (int src = 0; src < (off2 ? 2 : 1); ++src) {
             const int64_t *o = src ? off2 : off;
             const int32_t *ids = src ? py2 : py;
             const double *dd = src ? pd22 : pd2;
-            const int64_t b = o[r], e = o[r + 1];
+            const int64_t b = o[r], e = any ? o[r + 1] : b;
             for (int64_t c0 = b; c0 < e; c0 += 64) {
                 const int64_t i = c0 + lane;
                 uint64_t k = ~0ull;
                 if (i < e) k = ((uint64_t)__float_as_uint(__double2float_ru(dd[i])) << 32) | (uint32_t)ids[i];
+                if (pid && k <= after) k = ~0ull;
                 k = wave_sort_u64(k);
                 if (first) {
                     best = k;
@@ -1070,20 +1083,21 @@ __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32
                                                          const double *__restrict__ pd2, int dp,
                                                          const T *__restrict__ X, const int32_t *__restrict__ wid,
                                                          const float *__restrict__ wd2, bool both,
-                                                         uint8_t *__restrict__ alive,
+                                                         bool again, uint8_t *__restrict__ alive,
                                                          unsigned long long *counters) {
     constexpr bool F32 = sizeof(T) == 4;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const double g32 = (double)(dp + 8) * 0x1p-24;
     const int64_t nchunks = (np + kPartnerChunk - 1) / kPartnerChunk;
-    uint32_t ntests = 0, nkill = 0;
+    uint32_t ntests = 0, nkill = 0, ndeep = 0;
     for (int64_t ch = blockIdx.x * 4 + (threadIdx.x >> 6); ch < nchunks; ch += nw) {
         const int64_t p0 = ch * kPartnerChunk, p1 = p0 + kPartnerChunk < np ? p0 + kPartnerChunk : np;
         int32_t cx = -1, z0 = -1;
         float w0 = INFINITY;
         T zr[KR];
         for (int64_t p = p0; p < p1; ++p) {
+            if (again && alive[p] == 0) continue;   // decided by an earlier round (uniform)
             const int32_t x = __builtin_amdgcn_readfirstlane(px[p]);
             const int32_t y = __builtin_amdgcn_readfirstlane(py[p]);
             const double d2 = pd2[p];
@@ -1125,7 +1139,8 @@ __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32
                 }
                 kill = !out && acc < t;
             }
-            bool dead = __ballot(kill) != 0;
+            uint64_t km = __ballot(kill);   // lanes hold the partners nearest first
+            bool dead = km != 0;
             if (!dead && both) {
                 // y's partners against x
                 const int32_t z1 = wid[(int64_t)y * kPartnerWitnesses + lane];
@@ -1135,11 +1150,13 @@ __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32
                     ++ntests;
                     kill1 = below(X + (int64_t)x * dp, X + (int64_t)z1 * dp, dp, t);
                 }
-                dead = __ballot(kill1) != 0;
+                km = __ballot(kill1);
+                dead = km != 0;
             }
             if (lane == 0) {
                 alive[p] = dead ? 0 : 1;
                 nkill += dead;
+                ndeep += dead && __ffsll((long long)km) - 1 >= kPartnerWitnesses - kPartnerWitnesses / 4;
             }
         }
     }
@@ -1149,6 +1166,7 @@ __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32
         atomicAdd(&counters[C_DIST], (unsigned long long)ntests);
         atomicAdd(&counters[C_PARTNER_TESTS], (unsigned long long)ntests);
         if (nkill) atomicAdd(&counters[C_PARTNER_KILLS], (unsigned long long)nkill);
+        if (ndeep) atomicAdd(&counters[C_PARTNER_DEEP], (unsigned long long)ndeep);
     }
 }
 
@@ -1779,26 +1797,29 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
 }
 
 void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
-                        const int64_t *off2, const int32_t *py2, const double *pd22, int32_t *wid, float *wd2) {
+                        const int64_t *off2, const int32_t *py2, const double *pd22, const int32_t *pid,
+                        const float *pd2p, int32_t *wid, float *wd2) {
     if (nrows == 0) return;
     const int64_t grid = std::min<int64_t>(div_up(nrows, 4), 1 << 16);
-    k_partner_top<<<(unsigned)grid, 256, 0, s>>>(nrows, off, py, pd2, off2, py2, pd22, wid, wd2);
+    k_partner_top<<<(unsigned)grid, 256, 0, s>>>(nrows, off, py, pd2, off2, py2, pd22, pid, pd2p, wid, wd2);
     GRNG_LAUNCHED();
 }
 
 void launch_partner_witness(hipStream_t s, int64_t np, const int32_t *px, const int32_t *py, const double *pd2,
                             int dp, const float *Xf, const double *Xd, const int32_t *wid, const float *wd2,
-                            bool both, uint8_t *alive, uint64_t *counters) {
+                            bool both, bool again, uint8_t *alive, uint64_t *counters) {
     if (np == 0) return;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(div_up(div_up(np, kPartnerChunk), 4), 4096));
     unsigned long long *ctr = (unsigned long long *)counters;
     if (Xf && dp <= 16)
-        k_partner_witness<float, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, alive, ctr);
+        k_partner_witness<float, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, again,
+                                                                   alive, ctr);
     else if (Xf)
-        k_partner_witness<float, 32><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, alive, ctr);
+        k_partner_witness<float, 32><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xf, wid, wd2, both, again,
+                                                                   alive, ctr);
     else
-        k_partner_witness<double, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xd, wid, wd2, both, alive,
-                                                                    ctr);
+        k_partner_witness<double, 16><<<(unsigned)grid, 256, 0, s>>>(np, px, py, pd2, dp, Xd, wid, wd2, both, again,
+                                                                    alive, ctr);
     GRNG_LAUNCHED();
 }
 
