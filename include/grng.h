@@ -189,7 +189,9 @@ typedef struct grng_stats {
                                      tests every witness its cells hold; no visit order saves them) */
     double partner_tests;         /* Stage V with the row's other candidates (Algorithm 1, Stage 5): witness
                                      predicates evaluated, each pair of exhaustive_pairs against the 64
-                                     partners nearest to each of its ends in that list */
+                                     partners nearest to each of its ends in that list (and the pairs left
+                                     against the next 64 when at least 1% of the kills needed the last
+                                     quarter of the lists) */
     double partner_kills;         /* of exhaustive_pairs, those this pass proved non-edges (the exhaustive
                                      scan skips them) */
     double ms_partner;            /* device time of that pass in the last build */
