@@ -429,15 +429,15 @@ void launch_lune_guided(hipStream_t s, int64_t npairs, const int32_t *px, const 
                         const double *rel_d2x, const double *rad, const uint16_t *scorer, bool lune_order,
                         bool prekilled, uint8_t *alive,
                         uint64_t *work, uint64_t *counters);
-constexpr int kPartnerWitnesses = 64;   // nearest partners kept per row point and round
-constexpr int kPartnerRounds = 2;       // rounds: the 64 nearest partners, then the next 64
-constexpr double kPartnerDeepShare = 0.01;   // a next round runs while this share of kills came from deep partners
+constexpr int kPartnerWitnesses = 64;   // partners per row point in one list
+constexpr int kPartnerLists = 2;        // lists: the 64 nearest partners, then the next 64
+constexpr double kPartnerDeepShare = 0.01;   // the next list is used while this share of kills came from deep partners
 // Stage V with the row's other candidates as witnesses: each row point's 64
 // nearest partners in a row-sorted pair list (off: row offsets) and, when
 // off2 is given, in the same pairs sorted by their second point (with a
-// previous round's lists pid / pd2p: the next 64); then a proven-kill pass
-// writing alive[p] (0: proven non-edge, 1: left to the scan; again: pairs
-// an earlier round decided are skipped).
+// nearer lists pid / pd2p: the next 64); then a proven-kill pass writing
+// alive[p] (0: proven non-edge, 1: left to the scan; again: pairs decided
+// with a nearer list are skipped).
 void launch_partner_top(hipStream_t s, int64_t nrows, const int64_t *off, const int32_t *py, const double *pd2,
                         const int64_t *off2, const int32_t *py2, const double *pd22, const int32_t *pid,
                         const float *pd2p, int32_t *wid, float *wd2);

@@ -950,18 +950,18 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                                    ccnt.as<int32_t>(), coff.as<int64_t>(), cx.as<int32_t>(), cy.as<int32_t>(),
                                    cd2.as<double>());
         }
-        // Round 0: the 64 nearest partners.  The next 64 only while the last
+        // List 0: the 64 nearest partners.  The next 64 only while the last
         // quarter of a list still kills a share of the pairs (their killers
-        // then lie deeper in the lists: high dimension, large cells).
+        // then lie deeper: high dimension, large cells).
         uint64_t k0 = 0, d0 = 0;
-        for (int round = 0; round < kPartnerRounds; ++round) {
-            if (round > 0) {
+        for (int depth = 0; depth < kPartnerLists; ++depth) {
+            if (depth > 0) {
                 uint64_t c[C_NUM];
                 read_counters(idx, c);
                 const uint64_t kills = c[C_PARTNER_KILLS] - k0, deep = c[C_PARTNER_DEEP] - d0;
                 if (trace_on())
-                    std::fprintf(stderr, "[grng] partner round %d: %llu kills, %llu by the last quarter of the lists\n",
-                                 round - 1, (unsigned long long)kills, (unsigned long long)deep);
+                    std::fprintf(stderr, "[grng] partner list %d: %llu kills, %llu by its last quarter\n", depth - 1,
+                                 (unsigned long long)kills, (unsigned long long)deep);
                 if ((double)deep < kPartnerDeepShare * (double)kills) break;
                 k0 = c[C_PARTNER_KILLS];
                 d0 = c[C_PARTNER_DEEP];
@@ -971,17 +971,17 @@ void run_exhaustive(grng_index *idx, const Layer &L, const LayerAux &aux, const 
                 k0 = c[C_PARTNER_KILLS];
                 d0 = c[C_PARTNER_DEEP];
             }
-            DevBuf &wi = wid[round & 1], &wd = wd2[round & 1];
-            const DevBuf &pi = wid[(round & 1) ^ 1], &pd = wd2[(round & 1) ^ 1];
+            DevBuf &wi = wid[depth & 1], &wd = wd2[depth & 1];
+            const DevBuf &pi = wid[(depth & 1) ^ 1], &pd = wd2[(depth & 1) ^ 1];
             wi.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
             wd.alloc(4 * (size_t)kPartnerWitnesses * (size_t)n);
             launch_partner_top(s, n, roff.as<int64_t>(), P.y.as<int32_t>(), P.d2.as<double>(),
                                self ? coff.as<int64_t>() : nullptr, self ? cy.as<int32_t>() : nullptr,
-                               self ? cd2.as<double>() : nullptr, round ? pi.as<int32_t>() : nullptr,
-                               round ? pd.as<float>() : nullptr, wi.as<int32_t>(), wd.as<float>());
+                               self ? cd2.as<double>() : nullptr, depth ? pi.as<int32_t>() : nullptr,
+                               depth ? pd.as<float>() : nullptr, wi.as<int32_t>(), wd.as<float>());
             launch_partner_witness(s, np, P.x.as<int32_t>(), P.y.as<int32_t>(), P.d2.as<double>(), idx->dp,
                                    f32 ? S.Xf.as<float>() : nullptr, S.Xh.as<double>(), wi.as<int32_t>(),
-                                   wd.as<float>(), self, round > 0, alive.as<uint8_t>(), ctr);
+                                   wd.as<float>(), self, depth > 0, alive.as<uint8_t>(), ctr);
         }
         const double ms = pt.stop();
         bt.partner += ms;

@@ -982,8 +982,8 @@ __device__ inline uint64_t wave_merge_u64(uint64_t k) {
 // is the second point).  Key = float32 d^2 rounded up (an upper bound; bit
 // patterns of non-negative floats order as integers), then the partner's
 // index.  One wave per row, 64 entries per step merged into the running best
-// 64.  Unused slots: id -1, d^2 +inf.  With a previous round's lists (pid,
-// pd2p), only keys after the row's last one there count: the next 64.
+// 64.  Unused slots: id -1, d^2 +inf.  With the nearer lists before them
+// (pid, pd2p), only keys after the row's last one there count: the next 64.
 __global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ py, const double *__restrict__ pd2,
                                                      const int64_t *__restrict__ off2,
@@ -997,11 +997,11 @@ __global__ __launch_bounds__(256) void k_partner_top(int64_t nrows, const int64_
     for (int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += nw) {
         uint64_t best = ~0ull;
         bool first = true;
-        uint64_t after = 0;   // keys up to this one were taken by the previous round
+        uint64_t after = 0;   // keys up to this one are in the nearer list
         bool any = true;
         if (pid) {
             const int32_t last = pid[r * kPartnerWitnesses + kPartnerWitnesses - 1];
-            any = last >= 0;   // a previous round with fewer than 64 took them all
+            any = last >= 0;   // a nearer list with fewer than 64 holds them all
             if (any)
                 after = ((uint64_t)__float_as_uint(pd2p[r * kPartnerWitnesses + kPartnerWitnesses - 1]) << 32) |
                         (uint32_t)last;
@@ -1097,7 +1097,7 @@ __global__ __launch_bounds__(256) void k_partner_witness(int64_t np, const int32
         float w0 = INFINITY;
         T zr[KR];
         for (int64_t p = p0; p < p1; ++p) {
-            if (again && alive[p] == 0) continue;   // decided by an earlier round (uniform)
+            if (again && alive[p] == 0) continue;   // decided with a nearer list (uniform)
             const int32_t x = __builtin_amdgcn_readfirstlane(px[p]);
             const int32_t y = __builtin_amdgcn_readfirstlane(py[p]);
             const double d2 = pd2[p];
